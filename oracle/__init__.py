@@ -1,0 +1,15 @@
+"""Test-only FP64 CPU oracle for the orthogonal discrete spherical Bessel transform.
+
+This package is test infrastructure.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it.  The product library
+(``paper_1509_07115_amd``) never imports, links or executes anything here, and
+this package imports nothing from the product.
+
+Modules
+-------
+dsbt     dense FP64 transform built straight from the definitions (Sec. 2.2-2.5)
+exact    exact-rational (``fractions``) DLOP / DDLOP / T for tiny grids (Sec. 2.3-2.5, App. A)
+tdse     dense split-operator step, propagation and adjoint gradient (Sec. 4.1)
+sbf      spherical-Bessel references: closed forms, quadrature, corrected momenta (Sec. 3)
+"""
+from . import dsbt, exact, tdse, sbf  # noqa: F401

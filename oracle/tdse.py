@@ -1,0 +1,96 @@
+"""Dense FP64 split-operator step of the DSBT-DVR solver, and its adjoint.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+One step for a radial channel of angular momentum l with zero vector
+potential (Sec. 4.1, the split-operator sequence with A = 0, where the two
+half kinetic factors are adjacent and merge):
+
+    psi <- exp(-i s V tau/2) F^T T^T exp(-i E tau) T F exp(-i s V tau/2) psi
+
+with the diagonal kinetic energy E_n = k_nl^2 / 2 (eq. KinMat).  k_nl is
+n dk (plain mode, eq. tilde_k_grid) or the root of eq. kcorr (corrected mode)
+for the regular rows n >= n_0l; the completion rows (n < n_0l, which include
+n = 0 of odd l) take (N dk)^2/2 (reading R7: they are the highest-momentum
+components, Sec. 2.5 and the remark after eq. tilde_k_grid).
+
+The adjoint follows the PyTorch convention: the gradient with respect to a
+complex tensor is 2 dL/d(conj psi), so for L = |<phi|psi_T>|^2 it starts at
+2 z phi with z = <phi|psi_T>, runs backwards through U_t^H = U_t^{-1}
+(all factors are unitary), and dL/ds_t = (tau/2) sum_i V_i
+Im(conj(lam_{t+1}) psi_{t+1} + conj(lam_t) psi_t).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dsbt
+from .sbf import corrected_momenta
+
+__all__ = ["kinetic_energies", "hamiltonian", "step", "propagate", "loss_and_grad"]
+
+
+def kinetic_energies(N: int, rmax: float, ell: int, corrected: bool = False) -> np.ndarray:
+    """E in slot order j = n - p_l."""
+    p = dsbt.parity_p(ell)
+    nz = dsbt.n0(ell)
+    dk = dsbt.delta_k(rmax)
+    E = np.empty(N)
+    E[: nz - p] = 0.5 * (N * dk) ** 2
+    if corrected:
+        k = corrected_momenta(N, rmax, ell)
+    else:
+        k = np.arange(nz, N + p) * dk
+    E[nz - p:] = 0.5 * k ** 2
+    return E
+
+
+def hamiltonian(N: int, rmax: float, ell: int, V: np.ndarray, corrected: bool = False) -> np.ndarray:
+    """Dense H = B^T diag(E) B + diag(V) (eq. H_DVR with A = 0, one channel)."""
+    B = dsbt.dsbt_matrix(N, ell)
+    E = kinetic_energies(N, rmax, ell, corrected)
+    return B.T @ (E[:, None] * B) + np.diag(V)
+
+
+def step(psi: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray, dt: float,
+         s: float = 1.0, adjoint: bool = False) -> np.ndarray:
+    """One split-operator step U (or U^H when ``adjoint``) on psi of shape (N,) or (N, C)."""
+    sg = 1.0 if adjoint else -1.0
+    pv = np.exp(sg * 1j * s * V * dt / 2.0)
+    pk = np.exp(sg * 1j * E * dt)
+    if psi.ndim == 2:
+        pv = pv[:, None]
+        pk = pk[:, None]
+    x = pv * psi
+    b = dsbt.forward(x, ell)
+    x = dsbt.inverse(pk * b, ell)
+    return pv * x
+
+
+def propagate(psi0: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray, dt: float,
+              s: np.ndarray, keep: bool = False):
+    """Apply steps t = 0..len(s)-1 with potential strengths s[t]."""
+    x = np.array(psi0, dtype=np.complex128)
+    states = [x] if keep else None
+    for st in s:
+        x = step(x, ell, V, E, dt, st)
+        if keep:
+            states.append(x)
+    return states if keep else x
+
+
+def loss_and_grad(psi0: np.ndarray, phi: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray,
+                  dt: float, s: np.ndarray):
+    """L = |<phi|psi_T>|^2 and its gradients (PyTorch convention) wrt psi0 and s."""
+    states = propagate(psi0, ell, V, E, dt, s, keep=True)
+    z = np.vdot(phi, states[-1])
+    L = float(abs(z) ** 2)
+    lam = 2.0 * z * np.asarray(phi, dtype=np.complex128)
+    gs = np.zeros(len(s))
+    Vb = V[:, None] if psi0.ndim == 2 else V
+    for t in range(len(s) - 1, -1, -1):
+        lam_next = lam
+        lam = step(lam_next, ell, V, E, dt, s[t], adjoint=True)
+        acc = np.conj(lam_next) * states[t + 1] + np.conj(lam) * states[t]
+        gs[t] = 0.5 * dt * float(np.sum(Vb * acc.imag))
+    return L, lam, gs

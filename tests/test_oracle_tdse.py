@@ -1,0 +1,128 @@
+"""Pins of the oracle's kinetic diagonal, split-operator step and adjoint (CPU only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dsbt, tdse
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_hydrogen.json")
+
+
+@pytest.mark.parametrize("col", [0, 1, 2])
+def test_table1_hydrogen_l_positive(col):
+    # Sec. 4.3, Table 1: H-atom energies for l > 0 with rmax = 102.4.  The dense
+    # H = B^T diag(k_nl^2/2) B + diag(-1/r) with the corrected momenta of
+    # eq. kcorr (reading R7 for the completion rows) reproduces every printed
+    # digit.  This pins F, T and the kinetic diagonal together.
+    g = json.load(open(GOLDEN))
+    rmax = g["rmax"]
+    dr = g["dr_columns"][col]
+    N = int(round(rmax / dr))
+    r = dsbt.grid_r(N, rmax)
+    for ell in (1, 2):
+        ev = np.linalg.eigvalsh(tdse.hamiltonian(N, rmax, ell, -1.0 / r, corrected=True))
+        for row in g["rows"]:
+            if row["l"] == ell:
+                assert round(ev[row["index"]], 6) == pytest.approx(row["E"][col], abs=1e-12), (ell, row)
+
+
+def test_completion_rows_need_top_energy():
+    # reading R7: giving the completion row of l = 2 its literal k~_1 = dk puts a
+    # spurious deeply bound state below the 3d level.
+    rmax, dr, ell = 102.4, 0.2, 2
+    N = int(round(rmax / dr))
+    r = dsbt.grid_r(N, rmax)
+    B = dsbt.dsbt_matrix(N, ell)
+    E = tdse.kinetic_energies(N, rmax, ell, corrected=True)
+    E_lit = E.copy()
+    E_lit[0] = 0.5 * dsbt.delta_k(rmax) ** 2
+    ev = np.linalg.eigvalsh(B.T @ (E_lit[:, None] * B) + np.diag(-1.0 / r))
+    assert ev[0] < -1.0
+    ev_ok = np.linalg.eigvalsh(B.T @ (E[:, None] * B) + np.diag(-1.0 / r))
+    assert ev_ok[0] > -0.06
+
+
+def _setup(N=64, rmax=12.8, ell=3, seed=0):
+    r = dsbt.grid_r(N, rmax)
+    V = -1.0 / np.sqrt(r * r + 0.01) + ell * (ell + 1) / (2 * r * r)
+    E = tdse.kinetic_energies(N, rmax, ell)
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return V, E, psi / np.linalg.norm(psi)
+
+
+def test_step_is_unitary():
+    # Sec. 4.1: every factor of the step is unitary, so the norm is conserved
+    V, E, psi = _setup()
+    x = psi
+    for _ in range(50):
+        x = tdse.step(x, 3, V, E, 0.01)
+    assert abs(np.linalg.norm(x) - 1.0) < 1e-13
+    back = tdse.step(tdse.step(psi, 3, V, E, 0.01), 3, V, E, 0.01, adjoint=True)
+    assert np.max(np.abs(back - psi)) < 1e-13
+
+
+def test_free_steps_compose():
+    # V = 0: the step is exp(-i H0 tau) with H0 = B^T diag(E) B, so n steps of
+    # tau equal one step of n tau.
+    V, E, psi = _setup()
+    Z = np.zeros_like(V)
+    x = psi
+    for _ in range(7):
+        x = tdse.step(x, 3, Z, E, 0.03)
+    y = tdse.step(psi, 3, Z, E, 0.21)
+    assert np.max(np.abs(x - y)) < 1e-12
+
+
+def test_split_step_second_order():
+    # Sec. 4.1: global error O(tau^2): halving tau cuts the error ~x4 against
+    # the exact exp(-i H T) of the dense Hamiltonian.
+    N, rmax, ell = 64, 12.8, 1
+    r = dsbt.grid_r(N, rmax)
+    V = 0.5 * r * r
+    E = tdse.kinetic_energies(N, rmax, ell)
+    B = dsbt.dsbt_matrix(N, ell)
+    H = B.T @ (E[:, None] * B) + np.diag(V)
+    w, U = np.linalg.eigh(H)
+    psi = r ** 2 * np.exp(-0.5 * (r - 2.0) ** 2)
+    psi = psi / np.linalg.norm(psi)
+    T = 1.0
+    exact = U @ (np.exp(-1j * w * T) * (U.T @ psi))
+    errs = []
+    for nst in (40, 80):
+        x = psi.astype(complex)
+        for _ in range(nst):
+            x = tdse.step(x, ell, V, E, T / nst)
+        errs.append(np.linalg.norm(x - exact))
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_adjoint_matches_finite_differences():
+    V, E, psi0 = _setup(N=32, rmax=8.0, ell=2, seed=3)
+    rng = np.random.default_rng(11)
+    phi = rng.standard_normal(32) + 1j * rng.standard_normal(32)
+    phi /= np.linalg.norm(phi)
+    s = rng.uniform(0.9, 1.1, size=6)
+    dt = 0.05
+    L, gpsi, gs = tdse.loss_and_grad(psi0, phi, 2, V, E, dt, s)
+
+    def loss(p, ss):
+        x = tdse.propagate(p, 2, V, E, dt, ss)
+        return abs(np.vdot(phi, x)) ** 2
+
+    h = 1e-6
+    for t in range(len(s)):
+        sp, sm = s.copy(), s.copy()
+        sp[t] += h
+        sm[t] -= h
+        fd = (loss(psi0, sp) - loss(psi0, sm)) / (2 * h)
+        assert abs(fd - gs[t]) < 1e-7 * max(1.0, abs(fd))
+    for _ in range(3):
+        d = rng.standard_normal(32) + 1j * rng.standard_normal(32)
+        fd = (loss(psi0 + h * d, s) - loss(psi0 - h * d, s)) / (2 * h)
+        # PyTorch convention: dL = Re(<grad, d psi>)
+        assert abs(fd - np.real(np.vdot(gpsi, d))) < 1e-7 * max(1.0, abs(fd))
+    assert 0.0 <= L <= 1.0
