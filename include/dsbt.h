@@ -1,0 +1,170 @@
+/*
+ * dsbt.h -- C ABI of the MI355X orthogonal discrete spherical Bessel transform.
+ *
+ * The operation (Serov, "Orthogonal fast spherical Bessel transform on uniform
+ * grid"): for a radial channel of angular momentum l sampled on
+ * r_i = (i - 1/2) dr, i = 1..N (Sec. 2.2, eq. r_grid), with psi_i = psi(r_i) sqrt(dr),
+ *
+ *     forward   b   = T F psi        (Sec. 2.2 eq. f_vs_psi; Sec. 2.4 eq. b_vs_f)
+ *     inverse   psi = F^T T^T b      (eq. f_vs_b with T^{-1} = T^T, F^{-1} = F^T)
+ *
+ * F is the orthonormal sine (even l) or cosine (odd l) transform of
+ * eq. csFourierBasis, T the Fourier-to-Bessel matrix built from derivatives of
+ * discrete Legendre orthogonal polynomials (Sec. 2.4 eq. Tdef/Ldef) completed by
+ * ceil(l/2) DLOP rows (Sec. 2.5 eq. Tadd).  Both are real and orthogonal; complex
+ * data is transformed linearly.  Conventions (orthonormal F, the sign
+ * (-1)^ceil(l/2) in F, numerically normalised rows) follow the readings listed
+ * with the library's design notes.
+ *
+ * The split-operator step of Sec. 4.1 with zero vector potential,
+ *
+ *     psi <- exp(-i s V tau/2) F^T T^T exp(-i K tau) T F exp(-i s V tau/2) psi,
+ *
+ * uses the diagonal kinetic energy K_n = k_nl^2 / 2 of eq. KinMat.
+ *
+ * Data layout.  Every data buffer is a device pointer to packed interleaved
+ * complex values (re, im) -- complex64 (float2) for DSBT_C64 plans, complex128
+ * (double2) for DSBT_C128 plans -- the same memory layout as torch.complex64 /
+ * torch.complex128.  Channel c occupies elements [offset_c, offset_c + N_c).
+ * Coefficient vectors b are stored in slot order j = n - p_l, n = p_l..N_l,
+ * where p_l = 1 for even l and 0 for odd l (eq. k_grid).
+ *
+ * Ownership.  The caller owns every data buffer; the library never frees or
+ * retains them past the call.  A plan owns its device tables and is released
+ * by dsbt_plan_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * Transform and step calls only enqueue work on that stream and return; they
+ * do not synchronise.  dsbt_plan_create and dsbt_set_potential synchronise.
+ *
+ * Errors.  Every call returns a dsbt_status; 0 is success.  No exception
+ * crosses the ABI.  dsbt_last_error() gives a thread-local message for the
+ * most recent failure.  A HIP error from an earlier asynchronous launch may be
+ * reported by a later call as DSBT_ERR_HIP.
+ *
+ * Thread safety.  A plan is read-only after creation except for
+ * dsbt_set_potential and the graph cache used by dsbt_kinetic_step; calls on
+ * one plan from several host threads must not overlap those two.
+ */
+#ifndef DSBT_H
+#define DSBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dsbt_status;
+enum {
+    DSBT_OK = 0,
+    DSBT_ERR_INVALID_ARG = -1,   /* a NULL pointer, a bad size, overlapping channels */
+    DSBT_ERR_UNSUPPORTED = -2,   /* N not a power of two in [16, 8192], l too large */
+    DSBT_ERR_OOM = -3,           /* device or host allocation failed */
+    DSBT_ERR_HIP = -4,           /* a HIP runtime call or kernel launch failed */
+    DSBT_ERR_PLAN_MISMATCH = -5, /* call does not fit the plan (e.g. no potential set) */
+    DSBT_ERR_NO_DEVICE = -7      /* no HIP device is visible */
+};
+
+typedef struct dsbt_plan_s* dsbt_plan;   /* opaque; owned by the library */
+
+/* One radial channel.  N: grid size (power of two, 16..8192); ell: angular
+ * momentum, 0 <= ell <= min(2N - 2, 255); rmax > 0: box radius (dr = rmax/N,
+ * dk = pi/rmax); offset: first element of the channel in every data buffer,
+ * counted in complex elements.  Channels must not overlap. */
+typedef struct {
+    int32_t N;
+    int32_t ell;
+    double rmax;
+    int64_t offset;
+} dsbt_channel;
+
+enum { DSBT_C64 = 0, DSBT_C128 = 1 };               /* data precision */
+enum { DSBT_K_PLAIN = 0, DSBT_K_CORRECTED = 1 };     /* k_nl = n dk, or eq. kcorr roots */
+enum { DSBT_SIGN_C = 0, DSBT_SIGN_PRINTED_F = 1 };   /* F with / without (-1)^ceil(l/2) */
+enum { DSBT_MODE_BATCHED = 0, DSBT_MODE_PLAIN = 1 }; /* batched launches / one launch per channel and stage */
+enum { DSBT_PLAN_ON_DEVICE = 0, DSBT_PLAN_ON_HOST = 1 };
+
+typedef struct {
+    int32_t precision;    /* DSBT_C64 (default) or DSBT_C128 */
+    int32_t kinetic;      /* DSBT_K_PLAIN (default) or DSBT_K_CORRECTED */
+    int32_t sign;         /* DSBT_SIGN_C (default): b_n ~ c_l(k_n) sqrt(w_n) */
+    int32_t mode;         /* DSBT_MODE_BATCHED (default) or DSBT_MODE_PLAIN */
+    int32_t plan_where;   /* where the FP64 plan tables are generated */
+    int32_t tile;         /* moment tile B (power of two >= ceil((l+1)/2)); 0 = automatic */
+    int32_t chans_per_block; /* channels per workgroup in the transform stage; 0 = automatic */
+    int32_t reserved[9];
+} dsbt_plan_opts;
+
+/* Fill *o with the defaults above (all zero). */
+void dsbt_plan_opts_default(dsbt_plan_opts* o);
+
+/* Build a plan for nch channels described by ch[0..nch).  The FP64 plan (DLOP
+ * rows of T, the tiled moment tables, FFT twiddles) is generated once, cast to
+ * the data precision and uploaded; `stream` orders the upload.  o may be NULL
+ * (defaults).  On success *out receives the plan; on failure *out is NULL. */
+dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch,
+                             const dsbt_plan_opts* o, void* stream);
+
+/* Convenience: channels for every l in ells[0..nell) with a common N and rmax,
+ * packed back to back in the order given; with all_m != 0 each l gets 2l+1
+ * consecutive channels (m = -l..l). */
+dsbt_status dsbt_plan_create_uniform(dsbt_plan* out, int32_t N, double rmax,
+                                     const int32_t* ells, int32_t nell, int32_t all_m,
+                                     const dsbt_plan_opts* o, void* stream);
+
+dsbt_status dsbt_plan_destroy(dsbt_plan p);
+
+/* Plan facts: number of channels, total complex elements a data buffer must
+ * hold (max offset + N), data precision, and device bytes held by the plan. */
+dsbt_status dsbt_plan_info(dsbt_plan p, int32_t* nch, int64_t* elems, int32_t* precision,
+                           int64_t* table_bytes);
+
+/* Forward transform b = T F psi for every channel (device pointers, layout as
+ * above).  psi and b may be the same buffer.  Enqueued on `stream`. */
+dsbt_status dsbt_forward(dsbt_plan p, const void* psi, void* b, void* stream);
+
+/* Inverse transform psi = F^T T^T b for every channel.  b and psi may alias. */
+dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream);
+
+/* Radial potential for the split step (Sec. 4.1).  V is a HOST array of FP64
+ * values laid out like a data buffer (V[offset_c + i] = V_c(r_{i+1}), real);
+ * dt is the time step tau.  The phase factors exp(-i s V tau/2) and
+ * exp(-i K_n tau) are formed from FP64 angles reduced mod 2 pi.  Synchronises. */
+dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt);
+
+enum {
+    DSBT_STEP_ADJOINT = 1,   /* apply U^H (conjugated phases), steps in reverse order */
+    DSBT_STEP_GRAPH = 2,     /* capture the nsteps launches once in a hipGraph and replay it */
+    DSBT_STEP_RESIDENT = 4   /* one launch that keeps each channel in LDS for all steps */
+};
+
+/* nsteps split-operator steps in place on psi (device).  s: device FP32 array
+ * of nsteps potential strengths (step t uses s[t]; NULL means all ones); with
+ * DSBT_STEP_ADJOINT the steps run t = nsteps-1 .. 0.  Needs dsbt_set_potential. */
+dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const float* s,
+                              int32_t flags, void* stream);
+
+/* Gradient of a real loss L with respect to the strength s_t of one step,
+ * given psi_t, psi_{t+1} = U_t psi_t and the adjoint states lam_t = U_t^H lam_{t+1},
+ * lam_{t+1} (PyTorch convention: lam = 2 dL/d conj(psi)):
+ *   out[0] = (tau/2) sum_i V_i Im(conj(lam_{t+1,i}) psi_{t+1,i} + conj(lam_{t,i}) psi_{t,i}).
+ * out is a device FP64 scalar; written, not accumulated. */
+dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
+                             const void* lam_t, const void* lam_t1, double* out, void* stream);
+
+/* Host FP64 moment tables of one (N, l, B) for testing the plan without a GPU.
+ * Writes R*R*NT doubles, R = B + ceil(l/2), NT = N/B: block J (row-major,
+ * M[r][q]) maps [g_J ; mu_J] to [b_J ; mu_{J+1}] for the tile of slots
+ * [J B, J B + B).  If out is NULL or out_len is too small only *needed is set. */
+dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
+                                 int64_t out_len, int64_t* needed);
+
+const char* dsbt_status_string(dsbt_status s);
+const char* dsbt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSBT_H */

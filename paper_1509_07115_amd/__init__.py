@@ -1,0 +1,180 @@
+"""MI355X orthogonal discrete spherical Bessel transform (Serov, arXiv 1509.07115).
+
+A thin Python binding over the C ABI of ``libdsbt.so`` (include/dsbt.h):
+PyTorch supplies device memory and streams; every step of the transform runs
+in the library's HIP kernels.  There is no CPU fallback: if the library is not
+built, or no GPU is present, the calls raise.
+
+    from paper_1509_07115_amd import Plan
+    plan = Plan.uniform(N=2048, rmax=100.0, ells=range(64), all_m=True)
+    b = plan.forward(psi)          # psi: torch.complex64 on cuda, plan.elems elements
+    psi2 = plan.inverse(b)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["Plan", "DsbtError", "exported_symbols"]
+
+DsbtError = _lib.DsbtError
+
+
+def exported_symbols() -> list:
+    return list(_lib.EXPORTED)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Plan:
+    """A DSBT plan over a set of radial channels (``dsbt_plan_create``).
+
+    channels: sequence of (N, ell, rmax, offset) tuples (offset in complex elements).
+    precision: "c64" (complex64 data, FP32 arithmetic) or "c128".
+    mode: "batched" (default) or "plain" (one launch per channel and stage).
+    """
+
+    def __init__(self, channels: Sequence, precision: str = "c64", mode: str = "batched", tile: int = 0,
+                 chans_per_block: int = 0, sign: bool = True, stream=None, _create=True):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        self.precision = precision
+        self.channels = [tuple(c) for c in channels]
+        if not _create:
+            return
+        arr = (_lib.Channel * len(self.channels))()
+        for i, (N, ell, rmax, off) in enumerate(self.channels):
+            arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
+        opts = self._opts(precision, mode, tile, chans_per_block, sign)
+        _lib.check(self._lib.dsbt_plan_create(ctypes.byref(self._h), arr, len(self.channels), ctypes.byref(opts),
+                                              _stream_handle(stream)), "dsbt_plan_create")
+        self._info()
+
+    @staticmethod
+    def _opts(precision, mode, tile, chans_per_block, sign):
+        o = _lib.PlanOpts()
+        o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128}[precision]
+        o.mode = {"batched": _lib.DSBT_MODE_BATCHED, "plain": _lib.DSBT_MODE_PLAIN}[mode]
+        o.tile = int(tile)
+        o.chans_per_block = int(chans_per_block)
+        o.sign = _lib.DSBT_SIGN_C if sign else _lib.DSBT_SIGN_PRINTED_F
+        return o
+
+    @classmethod
+    def uniform(cls, N: int, rmax: float, ells: Iterable[int], all_m: bool = False, **kw) -> "Plan":
+        ells = [int(e) for e in ells]
+        ch, off = [], 0
+        for e in ells:
+            for _ in range(2 * e + 1 if all_m else 1):
+                ch.append((N, e, rmax, off))
+                off += N
+        return cls(ch, **kw)
+
+    def _info(self):
+        nch, elems, prec, tb = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _lib.check(self._lib.dsbt_plan_info(self._h, ctypes.byref(nch), ctypes.byref(elems), ctypes.byref(prec),
+                                            ctypes.byref(tb)), "dsbt_plan_info")
+        self.nch, self.elems, self.table_bytes = nch.value, elems.value, tb.value
+
+    # -- buffers ---------------------------------------------------------
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex64 if self.precision == "c64" else torch.complex128
+
+    def _check_buf(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if not t.is_contiguous() or t.numel() < self.elems:
+            raise ValueError(f"{name} must be contiguous with at least {self.elems} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self):
+        import torch
+        return torch.empty(self.elems, dtype=self.dtype, device="cuda")
+
+    # -- transforms ------------------------------------------------------
+    def forward(self, psi, out=None, stream=None):
+        """b = T F psi for every channel (``dsbt_forward``)."""
+        out = self.empty() if out is None else out
+        _lib.check(self._lib.dsbt_forward(self._h, self._check_buf(psi, "psi"), self._check_buf(out, "out"),
+                                          _stream_handle(stream)), "dsbt_forward")
+        return out
+
+    def inverse(self, b, out=None, stream=None):
+        """psi = F^T T^T b for every channel (``dsbt_inverse``)."""
+        out = self.empty() if out is None else out
+        _lib.check(self._lib.dsbt_inverse(self._h, self._check_buf(b, "b"), self._check_buf(out, "out"),
+                                          _stream_handle(stream)), "dsbt_inverse")
+        return out
+
+    def set_potential(self, V: np.ndarray, dt: float):
+        """Radial potential in data layout (FP64 host array) and time step (``dsbt_set_potential``)."""
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        if V.size < self.elems:
+            raise ValueError("potential shorter than the data layout")
+        _lib.check(self._lib.dsbt_set_potential(self._h, V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                float(dt)), "dsbt_set_potential")
+
+    def kinetic_step(self, psi, nsteps: int = 1, s=None, adjoint: bool = False, graph: bool = False,
+                     resident: bool = False, stream=None):
+        """nsteps split-operator steps in place (``dsbt_kinetic_step``); s: cuda float32 strengths."""
+        import torch
+        sp = None
+        if s is not None:
+            if not (isinstance(s, torch.Tensor) and s.is_cuda and s.dtype == torch.float32 and s.is_contiguous()
+                    and s.numel() >= nsteps):
+                raise TypeError("s must be a contiguous cuda float32 tensor with nsteps entries")
+            sp = ctypes.c_void_p(s.data_ptr())
+        flags = ((_lib.DSBT_STEP_ADJOINT if adjoint else 0) | (_lib.DSBT_STEP_GRAPH if graph else 0)
+                 | (_lib.DSBT_STEP_RESIDENT if resident else 0))
+        _lib.check(self._lib.dsbt_kinetic_step(self._h, self._check_buf(psi, "psi"), int(nsteps), sp, flags,
+                                               _stream_handle(stream)), "dsbt_kinetic_step")
+        return psi
+
+    def step_grad_s(self, psi_t, psi_t1, lam_t, lam_t1, out, stream=None):
+        """out[0] = (tau/2) sum V Im(conj(lam_t1) psi_t1 + conj(lam_t) psi_t) (``dsbt_step_grad_s``)."""
+        import torch
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 1):
+            raise TypeError("out must be a cuda float64 tensor")
+        _lib.check(self._lib.dsbt_step_grad_s(self._h, self._check_buf(psi_t, "psi_t"),
+                                              self._check_buf(psi_t1, "psi_t1"), self._check_buf(lam_t, "lam_t"),
+                                              self._check_buf(lam_t1, "lam_t1"), ctypes.c_void_p(out.data_ptr()),
+                                              _stream_handle(stream)), "dsbt_step_grad_s")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dsbt_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def host_ftb_tables(N: int, ell: int, B: int) -> np.ndarray:
+    """FP64 moment-tile blocks of the plan (``dsbt_host_ftb_tables``), shape (N/B, R, R)."""
+    lib = _lib.load()
+    need = ctypes.c_int64()
+    _lib.check(lib.dsbt_host_ftb_tables(N, ell, B, None, 0, ctypes.byref(need)), "dsbt_host_ftb_tables")
+    out = np.empty(need.value, dtype=np.float64)
+    _lib.check(lib.dsbt_host_ftb_tables(N, ell, B, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        need.value, ctypes.byref(need)), "dsbt_host_ftb_tables")
+    k = (ell + 1) // 2
+    R = B + k
+    return out.reshape(N // B, R, R)

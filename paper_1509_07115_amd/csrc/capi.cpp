@@ -1,0 +1,646 @@
+// C ABI of the MI355X DSBT library: plan management, table upload and the
+// launch sequences of forward / inverse / split step (declared in include/dsbt.h).
+#include "../../include/dsbt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+#include "plan_host.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dsbt_status fail(dsbt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+struct HipError : std::runtime_error {
+    hipError_t code;
+    HipError(hipError_t c, const char* what) : std::runtime_error(what), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* where) {
+    if (e != hipSuccess) {
+        std::string m = std::string(where) + ": " + hipGetErrorString(e);
+        throw HipError(e, m.c_str());
+    }
+}
+
+struct StatusError : std::runtime_error {
+    dsbt_status st;
+    StatusError(dsbt_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// Phase factor exp(-i a) rounded to FP32 with |z| as close to one as the four
+// neighbouring roundings allow (keeps the step unitary to FP32 rounding).
+float2 unit_phase(double a) {
+    const double twopi = 6.283185307179586476925286766559;
+    a -= twopi * std::nearbyint(a / twopi);
+    const double c = std::cos(a), s = -std::sin(a);
+    const float c0 = (float)c, s0 = (float)s;
+    float best_c = c0, best_s = s0;
+    double best = 1e300;
+    for (int dc = -1; dc <= 1; ++dc) {
+        for (int ds = -1; ds <= 1; ++ds) {
+            float cc = c0, ss = s0;
+            if (dc) cc = std::nextafter(c0, dc > 0 ? 2.0f : -2.0f);
+            if (ds) ss = std::nextafter(s0, ds > 0 ? 2.0f : -2.0f);
+            // stay within one ulp of the exact value
+            if (std::fabs((double)cc - c) > 2.0 * std::fabs((double)std::nextafter(c0, 2.0f) - c0)) continue;
+            if (std::fabs((double)ss - s) > 2.0 * std::fabs((double)std::nextafter(s0, 2.0f) - s0)) continue;
+            const double m = std::fabs((double)cc * cc + (double)ss * ss - 1.0);
+            if (m < best) {
+                best = m;
+                best_c = cc;
+                best_s = ss;
+            }
+        }
+    }
+    return make_float2(best_c, best_s);
+}
+
+}  // namespace
+
+struct dsbt_plan_s {
+    int device = 0;
+    int precision = DSBT_C64;
+    dsbt_plan_opts opts{};
+    std::vector<dsbt_channel> ch;
+    int64_t elems = 0;
+    size_t elem_bytes = 8;
+    int maxN = 0, maxR = 0;
+
+    // groups of channels with equal (N, l, rmax)
+    struct Group {
+        int N, ell, p, k, B, R, NT;
+        double rmax;
+        std::vector<int> chans;
+        float2* d_kphase = nullptr;  // per slot, after set_potential
+    };
+    std::vector<Group> groups;
+
+    std::vector<void*> allocs;
+    int64_t table_bytes = 0;
+
+    dsbt::FChan* d_fchans = nullptr;     // one per channel
+    dsbt::MItem* d_items = nullptr;      // batched items
+    int nitems = 0;
+    dsbt::MItem* d_items1 = nullptr;     // one channel per item, channel order
+    std::vector<dsbt::FChan> h_fchans;
+
+    // potential
+    bool has_potential = false;
+    double dt = 0.0;
+    float2* d_vphase = nullptr;
+    double* d_vangle = nullptr;
+    double* d_scratch = nullptr;
+
+    // graph cache for dsbt_kinetic_step
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::tuple<void*, int, const float*, int> graph_key{nullptr, 0, nullptr, 0};
+
+    void* dalloc(size_t bytes) {
+        void* p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw StatusError(DSBT_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        allocs.push_back(p);
+        table_bytes += (int64_t)bytes;
+        return p;
+    }
+    void release() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        for (void* p : allocs) (void)hipFree(p);
+        allocs.clear();
+    }
+};
+
+namespace {
+
+template <typename T>
+void* upload_converted(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s) {
+    std::vector<T> h(v.size());
+    for (size_t i = 0; i < v.size(); ++i) h[i] = (T)v[i];
+    void* d = P->dalloc(h.size() * sizeof(T));
+    hip_check(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+    return d;
+}
+
+dsbt_status validate_channels(const dsbt_channel* ch, int nch, int precision, size_t max_lds) {
+    if (!ch || nch <= 0) return fail(DSBT_ERR_INVALID_ARG, "no channels");
+    std::vector<std::pair<int64_t, int64_t>> iv;
+    for (int c = 0; c < nch; ++c) {
+        const dsbt_channel& x = ch[c];
+        if (!is_pow2(x.N) || x.N < 16 || x.N > 8192)
+            return fail(DSBT_ERR_UNSUPPORTED, "channel " + std::to_string(c) + ": N must be a power of two in [16, 8192]");
+        const size_t lds = (size_t)x.N * (precision == DSBT_C128 ? 16 : 8);
+        if (lds > max_lds)
+            return fail(DSBT_ERR_UNSUPPORTED, "channel " + std::to_string(c) + ": N too large for LDS at this precision");
+        if (x.ell < 0 || x.ell > 2 * x.N - 2 || x.ell > 255)
+            return fail(DSBT_ERR_UNSUPPORTED, "channel " + std::to_string(c) + ": need 0 <= l <= min(2N-2, 255)");
+        if (!(x.rmax > 0.0) || !std::isfinite(x.rmax))
+            return fail(DSBT_ERR_INVALID_ARG, "channel " + std::to_string(c) + ": rmax must be positive");
+        if (x.offset < 0) return fail(DSBT_ERR_INVALID_ARG, "channel " + std::to_string(c) + ": negative offset");
+        iv.emplace_back(x.offset, x.offset + x.N);
+    }
+    std::sort(iv.begin(), iv.end());
+    for (size_t i = 1; i < iv.size(); ++i)
+        if (iv[i].first < iv[i - 1].second) return fail(DSBT_ERR_INVALID_ARG, "channels overlap");
+    return DSBT_OK;
+}
+
+template <typename T>
+void build_plan(dsbt_plan_s* P, hipStream_t s) {
+    const int nch = (int)P->ch.size();
+    // groups
+    std::map<std::tuple<int, int, double>, int> gid;
+    for (int c = 0; c < nch; ++c) {
+        const auto& x = P->ch[c];
+        auto key = std::make_tuple(x.N, x.ell, x.rmax);
+        auto itg = gid.find(key);
+        if (itg == gid.end()) {
+            dsbt_plan_s::Group g;
+            g.N = x.N;
+            g.ell = x.ell;
+            g.rmax = x.rmax;
+            g.p = dsbt::parity_p(x.ell);
+            g.k = dsbt::n_extra(x.ell);
+            gid[key] = (int)P->groups.size();
+            P->groups.push_back(g);
+            itg = gid.find(key);
+        }
+        P->groups[itg->second].chans.push_back(c);
+    }
+    // tile per l: shared by every N with that l
+    std::map<int, int> minN, maxN;
+    for (auto& g : P->groups) {
+        minN[g.ell] = minN.count(g.ell) ? std::min(minN[g.ell], g.N) : g.N;
+        maxN[g.ell] = std::max(maxN[g.ell], g.N);
+    }
+    std::map<int, int> tileB;
+    for (auto& kv : minN) {
+        const int ell = kv.first;
+        int B = dsbt::auto_tile(ell, kv.second);
+        const int req = P->opts.tile;
+        if (req > 0) {
+            if (!is_pow2(req) || req < dsbt::n0_of(ell) || req > kv.second)
+                throw StatusError(DSBT_ERR_UNSUPPORTED, "requested tile does not fit l = " + std::to_string(ell));
+            B = req;
+        }
+        tileB[ell] = B;
+    }
+    // moment tables per l
+    struct Tab { const void* f; const void* i; };
+    std::map<int, Tab> tabs;
+    for (auto& kv : tileB) {
+        const int ell = kv.first, B = kv.second, NT = maxN[ell] / B;
+        const int R = B + dsbt::n_extra(ell);
+        std::vector<double> blk;
+        dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
+        std::vector<double> tr(blk.size());
+        for (int J = 0; J < NT; ++J) {
+            const double* a = blk.data() + (size_t)J * R * R;
+            double* b = tr.data() + (size_t)J * R * R;
+            for (int q = 0; q < R; ++q)
+                for (int r = 0; r < R; ++r) b[(size_t)q * R + r] = a[(size_t)r * R + q];
+        }
+        Tab t;
+        t.f = upload_converted<T>(P, tr, s);
+        t.i = upload_converted<T>(P, blk, s);
+        tabs[ell] = t;
+    }
+    // twiddles per N
+    std::map<int, std::pair<const void*, const void*>> twd;
+    for (auto& g : P->groups) {
+        if (twd.count(g.N)) continue;
+        std::vector<double> tw, post;
+        dsbt::fft_twiddles(g.N, tw, post);
+        twd[g.N] = {upload_converted<T>(P, tw, s), upload_converted<T>(P, post, s)};
+    }
+    // channel descriptors
+    P->h_fchans.resize(nch);
+    P->maxN = 0;
+    for (int c = 0; c < nch; ++c) {
+        const auto& x = P->ch[c];
+        dsbt::FChan f{};
+        f.off = x.offset;
+        f.N = x.N;
+        f.log2N = ilog2(x.N);
+        f.p = dsbt::parity_p(x.ell);
+        const int sg = (((x.ell + 1) / 2) % 2) ? -1 : 1;
+        f.sign = (P->opts.sign == DSBT_SIGN_PRINTED_F) ? 1.0f : (float)sg;
+        f.tw = twd[x.N].first;
+        f.post = twd[x.N].second;
+        P->h_fchans[c] = f;
+        P->maxN = std::max(P->maxN, x.N);
+    }
+    P->d_fchans = (dsbt::FChan*)P->dalloc(sizeof(dsbt::FChan) * nch);
+    hip_check(hipMemcpy(P->d_fchans, P->h_fchans.data(), sizeof(dsbt::FChan) * nch, hipMemcpyHostToDevice), "fchans");
+    // moment items
+    int cpi = P->opts.chans_per_block > 0 ? std::min(P->opts.chans_per_block, dsbt::kMaxChanPerItem)
+                                          : dsbt::kMaxChanPerItem;
+    std::vector<dsbt::MItem> items, items1(nch);
+    P->maxR = 0;
+    for (auto& g : P->groups) {
+        g.B = tileB[g.ell];
+        g.R = g.B + g.k;
+        g.NT = g.N / g.B;
+        P->maxR = std::max(P->maxR, g.R);
+        dsbt::MItem base{};
+        base.tab_f = tabs[g.ell].f;
+        base.tab_i = tabs[g.ell].i;
+        base.B = g.B;
+        base.k = g.k;
+        base.R = g.R;
+        base.NT = g.NT;
+        base.p = g.p;
+        for (size_t i0 = 0; i0 < g.chans.size(); i0 += cpi) {
+            dsbt::MItem it = base;
+            it.nch = (int)std::min<size_t>(cpi, g.chans.size() - i0);
+            for (int j = 0; j < it.nch; ++j) it.off[j] = P->ch[g.chans[i0 + j]].offset;
+            items.push_back(it);
+        }
+        for (int c : g.chans) {
+            dsbt::MItem it = base;
+            it.nch = 1;
+            it.off[0] = P->ch[c].offset;
+            items1[c] = it;
+        }
+    }
+    // heaviest items first
+    std::stable_sort(items.begin(), items.end(), [](const dsbt::MItem& a, const dsbt::MItem& b) {
+        return (double)a.NT * a.R * a.R * a.nch > (double)b.NT * b.R * b.R * b.nch;
+    });
+    P->nitems = (int)items.size();
+    P->d_items = (dsbt::MItem*)P->dalloc(sizeof(dsbt::MItem) * items.size());
+    hip_check(hipMemcpy(P->d_items, items.data(), sizeof(dsbt::MItem) * items.size(), hipMemcpyHostToDevice), "items");
+    P->d_items1 = (dsbt::MItem*)P->dalloc(sizeof(dsbt::MItem) * nch);
+    hip_check(hipMemcpy(P->d_items1, items1.data(), sizeof(dsbt::MItem) * nch, hipMemcpyHostToDevice), "items1");
+    P->d_scratch = (double*)P->dalloc(sizeof(double) * (nch + 1));
+    const size_t f_lds = P->elem_bytes * (size_t)P->maxN;
+    const size_t m_lds = P->elem_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
+    hip_check(dsbt::set_lds_limits<T>(f_lds, m_lds), "set LDS limits");
+}
+
+template <typename T>
+void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv,
+                     dsbt::PhaseArgs pk) {
+    const int nch = (int)P->ch.size();
+    dsbt::PhaseArgs none{};
+    (void)none;
+    if (P->opts.mode == DSBT_MODE_PLAIN) {
+        for (int c = 0; c < nch; ++c) {
+            hip_check(dsbt::launch_fstage<T>(P->d_fchans + c, 1, P->ch[c].N, src, dst, false, pv, s), "fstage");
+            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, dst, dst, false, pk, s), "mstage");
+        }
+        return;
+    }
+    hip_check(dsbt::launch_fstage<T>(P->d_fchans, nch, P->maxN, src, dst, false, pv, s), "fstage");
+    hip_check(dsbt::launch_mstage<T>(P->d_items, P->nitems, P->maxR, dst, dst, false, pk, s), "mstage");
+}
+
+template <typename T>
+void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv) {
+    const int nch = (int)P->ch.size();
+    dsbt::PhaseArgs none{};
+    if (P->opts.mode == DSBT_MODE_PLAIN) {
+        for (int c = 0; c < nch; ++c) {
+            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, true, none, s), "mstage");
+            hip_check(dsbt::launch_fstage<T>(P->d_fchans + c, 1, P->ch[c].N, dst, dst, true, pv, s), "fstage");
+        }
+        return;
+    }
+    hip_check(dsbt::launch_mstage<T>(P->d_items, P->nitems, P->maxR, src, dst, true, none, s), "mstage");
+    hip_check(dsbt::launch_fstage<T>(P->d_fchans, nch, P->maxN, dst, dst, true, pv, s), "fstage");
+}
+
+template <typename T>
+void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool adjoint, hipStream_t s) {
+    for (int u = 0; u < nsteps; ++u) {
+        const int t = adjoint ? (nsteps - 1 - u) : u;
+        dsbt::PhaseArgs pv{1, adjoint ? 1 : 0, sc, t};
+        dsbt::PhaseArgs pk{1, adjoint ? 1 : 0, nullptr, 0};
+        enqueue_forward<T>(P, psi, psi, s, pv, pk);
+        enqueue_inverse<T>(P, psi, psi, s, pv);
+    }
+}
+
+template <typename F>
+dsbt_status guarded(F&& f) {
+    try {
+        return f();
+    } catch (const StatusError& e) {
+        return fail(e.st, e.what());
+    } catch (const HipError& e) {
+        return fail(DSBT_ERR_HIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(DSBT_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(DSBT_ERR_INVALID_ARG, e.what());
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void dsbt_plan_opts_default(dsbt_plan_opts* o) {
+    if (o) std::memset(o, 0, sizeof(*o));
+}
+
+dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch, const dsbt_plan_opts* o,
+                             void* stream) {
+    if (!out) return fail(DSBT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    return guarded([&]() -> dsbt_status {
+        dsbt_plan_opts opts{};
+        if (o) opts = *o;
+        if (opts.precision != DSBT_C64 && opts.precision != DSBT_C128)
+            return fail(DSBT_ERR_INVALID_ARG, "unknown precision");
+        if (opts.kinetic != DSBT_K_PLAIN) return fail(DSBT_ERR_UNSUPPORTED, "corrected kinetic momenta not built in");
+        if (opts.mode != DSBT_MODE_BATCHED && opts.mode != DSBT_MODE_PLAIN)
+            return fail(DSBT_ERR_INVALID_ARG, "unknown mode");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(DSBT_ERR_NO_DEVICE, "no HIP device");
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        size_t max_lds = prop.sharedMemPerBlock;
+        if (prop.maxSharedMemoryPerMultiProcessor > max_lds) max_lds = prop.maxSharedMemoryPerMultiProcessor;
+        dsbt_status st = validate_channels(ch, nch, opts.precision, max_lds);
+        if (st != DSBT_OK) return st;
+        dsbt_plan_s* P = new dsbt_plan_s();
+        P->device = dev;
+        P->opts = opts;
+        P->precision = opts.precision;
+        P->elem_bytes = opts.precision == DSBT_C128 ? 16 : 8;
+        P->ch.assign(ch, ch + nch);
+        for (auto& x : P->ch) P->elems = std::max<int64_t>(P->elems, x.offset + x.N);
+        try {
+            hipStream_t s = (hipStream_t)stream;
+            if (P->precision == DSBT_C128)
+                build_plan<double>(P, s);
+            else
+                build_plan<float>(P, s);
+            hip_check(hipStreamSynchronize(s), "plan sync");
+        } catch (...) {
+            P->release();
+            delete P;
+            throw;
+        }
+        *out = P;
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_plan_create_uniform(dsbt_plan* out, int32_t N, double rmax, const int32_t* ells, int32_t nell,
+                                     int32_t all_m, const dsbt_plan_opts* o, void* stream) {
+    if (!out) return fail(DSBT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ells || nell <= 0) return fail(DSBT_ERR_INVALID_ARG, "no l values");
+    std::vector<dsbt_channel> ch;
+    int64_t off = 0;
+    for (int i = 0; i < nell; ++i) {
+        if (ells[i] < 0) return fail(DSBT_ERR_UNSUPPORTED, "negative l");
+        const int reps = all_m ? 2 * ells[i] + 1 : 1;
+        for (int m = 0; m < reps; ++m) {
+            ch.push_back(dsbt_channel{N, ells[i], rmax, off});
+            off += N;
+        }
+    }
+    return dsbt_plan_create(out, ch.data(), (int32_t)ch.size(), o, stream);
+}
+
+dsbt_status dsbt_plan_destroy(dsbt_plan p) {
+    if (!p) return DSBT_OK;
+    p->release();
+    delete p;
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_plan_info(dsbt_plan p, int32_t* nch, int64_t* elems, int32_t* precision, int64_t* table_bytes) {
+    if (!p) return fail(DSBT_ERR_INVALID_ARG, "plan is NULL");
+    if (nch) *nch = (int32_t)p->ch.size();
+    if (elems) *elems = p->elems;
+    if (precision) *precision = p->precision;
+    if (table_bytes) *table_bytes = p->table_bytes;
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_forward(dsbt_plan p, const void* psi, void* b, void* stream) {
+    if (!p || !psi || !b) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> dsbt_status {
+        dsbt::PhaseArgs none{};
+        if (p->precision == DSBT_C128)
+            enqueue_forward<double>(p, psi, b, (hipStream_t)stream, none, none);
+        else
+            enqueue_forward<float>(p, psi, b, (hipStream_t)stream, none, none);
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream) {
+    if (!p || !psi || !b) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> dsbt_status {
+        dsbt::PhaseArgs none{};
+        if (p->precision == DSBT_C128)
+            enqueue_inverse<double>(p, b, psi, (hipStream_t)stream, none);
+        else
+            enqueue_inverse<float>(p, b, psi, (hipStream_t)stream, none);
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
+    if (!p || !V) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DSBT_ERR_INVALID_ARG, "dt must be positive");
+    return guarded([&]() -> dsbt_status {
+        const int64_t n = p->elems;
+        std::vector<float2> ph(n, make_float2(1.0f, 0.0f));
+        std::vector<double> ang(n, 0.0);
+        for (auto& x : p->ch) {
+            for (int i = 0; i < x.N; ++i) {
+                const double v = V[x.offset + i];
+                if (!std::isfinite(v)) throw StatusError(DSBT_ERR_INVALID_ARG, "non-finite potential");
+                ang[x.offset + i] = v * dt / 2.0;
+                ph[x.offset + i] = unit_phase(v * dt / 2.0);
+            }
+        }
+        if (!p->d_vphase) {
+            p->d_vphase = (float2*)p->dalloc(sizeof(float2) * n);
+            p->d_vangle = (double*)p->dalloc(sizeof(double) * n);
+        }
+        hip_check(hipMemcpy(p->d_vphase, ph.data(), sizeof(float2) * n, hipMemcpyHostToDevice), "vphase");
+        hip_check(hipMemcpy(p->d_vangle, ang.data(), sizeof(double) * n, hipMemcpyHostToDevice), "vangle");
+        // kinetic phases per group: K = (n dk)^2/2 for regular rows, (N dk)^2/2 for completion rows
+        const double pi = 3.14159265358979323846;
+        for (auto& g : p->groups) {
+            const double dk = pi / g.rmax;
+            std::vector<float2> kp(g.N);
+            for (int j = 0; j < g.N; ++j) {
+                const int nidx = j + g.p;
+                const double kn = (j < g.k) ? g.N * dk : nidx * dk;
+                kp[j] = unit_phase(0.5 * kn * kn * dt);
+            }
+            if (!g.d_kphase) g.d_kphase = (float2*)p->dalloc(sizeof(float2) * g.N);
+            hip_check(hipMemcpy(g.d_kphase, kp.data(), sizeof(float2) * g.N, hipMemcpyHostToDevice), "kphase");
+        }
+        // refresh descriptors with the phase pointers
+        for (size_t c = 0; c < p->ch.size(); ++c) {
+            p->h_fchans[c].vphase = p->d_vphase + p->ch[c].offset;
+            p->h_fchans[c].vangle = p->d_vangle + p->ch[c].offset;
+        }
+        hip_check(hipMemcpy(p->d_fchans, p->h_fchans.data(), sizeof(dsbt::FChan) * p->ch.size(),
+                            hipMemcpyHostToDevice), "fchans");
+        std::vector<dsbt::MItem> items(p->nitems), items1(p->ch.size());
+        hip_check(hipMemcpy(items.data(), p->d_items, sizeof(dsbt::MItem) * p->nitems, hipMemcpyDeviceToHost), "items");
+        hip_check(hipMemcpy(items1.data(), p->d_items1, sizeof(dsbt::MItem) * p->ch.size(), hipMemcpyDeviceToHost),
+                  "items1");
+        std::map<int64_t, float2*> by_off;
+        for (auto& g : p->groups)
+            for (int c : g.chans) by_off[p->ch[c].offset] = g.d_kphase;
+        for (auto& it : items) it.kphase = by_off[it.off[0]];
+        for (auto& it : items1) it.kphase = by_off[it.off[0]];
+        hip_check(hipMemcpy(p->d_items, items.data(), sizeof(dsbt::MItem) * p->nitems, hipMemcpyHostToDevice), "items");
+        hip_check(hipMemcpy(p->d_items1, items1.data(), sizeof(dsbt::MItem) * p->ch.size(), hipMemcpyHostToDevice),
+                  "items1");
+        p->has_potential = true;
+        p->dt = dt;
+        if (p->graph_exec) {
+            (void)hipGraphExecDestroy(p->graph_exec);
+            (void)hipGraphDestroy(p->graph);
+            p->graph_exec = nullptr;
+            p->graph = nullptr;
+        }
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const float* s, int32_t flags, void* stream) {
+    if (!p || !psi) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (nsteps < 0) return fail(DSBT_ERR_INVALID_ARG, "negative step count");
+    if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    if (flags & ~(DSBT_STEP_ADJOINT | DSBT_STEP_GRAPH | DSBT_STEP_RESIDENT))
+        return fail(DSBT_ERR_INVALID_ARG, "unknown step flag");
+    if (flags & DSBT_STEP_RESIDENT) return fail(DSBT_ERR_UNSUPPORTED, "resident step kernel not built in");
+    if (nsteps == 0) return DSBT_OK;
+    return guarded([&]() -> dsbt_status {
+        hipStream_t st = (hipStream_t)stream;
+        const bool adj = (flags & DSBT_STEP_ADJOINT) != 0;
+        auto enqueue = [&](hipStream_t q) {
+            if (p->precision == DSBT_C128)
+                enqueue_steps<double>(p, psi, nsteps, s, adj, q);
+            else
+                enqueue_steps<float>(p, psi, nsteps, s, adj, q);
+        };
+        if (!(flags & DSBT_STEP_GRAPH)) {
+            enqueue(st);
+            return DSBT_OK;
+        }
+        auto key = std::make_tuple(psi, (int)nsteps, s, (int)flags);
+        if (!p->graph_exec || p->graph_key != key) {
+            if (p->graph_exec) {
+                (void)hipGraphExecDestroy(p->graph_exec);
+                (void)hipGraphDestroy(p->graph);
+                p->graph_exec = nullptr;
+                p->graph = nullptr;
+            }
+            hipStream_t cap;
+            hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                try {
+                    enqueue(cap);
+                } catch (...) {
+                    hipGraph_t g;
+                    (void)hipStreamEndCapture(cap, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    (void)hipStreamDestroy(cap);
+                    throw;
+                }
+                e = hipStreamEndCapture(cap, &p->graph);
+            }
+            (void)hipStreamDestroy(cap);
+            hip_check(e, "graph capture");
+            hip_check(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0), "graph instantiate");
+            p->graph_key = key;
+        }
+        hip_check(hipGraphLaunch(p->graph_exec, st), "graph launch");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1, const void* lam_t,
+                             const void* lam_t1, double* out, void* stream) {
+    if (!p || !psi_t || !psi_t1 || !lam_t || !lam_t1 || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    return guarded([&]() -> dsbt_status {
+        const int nch = (int)p->ch.size();
+        hipStream_t st = (hipStream_t)stream;
+        if (p->precision == DSBT_C128)
+            hip_check(dsbt::launch_grad_s<double>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
+                                                  st), "grad_s");
+        else
+            hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
+                                                 st), "grad_s");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out, int64_t out_len, int64_t* needed) {
+    if (!is_pow2(N) || N < 2) return fail(DSBT_ERR_UNSUPPORTED, "N must be a power of two");
+    if (ell < 0 || ell > 2 * N - 2) return fail(DSBT_ERR_UNSUPPORTED, "need 0 <= l <= 2N-2");
+    if (!is_pow2(B) || B > N || B < dsbt::n0_of(ell)) return fail(DSBT_ERR_UNSUPPORTED, "bad tile");
+    const int R = B + dsbt::n_extra(ell), NT = N / B;
+    const int64_t need = (int64_t)R * R * NT;
+    if (needed) *needed = need;
+    if (!out || out_len < need) return DSBT_OK;
+    return guarded([&]() -> dsbt_status {
+        std::vector<double> blk;
+        dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
+        std::memcpy(out, blk.data(), sizeof(double) * blk.size());
+        return DSBT_OK;
+    });
+}
+
+const char* dsbt_status_string(dsbt_status s) {
+    switch (s) {
+        case DSBT_OK: return "ok";
+        case DSBT_ERR_INVALID_ARG: return "invalid argument";
+        case DSBT_ERR_UNSUPPORTED: return "unsupported size or option";
+        case DSBT_ERR_OOM: return "out of memory";
+        case DSBT_ERR_HIP: return "HIP error";
+        case DSBT_ERR_PLAN_MISMATCH: return "call does not fit the plan";
+        case DSBT_ERR_NO_DEVICE: return "no HIP device";
+        default: return "unknown status";
+    }
+}
+
+const char* dsbt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

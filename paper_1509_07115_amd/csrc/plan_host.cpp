@@ -1,0 +1,211 @@
+// Host FP64 plan generation for the orthogonal DSBT.  See plan_host.h for the
+// tiled moment form; the formulas cited here are those of Sec. 2.3-2.5.
+#include "plan_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <stdexcept>
+#include <thread>
+
+namespace dsbt {
+
+int parity_p(int ell) { return (ell % 2 == 0) ? 1 : 0; }
+int n0_of(int ell) { return (ell + 2) / 2; }            // ceil((l+1)/2), Sec. 2.4
+int n_extra(int ell) { return n0_of(ell) - parity_p(ell); }  // ceil(l/2), Sec. 2.5
+
+// Degree recurrence of the DLOP at fixed x (an identity of the
+// falling-factorial definition in Sec. 2.3):
+//   (j+1)(M-j) P_{j+1} = (2j+1)(M-2x) P_j - j(M+j+1) P_{j-1},  P_0 = 1, P_1 = 1 - 2x/M.
+// Fills out[j][x] for j = 0..dmax, x = 0..xmax.
+static void dlop_degree_table(int dmax, int M, int xmax, double* out) {
+    const int X = xmax + 1;
+    for (int x = 0; x <= xmax; ++x) out[x] = 1.0;
+    if (dmax == 0) return;
+    for (int x = 0; x <= xmax; ++x) out[X + x] = 1.0 - 2.0 * x / M;
+    for (int j = 1; j < dmax; ++j) {
+        const double a = 2.0 * j + 1.0, c = j * (M + j + 1.0), den = (j + 1.0) * (M - j);
+        const double* pm = out + (size_t)(j - 1) * X;
+        const double* pc = out + (size_t)j * X;
+        double* pn = out + (size_t)(j + 1) * X;
+        for (int x = 0; x <= xmax; ++x) pn[x] = (a * (M - 2.0 * x) * pc[x] - c * pm[x]) / den;
+    }
+}
+
+// Difference equation of the DLOP in x (Hahn form, alpha = beta = 0):
+//   B(x) y(x+1) = [d(d+1) + B(x) + D(x)] y(x) - D(x) y(x-1),
+//   B(x) = (x+1)(x-M), D(x) = x(x-M-1), y(0) = 1.
+static void dlop_march(int d, int M, int xmax, double* y) {
+    y[0] = 1.0;
+    if (xmax >= 1) y[1] = 1.0 - d * (d + 1.0) / M;
+    const double lam = d * (d + 1.0);
+    for (int x = 1; x < xmax; ++x) {
+        const double B = (x + 1.0) * (x - M), D = x * (x - M - 1.0);
+        y[x + 1] = ((lam + B + D) * y[x] - D * y[x - 1]) / B;
+    }
+}
+
+void dlop_values(int d, int M, int xmax, double* out) {
+    if (d < 0 || d > M || xmax > M) throw std::invalid_argument("dlop_values: bad degree or range");
+    if (M == 0) {
+        for (int x = 0; x <= xmax; ++x) out[x] = 1.0;
+        return;
+    }
+    if ((long long)d * d <= 2LL * M) {
+        // degree recurrence, keeping only the last two degrees
+        std::vector<double> a(xmax + 1, 1.0), b(xmax + 1), c(xmax + 1);
+        if (d == 0) {
+            std::copy(a.begin(), a.end(), out);
+            return;
+        }
+        for (int x = 0; x <= xmax; ++x) b[x] = 1.0 - 2.0 * x / M;
+        for (int j = 1; j < d; ++j) {
+            const double aa = 2.0 * j + 1.0, cc = j * (M + j + 1.0), den = (j + 1.0) * (M - j);
+            for (int x = 0; x <= xmax; ++x) c[x] = (aa * (M - 2.0 * x) * b[x] - cc * a[x]) / den;
+            std::swap(a, b);
+            std::swap(b, c);
+        }
+        std::copy(b.begin(), b.end(), out);
+        return;
+    }
+    dlop_march(d, M, xmax, out);
+}
+
+void tile_basis(int ell, int t, double* out) {
+    const int p = parity_p(ell), k = n_extra(ell);
+    if (k == 0) return;
+    const int M = 2 * t - 2, xmax = t - 1;   // DLOP grid 0..2t-2 centred at t-1
+    const int dmax = 2 * (k - 1) + p;          // highest degree, <= l - 1
+    if (dmax > M) throw std::invalid_argument("tile_basis: tile too small for the degree");
+    // degrees handled by the recurrence: d^2 <= 2M
+    int drec = 0;
+    while ((long long)(drec + 1) * (drec + 1) <= 2LL * M && drec + 1 <= dmax) ++drec;
+    std::vector<double> rec;
+    if (M > 0) {
+        rec.resize((size_t)(drec + 1) * (xmax + 1));
+        dlop_degree_table(drec, M, xmax, rec.data());
+    }
+    std::vector<double> tmp(xmax + 1);
+    for (int kk = 0; kk < k; ++kk) {
+        const int d = 2 * kk + p;
+        const double* P;
+        if (M == 0) {
+            tmp[0] = 1.0;
+            P = tmp.data();
+        } else if (d <= drec) {
+            P = rec.data() + (size_t)d * (xmax + 1);
+        } else {
+            dlop_march(d, M, xmax, tmp.data());
+            P = tmp.data();
+        }
+        // q(m) = (-1)^d P_d(t-1-m, M): the polynomial in m has parity (-1)^d
+        const double sg = (d & 1) ? -1.0 : 1.0;
+        double* q = out + (size_t)kk * t;
+        double nrm = 0.0;
+        for (int m = 0; m < t; ++m) {
+            q[m] = sg * P[t - 1 - m];
+            nrm += (m == 0 ? 0.5 : 1.0) * q[m] * q[m];
+        }
+        const double inv = 1.0 / std::sqrt(nrm);
+        for (int m = 0; m < t; ++m) q[m] *= inv;
+    }
+}
+
+int auto_tile(int ell, int N) {
+    int B = 16;
+    while (B < n0_of(ell)) B *= 2;
+    return std::min(B, N);
+}
+
+// Regular row n of T divided by w_m (Sec. 2.4 eq. Tdef/Ldef): kappa(m) for
+// m = 0..n, with kappa(n) the diagonal.  Up to a positive factor the row of
+// I - L is v_nn = 1, v_nm = w_m [P_l(n-m, 2n-1) - P_l(n-m-1, 2n-1)]; alpha_n is
+// the numerical norm of the weighted row over m = p..n.  kappa(0) is the kernel
+// polynomial's value at m = 0 also for even l, where m = 0 is not a grid slot.
+static void regular_row(int ell, int n, std::vector<double>& P, std::vector<double>& kap) {
+    const int p = parity_p(ell);
+    P.resize(n + 1);
+    dlop_values(ell, 2 * n - 1, n, P.data());
+    kap.resize(n + 1);
+    for (int m = 0; m < n; ++m) kap[m] = P[n - m] - P[n - m - 1];
+    kap[n] = 1.0;
+    double nrm = 0.0;
+    for (int m = p; m <= n; ++m) nrm += ((m == 0) ? 0.5 : 1.0) * kap[m] * kap[m];
+    const double beta = 1.0 / std::sqrt(nrm);
+    for (int m = 0; m <= n; ++m) kap[m] *= beta;
+}
+
+void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int nthreads) {
+    const int p = parity_p(ell), k = n_extra(ell), n0 = n0_of(ell);
+    const int R = B + k;
+    if (B < n0) throw std::invalid_argument("tile smaller than the first regular row");
+    blocks.assign((size_t)NT * R * R, 0.0);
+    std::atomic<int> next(0);
+    auto work = [&]() {
+        std::vector<double> qA, qB, P, kap;
+        for (;;) {
+            const int J = next.fetch_add(1);
+            if (J >= NT) break;
+            double* Mj = blocks.data() + (size_t)J * R * R;
+            const int t0 = p + J * B, t1 = t0 + B;
+            if (k > 0) {
+                qA.resize((size_t)k * t1);
+                tile_basis(ell, t1, qA.data());
+                if (J >= 1) {
+                    qB.resize((size_t)k * t0);
+                    tile_basis(ell, t0, qB.data());
+                }
+            }
+            for (int s = 0; s < B; ++s) {
+                const int n = t0 + s;
+                if (n < n0) continue;   // completion rows come from the final moments
+                regular_row(ell, n, P, kap);
+                double* row = Mj + (size_t)s * R;
+                for (int sp = 0; sp <= s; ++sp) row[sp] = kap[t0 + sp];
+                if (J >= 1) {
+                    for (int kk = 0; kk < k; ++kk) {
+                        const double* q = qB.data() + (size_t)kk * t0;
+                        double acc = 0.5 * kap[0] * q[0];
+                        for (int m = 1; m < t0; ++m) acc += kap[m] * q[m];
+                        row[B + kk] = acc;
+                    }
+                }
+            }
+            for (int a = 0; a < k; ++a) {
+                double* row = Mj + (size_t)(B + a) * R;
+                const double* qa = qA.data() + (size_t)a * t1;
+                for (int s = 0; s < B; ++s) row[s] = qa[t0 + s];
+                if (J >= 1) {
+                    for (int c = 0; c < k; ++c) {
+                        const double* qc = qB.data() + (size_t)c * t0;
+                        double acc = 0.5 * qa[0] * qc[0];
+                        for (int m = 1; m < t0; ++m) acc += qa[m] * qc[m];
+                        row[B + c] = acc;
+                    }
+                }
+            }
+        }
+    };
+    int nt = nthreads > 0 ? nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = std::min(nt, NT);
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nt; ++i) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+}
+
+void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
+    tw.resize(2 * (size_t)N);
+    post.resize(2 * (size_t)N);
+    const double pi = 3.14159265358979323846;
+    for (int t = 0; t < N; ++t) {
+        const double a = -2.0 * pi * t / N;
+        tw[2 * t] = std::cos(a);
+        tw[2 * t + 1] = std::sin(a);
+        const double b = -pi * t / (2.0 * N);
+        post[2 * t] = std::cos(b);
+        post[2 * t + 1] = std::sin(b);
+    }
+}
+
+}  // namespace dsbt
