@@ -12,6 +12,7 @@
 #include <stdexcept>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -101,11 +102,21 @@ struct dsbt_plan_s {
     std::vector<void*> allocs;
     int64_t table_bytes = 0;
 
-    dsbt::FChan* d_fchans = nullptr;     // one per channel
-    dsbt::MItem* d_items = nullptr;      // batched items
-    int nitems = 0;
-    dsbt::MItem* d_items1 = nullptr;     // one channel per item, channel order
+    dsbt::FChan* d_fchans = nullptr;     // one per channel, channel order
     std::vector<dsbt::FChan> h_fchans;
+    dsbt::FChan* d_fchans_n = nullptr;   // sorted by N, for one launch per N
+    std::vector<int> order_n;            // channel index of each entry of d_fchans_n
+    std::vector<std::tuple<int, int, int>> n_ranges;  // (N, first, count) in d_fchans_n
+    // moment-stage work items: matrix-core kernel (FP32, R16 <= 128) and the
+    // generic kernel (FP64 plans, larger blocks); per-channel items for the
+    // plain form
+    std::vector<dsbt::MItem> h_items_mf, h_items_v1, h_items1;
+    std::vector<char> items1_mf;          // per channel: item uses the matrix-core kernel
+    dsbt::MItem* d_items_mf = nullptr;
+    dsbt::MItem* d_items_v1 = nullptr;
+    dsbt::MItem* d_items1 = nullptr;
+    int mf_waves = 4;
+    size_t mf_lds = 0;
 
     // potential
     bool has_potential = false;
@@ -173,6 +184,12 @@ dsbt_status validate_channels(const dsbt_channel* ch, int nch, int precision, si
     return DSBT_OK;
 }
 
+void upload_fchans_n(dsbt_plan_s* P) {
+    std::vector<dsbt::FChan> v(P->ch.size());
+    for (size_t i = 0; i < v.size(); ++i) v[i] = P->h_fchans[P->order_n[i]];
+    hip_check(hipMemcpy(P->d_fchans_n, v.data(), sizeof(dsbt::FChan) * v.size(), hipMemcpyHostToDevice), "fchans");
+}
+
 template <typename T>
 void build_plan(dsbt_plan_s* P, hipStream_t s) {
     const int nch = (int)P->ch.size();
@@ -214,23 +231,35 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         tileB[ell] = B;
     }
     // moment tables per l
-    struct Tab { const void* f; const void* i; };
+    struct Tab { const void* f; const void* i; const float* mf; const float* mi; int NB; };
     std::map<int, Tab> tabs;
+    const bool fp32 = std::is_same<T, float>::value;
     for (auto& kv : tileB) {
         const int ell = kv.first, B = kv.second, NT = maxN[ell] / B;
-        const int R = B + dsbt::n_extra(ell);
+        const int k = dsbt::n_extra(ell), R = B + k;
         std::vector<double> blk;
         dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
-        std::vector<double> tr(blk.size());
-        for (int J = 0; J < NT; ++J) {
-            const double* a = blk.data() + (size_t)J * R * R;
-            double* b = tr.data() + (size_t)J * R * R;
-            for (int q = 0; q < R; ++q)
-                for (int r = 0; r < R; ++r) b[(size_t)q * R + r] = a[(size_t)r * R + q];
+        Tab t{nullptr, nullptr, nullptr, nullptr, 0};
+        // matrix-core path: B = 32 with R <= 64, or B = 64 with R <= 128
+        const int R16 = 2 * B;
+        if (fp32 && (B == 32 || B == 64) && R <= R16) {
+            t.NB = R16 / 16;
+            std::vector<double> arr;
+            dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, false, arr);
+            t.mf = (const float*)upload_converted<float>(P, arr, s);
+            dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, true, arr);
+            t.mi = (const float*)upload_converted<float>(P, arr, s);
+        } else {
+            std::vector<double> tr(blk.size());
+            for (int J = 0; J < NT; ++J) {
+                const double* a = blk.data() + (size_t)J * R * R;
+                double* b = tr.data() + (size_t)J * R * R;
+                for (int q = 0; q < R; ++q)
+                    for (int r = 0; r < R; ++r) b[(size_t)q * R + r] = a[(size_t)r * R + q];
+            }
+            t.f = upload_converted<T>(P, tr, s);
+            t.i = upload_converted<T>(P, blk, s);
         }
-        Tab t;
-        t.f = upload_converted<T>(P, tr, s);
-        t.i = upload_converted<T>(P, blk, s);
         tabs[ell] = t;
     }
     // twiddles per N
@@ -260,67 +289,166 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     }
     P->d_fchans = (dsbt::FChan*)P->dalloc(sizeof(dsbt::FChan) * nch);
     hip_check(hipMemcpy(P->d_fchans, P->h_fchans.data(), sizeof(dsbt::FChan) * nch, hipMemcpyHostToDevice), "fchans");
+    P->order_n.resize(nch);
+    for (int c = 0; c < nch; ++c) P->order_n[c] = c;
+    std::stable_sort(P->order_n.begin(), P->order_n.end(), [&](int a, int b) { return P->ch[a].N > P->ch[b].N; });
+    P->n_ranges.clear();
+    for (int i = 0; i < nch; ++i) {
+        const int N = P->ch[P->order_n[i]].N;
+        if (P->n_ranges.empty() || std::get<0>(P->n_ranges.back()) != N) P->n_ranges.emplace_back(N, i, 0);
+        std::get<2>(P->n_ranges.back())++;
+    }
+    P->d_fchans_n = (dsbt::FChan*)P->dalloc(sizeof(dsbt::FChan) * nch);
+    upload_fchans_n(P);
     // moment items
-    int cpi = P->opts.chans_per_block > 0 ? std::min(P->opts.chans_per_block, dsbt::kMaxChanPerItem)
-                                          : dsbt::kMaxChanPerItem;
-    std::vector<dsbt::MItem> items, items1(nch);
+    const int cpb = P->opts.chans_per_block;
+    bool any_nb8 = false;
+    for (auto& g : P->groups)
+        if (tabs[g.ell].NB == 8) any_nb8 = true;
+    P->mf_waves = any_nb8 ? 8 : 4;
+    std::vector<dsbt::MItem> items_mf, items_v1;
+    std::vector<int> items_mf_ell;
+    P->h_items1.assign(nch, dsbt::MItem{});
+    P->items1_mf.assign(nch, 0);
     P->maxR = 0;
+    P->mf_lds = 0;
     for (auto& g : P->groups) {
+        const Tab& t = tabs[g.ell];
         g.B = tileB[g.ell];
         g.R = g.B + g.k;
         g.NT = g.N / g.B;
         P->maxR = std::max(P->maxR, g.R);
         dsbt::MItem base{};
-        base.tab_f = tabs[g.ell].f;
-        base.tab_i = tabs[g.ell].i;
+        base.tab_f = t.f;
+        base.tab_i = t.i;
+        base.mf_f = t.mf;
+        base.mf_i = t.mi;
         base.B = g.B;
         base.k = g.k;
         base.R = g.R;
         base.NT = g.NT;
         base.p = g.p;
-        for (size_t i0 = 0; i0 < g.chans.size(); i0 += cpi) {
+        base.NB = t.NB;
+        const bool mf = t.mf != nullptr;
+        int per = dsbt::kMaxChanPerItem;
+        if (mf) {
+            base.NCB = dsbt::mfma_ncb(P->mf_waves, base.NB);
+            per = 8 * base.NCB;
+        }
+        if (cpb > 0) per = std::min(per, cpb);
+        for (size_t i0 = 0; i0 < g.chans.size(); i0 += per) {
             dsbt::MItem it = base;
-            it.nch = (int)std::min<size_t>(cpi, g.chans.size() - i0);
-            for (int j = 0; j < it.nch; ++j) it.off[j] = P->ch[g.chans[i0 + j]].offset;
-            items.push_back(it);
+            it.nch = (int)std::min<size_t>(per, g.chans.size() - i0);
+            for (int j = 0; j < dsbt::kMaxChanPerItem; ++j)
+                it.off[j] = P->ch[g.chans[i0 + (j < it.nch ? j : 0)]].offset;   // repeat a real channel
+            if (mf) {
+                items_mf.push_back(it);
+                items_mf_ell.push_back(g.ell);
+                P->mf_lds = std::max(P->mf_lds, dsbt::mfma_lds_bytes_for(it.NB, it.NCB, it.B));
+            } else {
+                items_v1.push_back(it);
+            }
         }
         for (int c : g.chans) {
             dsbt::MItem it = base;
             it.nch = 1;
-            it.off[0] = P->ch[c].offset;
-            items1[c] = it;
+            for (int j = 0; j < dsbt::kMaxChanPerItem; ++j) it.off[j] = P->ch[c].offset;
+            P->h_items1[c] = it;
+            P->items1_mf[c] = mf ? 1 : 0;
+            if (mf) P->mf_lds = std::max(P->mf_lds, dsbt::mfma_lds_bytes_for(it.NB, it.NCB, it.B));
         }
     }
-    // heaviest items first
-    std::stable_sort(items.begin(), items.end(), [](const dsbt::MItem& a, const dsbt::MItem& b) {
+    // generic kernel: heaviest items first
+    std::stable_sort(items_v1.begin(), items_v1.end(), [](const dsbt::MItem& a, const dsbt::MItem& b) {
         return (double)a.NT * a.R * a.R * a.nch > (double)b.NT * b.R * b.R * b.nch;
     });
-    P->nitems = (int)items.size();
-    P->d_items = (dsbt::MItem*)P->dalloc(sizeof(dsbt::MItem) * items.size());
-    hip_check(hipMemcpy(P->d_items, items.data(), sizeof(dsbt::MItem) * items.size(), hipMemcpyHostToDevice), "items");
-    P->d_items1 = (dsbt::MItem*)P->dalloc(sizeof(dsbt::MItem) * nch);
-    hip_check(hipMemcpy(P->d_items1, items1.data(), sizeof(dsbt::MItem) * nch, hipMemcpyHostToDevice), "items1");
+    // matrix-core kernel: workgroup b runs on XCD b % 8.  Items of one l are cut
+    // into chunks of up to 4 (they read the same table at the same time, so a
+    // chunk shares that XCD's L2), chunks are dealt to the XCDs heaviest first
+    // by least accumulated cost, and the per-XCD lists are interleaved.
+    {
+        const int nx = 8, chunk = 4;
+        std::vector<std::pair<double, std::vector<int>>> chunks;
+        std::map<int, std::vector<int>> by_ell;
+        for (size_t i = 0; i < items_mf.size(); ++i) by_ell[items_mf_ell[i]].push_back((int)i);
+        for (auto& kv : by_ell) {
+            for (size_t j = 0; j < kv.second.size(); j += chunk) {
+                std::vector<int> ids(kv.second.begin() + j, kv.second.begin() + std::min(kv.second.size(), j + chunk));
+                double cost = 0.0;
+                for (int i : ids) cost += (double)items_mf[i].NT * items_mf[i].NB * items_mf[i].NB;
+                chunks.emplace_back(cost, ids);
+            }
+        }
+        std::stable_sort(chunks.begin(), chunks.end(),
+                         [](const auto& a, const auto& b) { return a.first > b.first; });
+        std::vector<std::vector<int>> bins(nx);
+        std::vector<double> load(nx, 0.0);
+        for (auto& ch : chunks) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int i : ch.second) bins[x].push_back(i);
+            load[x] += ch.first;
+        }
+        size_t depth = 0;
+        for (auto& b : bins) depth = std::max(depth, b.size());
+        std::vector<dsbt::MItem> placed(depth * nx, dsbt::MItem{});   // nch = 0: idle slot
+        for (int x = 0; x < nx; ++x)
+            for (size_t j = 0; j < bins[x].size(); ++j) placed[j * nx + x] = items_mf[bins[x][j]];
+        if (items_mf.empty()) placed.clear();
+        P->h_items_mf = placed;
+    }
+    P->h_items_v1 = items_v1;
+    auto upload_items = [&](const std::vector<dsbt::MItem>& v) -> dsbt::MItem* {
+        if (v.empty()) return nullptr;
+        auto* d = (dsbt::MItem*)P->dalloc(sizeof(dsbt::MItem) * v.size());
+        hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::MItem) * v.size(), hipMemcpyHostToDevice), "items");
+        return d;
+    };
+    P->d_items_mf = upload_items(P->h_items_mf);
+    P->d_items_v1 = upload_items(P->h_items_v1);
+    P->d_items1 = upload_items(P->h_items1);
     P->d_scratch = (double*)P->dalloc(sizeof(double) * (nch + 1));
     const size_t f_lds = P->elem_bytes * (size_t)P->maxN;
     const size_t m_lds = P->elem_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
     hip_check(dsbt::set_lds_limits<T>(f_lds, m_lds), "set LDS limits");
+    hip_check(dsbt::set_lds_limits_mfma(), "set LDS limits");
+    hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
+}
+
+template <typename T>
+void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
+    if (P->d_items_mf)
+        hip_check(dsbt::launch_mstage_mfma(P->d_items_mf, (int)P->h_items_mf.size(), P->mf_waves, P->mf_lds, src, dst,
+                                           inverse, ph, s), "mstage_mfma");
+    if (P->d_items_v1)
+        hip_check(dsbt::launch_mstage<T>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph, s),
+                  "mstage");
+}
+
+template <typename T>
+void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool inverse, hipStream_t s,
+                        dsbt::PhaseArgs ph) {
+    if (P->items1_mf[c])
+        hip_check(dsbt::launch_mstage_mfma(P->d_items1 + c, 1, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s),
+                  "mstage_mfma");
+    else
+        hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
 }
 
 template <typename T>
 void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv,
                      dsbt::PhaseArgs pk) {
     const int nch = (int)P->ch.size();
-    dsbt::PhaseArgs none{};
-    (void)none;
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
-            hip_check(dsbt::launch_fstage<T>(P->d_fchans + c, 1, P->ch[c].N, src, dst, false, pv, s), "fstage");
-            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, dst, dst, false, pk, s), "mstage");
+            hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, src, dst, false, pv, s), "fstage");
+            enqueue_mstage_one<T>(P, c, dst, dst, false, s, pk);
         }
         return;
     }
-    hip_check(dsbt::launch_fstage<T>(P->d_fchans, nch, P->maxN, src, dst, false, pv, s), "fstage");
-    hip_check(dsbt::launch_mstage<T>(P->d_items, P->nitems, P->maxR, dst, dst, false, pk, s), "mstage");
+    for (auto& r : P->n_ranges)
+        hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src, dst,
+                                           false, pv, s), "fstage");
+    enqueue_mstage<T>(P, dst, dst, false, s, pk);
 }
 
 template <typename T>
@@ -329,13 +457,15 @@ void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
     dsbt::PhaseArgs none{};
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
-            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, true, none, s), "mstage");
-            hip_check(dsbt::launch_fstage<T>(P->d_fchans + c, 1, P->ch[c].N, dst, dst, true, pv, s), "fstage");
+            enqueue_mstage_one<T>(P, c, src, dst, true, s, none);
+            hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
         }
         return;
     }
-    hip_check(dsbt::launch_mstage<T>(P->d_items, P->nitems, P->maxR, src, dst, true, none, s), "mstage");
-    hip_check(dsbt::launch_fstage<T>(P->d_fchans, nch, P->maxN, dst, dst, true, pv, s), "fstage");
+    enqueue_mstage<T>(P, src, dst, true, s, none);
+    for (auto& r : P->n_ranges)
+        hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst, dst,
+                                           true, pv, s), "fstage");
 }
 
 template <typename T>
@@ -517,18 +647,18 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
         }
         hip_check(hipMemcpy(p->d_fchans, p->h_fchans.data(), sizeof(dsbt::FChan) * p->ch.size(),
                             hipMemcpyHostToDevice), "fchans");
-        std::vector<dsbt::MItem> items(p->nitems), items1(p->ch.size());
-        hip_check(hipMemcpy(items.data(), p->d_items, sizeof(dsbt::MItem) * p->nitems, hipMemcpyDeviceToHost), "items");
-        hip_check(hipMemcpy(items1.data(), p->d_items1, sizeof(dsbt::MItem) * p->ch.size(), hipMemcpyDeviceToHost),
-                  "items1");
+        upload_fchans_n(p);
         std::map<int64_t, float2*> by_off;
         for (auto& g : p->groups)
             for (int c : g.chans) by_off[p->ch[c].offset] = g.d_kphase;
-        for (auto& it : items) it.kphase = by_off[it.off[0]];
-        for (auto& it : items1) it.kphase = by_off[it.off[0]];
-        hip_check(hipMemcpy(p->d_items, items.data(), sizeof(dsbt::MItem) * p->nitems, hipMemcpyHostToDevice), "items");
-        hip_check(hipMemcpy(p->d_items1, items1.data(), sizeof(dsbt::MItem) * p->ch.size(), hipMemcpyHostToDevice),
-                  "items1");
+        auto refresh = [&](std::vector<dsbt::MItem>& v, dsbt::MItem* d) {
+            for (auto& it : v)
+                if (it.nch > 0) it.kphase = by_off[it.off[0]];
+            if (d) hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::MItem) * v.size(), hipMemcpyHostToDevice), "items");
+        };
+        refresh(p->h_items_mf, p->d_items_mf);
+        refresh(p->h_items_v1, p->d_items_v1);
+        refresh(p->h_items1, p->d_items1);
         p->has_potential = true;
         p->dt = dt;
         if (p->graph_exec) {

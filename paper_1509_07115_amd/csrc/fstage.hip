@@ -1,0 +1,326 @@
+// Sine / cosine stage of the DSBT (Sec. 2.2, eq. csFourierBasis) with the FFT
+// size known at compile time.
+//
+// Forward, for one complex channel x of N points: even l flips x_i -> (-1)^i x_i
+// (the DST-II is the DCT-II of that sequence read backwards); the DCT-II
+// reorders v_j = x_2j, v_{N-1-j} = x_{2j+1}, takes V = FFT_N(v) and combines
+// X_k = (w^k V_k + w^-k V_{N-k})/2, w = exp(-i pi/(2N)); the orthonormal scale
+// sqrt((2 - delta_k0)/N) and the sign (-1)^ceil(l/2) follow.  The inverse
+// applies the exact transpose of every step; since the DFT matrix is
+// symmetric it uses the same forward FFT.
+//
+// Layout: a block handles CPB channels of N points with N/8 threads each; each
+// thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
+// pass for the remaining factor), data stay in LDS with one pad slot per 32
+// complex values.  Twiddles: one load per butterfly from the FP64-built table
+// exp(-2 pi i t/N), its powers by complex multiplication.
+#include "kernels.h"
+
+namespace dsbt {
+
+template <typename T> struct CV;
+template <> struct CV<float> { using t = float2; };
+template <> struct CV<double> { using t = double2; };
+
+template <typename V> __device__ __forceinline__ V f_add(V a, V b) { return {a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V f_sub(V a, V b) { return {a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V f_mul(V a, V b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename V, typename S> __device__ __forceinline__ V f_scale(V a, S s) { return {a.x * s, a.y * s}; }
+template <typename V> __device__ __forceinline__ V f_negi(V a) { return {a.y, -a.x}; }   // -i a
+template <typename V> __device__ __forceinline__ V f_posi(V a) { return {-a.y, a.x}; }   // +i a
+
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 5); }   // one LDS pad per 32 values
+
+// in-register DFTs with the forward sign exp(-2 pi i jk/R)
+template <typename T, typename V>
+__device__ __forceinline__ void dft2(V& a, V& b) {
+    const V t = a;
+    a = f_add(t, b);
+    b = f_sub(t, b);
+}
+template <typename T, typename V>
+__device__ __forceinline__ void dft4(V* v) {
+    const V a0 = f_add(v[0], v[2]), a1 = f_sub(v[0], v[2]);
+    const V a2 = f_add(v[1], v[3]), a3 = f_negi(f_sub(v[1], v[3]));
+    v[0] = f_add(a0, a2);
+    v[2] = f_sub(a0, a2);
+    v[1] = f_add(a1, a3);
+    v[3] = f_sub(a1, a3);
+}
+template <typename T, typename V>
+__device__ __forceinline__ void dft8(V* v) {
+    // two radix-4 on even/odd, then combine with exp(-2 pi i k/8)
+    V e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<T>(e);
+    dft4<T>(o);
+    const T h = (T)0.70710678118654752440;
+    const V o1 = {(o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h};   // o1 * exp(-i pi/4)
+    const V o2 = f_negi(o[2]);                                     // o2 * exp(-i pi/2)
+    const V o3 = {(o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h};  // o3 * exp(-3 i pi/4)
+    v[0] = f_add(e[0], o[0]);
+    v[4] = f_sub(e[0], o[0]);
+    v[1] = f_add(e[1], o1);
+    v[5] = f_sub(e[1], o1);
+    v[2] = f_add(e[2], o2);
+    v[6] = f_sub(e[2], o2);
+    v[3] = f_add(e[3], o3);
+    v[7] = f_sub(e[3], o3);
+}
+
+// One Stockham pass of radix R on the channel at buf (padded indexing);
+// thread t of the channel owns butterflies j = t + u N/8, u < 8/R.
+template <typename T, int N, int R>
+__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const typename CV<T>::t* tw, int t) {
+    using V = typename CV<T>::t;
+    constexpr int NR = N / R, U = 8 / R;
+    V v[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + u * (N / 8);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(j + r * NR)];
+        const int jm = j & (Ns - 1);
+        if (Ns > 1) {
+            const V w = tw[jm * (N / (Ns * R))];
+            V wr = w;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                v[u][r] = f_mul(v[u][r], wr);
+                if (r + 1 < R) wr = f_mul(wr, w);
+            }
+        }
+        if constexpr (R == 8) dft8<T>(v[u]);
+        else if constexpr (R == 4) dft4<T>(v[u]);
+        else dft2<T>(v[u][0], v[u][1]);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = t + u * (N / 8);
+        const int jm = j & (Ns - 1);
+        const int base = (j - jm) * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pidx(base + r * Ns)] = v[u][r];
+    }
+    lds_barrier();
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<T>::t* tw, int t) {
+    constexpr int L = __builtin_ctz(N);
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < L / 3; ++s) {
+        fft_pass<T, N, 8>(buf, Ns, tw, t);
+        Ns *= 8;
+    }
+    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw, t);
+    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw, t);
+}
+
+template <typename V>
+__device__ __forceinline__ V phase_factor(const FChan& c, int i, const PhaseArgs& ph);
+
+template <>
+__device__ __forceinline__ float2 phase_factor<float2>(const FChan& c, int i, const PhaseArgs& ph) {
+    float2 z;
+    if (ph.scale == nullptr) {
+        z = c.vphase[i];
+    } else {
+        double a = (double)ph.scale[ph.step] * c.vangle[i];
+        const double twopi = 6.283185307179586476925286766559;
+        a -= twopi * rint(a / twopi);
+        float sn, cs;
+        sincosf((float)a, &sn, &cs);
+        z = make_float2(cs, -sn);
+    }
+    if (ph.conj) z.y = -z.y;
+    return z;
+}
+template <>
+__device__ __forceinline__ double2 phase_factor<double2>(const FChan& c, int i, const PhaseArgs& ph) {
+    double2 z;
+    if (ph.scale == nullptr) {
+        z = make_double2((double)c.vphase[i].x, (double)c.vphase[i].y);
+    } else {
+        double a = (double)ph.scale[ph.step] * c.vangle[i];
+        const double twopi = 6.283185307179586476925286766559;
+        a -= twopi * rint(a / twopi);
+        double sn, cs;
+        sincos(a, &sn, &cs);
+        z = make_double2(cs, -sn);
+    }
+    if (ph.conj) z.y = -z.y;
+    return z;
+}
+
+constexpr int fstage_threads(int N) { return N / 8 >= 256 ? N / 8 : 256; }
+
+template <typename T, int N, bool INV>
+__global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
+                                                const typename CV<T>::t* src, typename CV<T>::t* dst, PhaseArgs ph) {
+    using V = typename CV<T>::t;
+    constexpr int TPC = N / 8;              // threads per channel
+    constexpr int PADN = N + N / 32;        // padded LDS slots per channel
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int cl = threadIdx.x / TPC, t = threadIdx.x % TPC;
+    const int cidx = blockIdx.x * cpb + cl;
+    V* buf = reinterpret_cast<V*>(smem_raw) + cl * PADN;
+    // a block's last slots may be past the channel list: they take part in the
+    // barriers on a copy of the last descriptor (valid tables) and store nothing
+    const bool live = cidx < nch;
+    const FChan c = chans[live ? cidx : nch - 1];
+    const V* tw = reinterpret_cast<const V*>(c.tw);
+    const V* post = reinterpret_cast<const V*>(c.post);
+    const T s0 = (T)c.sign * sqrt((T)1 / (T)N), s1 = (T)c.sign * sqrt((T)2 / (T)N);
+    if constexpr (!INV) {
+        if (live) {
+            const V* x = src + c.off;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = t + u * TPC;
+                V a = x[i];
+                if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
+                if (c.p && (i & 1)) a = {-a.x, -a.y};
+                buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))] = a;
+            }
+        }
+        lds_barrier();
+        fft_n<T, N>(buf, tw, t);
+        if (live) {
+            V* y = dst + c.off;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = t + u * TPC;
+                const V w = post[k];
+                const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
+                // w a + conj(w) b
+                V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
+                X = f_scale(X, (T)0.5 * (k == 0 ? s0 : s1));
+                y[c.p ? (N - 1 - k) : k] = X;
+            }
+        }
+    } else {
+        if (live) {
+            const V* f = src + c.off;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = t + u * TPC;
+                const int k = c.p ? (N - 1 - j) : j;
+                buf[pidx(k)] = f_scale(f[j], k == 0 ? s0 : s1);
+            }
+        }
+        lds_barrier();
+        // U = A^T X: U_0 = X_0, U_j = (w^j/2)(X_j + i X_{N-j})
+        V u8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = t + u * TPC;
+            if (j == 0) {
+                u8[u] = buf[0];
+            } else {
+                const V s = f_add(buf[pidx(j)], f_posi(buf[pidx(N - j)]));
+                u8[u] = f_scale(f_mul(post[j], s), (T)0.5);
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) buf[pidx(t + u * TPC)] = u8[u];
+        lds_barrier();
+        fft_n<T, N>(buf, tw, t);
+        if (live) {
+            V* x = dst + c.off;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = t + u * TPC;
+                V a = buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))];
+                if (c.p && (i & 1)) a = {-a.x, -a.y};
+                if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
+                x[i] = a;
+            }
+        }
+    }
+}
+
+// Threads per block for size N and channels per block.
+static inline void fstage_shape(int N, int& cpb, int& threads) {
+    const int tpc = N / 8;
+    cpb = tpc >= 256 ? 1 : 256 / tpc;
+    threads = tpc * cpb;
+}
+
+template <typename T, bool INV>
+static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void* dst, PhaseArgs ph, hipStream_t s) {
+    using V = typename CV<T>::t;
+    int cpb, threads;
+    fstage_shape(N, cpb, threads);
+    const int blocks = (nch + cpb - 1) / cpb;
+    const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
+#define DSBT_FN(NN)                                                                                     \
+    case NN:                                                                                            \
+        hipLaunchKernelGGL((fstage_n<T, NN, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,   \
+                           (const V*)src, (V*)dst, ph);                                                 \
+        break;
+    switch (N) {
+        DSBT_FN(16) DSBT_FN(32) DSBT_FN(64) DSBT_FN(128) DSBT_FN(256) DSBT_FN(512) DSBT_FN(1024)
+        DSBT_FN(2048)
+        case 4096:
+            hipLaunchKernelGGL((fstage_n<T, 4096, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,
+                               (const V*)src, (V*)dst, ph);
+            break;
+        case 8192:
+            hipLaunchKernelGGL((fstage_n<T, 8192, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,
+                               (const V*)src, (V*)dst, ph);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+#undef DSBT_FN
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
+                           PhaseArgs ph, hipStream_t s) {
+    if (nch <= 0) return hipSuccess;
+    return inverse ? launch_n<T, true>(N, d_chans, nch, src, dst, ph, s)
+                   : launch_n<T, false>(N, d_chans, nch, src, dst, ph, s);
+}
+
+template <typename T, bool INV>
+static hipError_t lds_attr_all() {
+    using V = typename CV<T>::t;
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f, int N) {
+        int cpb, threads;
+        fstage_shape(N, cpb, threads);
+        const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    set((const void*)fstage_n<T, 16, INV>, 16);
+    set((const void*)fstage_n<T, 32, INV>, 32);
+    set((const void*)fstage_n<T, 64, INV>, 64);
+    set((const void*)fstage_n<T, 128, INV>, 128);
+    set((const void*)fstage_n<T, 256, INV>, 256);
+    set((const void*)fstage_n<T, 512, INV>, 512);
+    set((const void*)fstage_n<T, 1024, INV>, 1024);
+    set((const void*)fstage_n<T, 2048, INV>, 2048);
+    set((const void*)fstage_n<T, 4096, INV>, 4096);
+    set((const void*)fstage_n<T, 8192, INV>, 8192);
+    return e;
+}
+
+template <typename T>
+hipError_t set_lds_limits_fstage_n() {
+    hipError_t e = lds_attr_all<T, false>();
+    if (e != hipSuccess) return e;
+    return lds_attr_all<T, true>();
+}
+
+template hipError_t launch_fstage_n<float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs, hipStream_t);
+template hipError_t launch_fstage_n<double>(int, const FChan*, int, const void*, void*, bool, PhaseArgs, hipStream_t);
+template hipError_t set_lds_limits_fstage_n<float>();
+template hipError_t set_lds_limits_fstage_n<double>();
+
+}  // namespace dsbt

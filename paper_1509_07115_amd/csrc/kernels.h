@@ -25,10 +25,21 @@ struct FChan {
 struct MItem {
     const void* tab_f;     // NT blocks, A[q][r] = M_J[r][q]
     const void* tab_i;     // NT blocks, A[q][r] = M_J[q][r]
+    const float* mf_f;     // MFMA operand layout of the forward blocks (FP32 plans), or nullptr
+    const float* mf_i;     // MFMA operand layout of the inverse blocks
     const float2* kphase;  // unit-modulus exp(-i K_n tau) per slot, or nullptr
     int B, k, R, NT, p, nch;
+    int NB;                // 16-row blocks of the padded block size R16 = 16 NB (1, 2, 4 or 8)
+    int NCB;               // 8-channel column blocks of the item (mfma_ncb on the matrix-core path)
     int64_t off[kMaxChanPerItem];
 };
+
+// MFMA operand layout of one direction's blocks: for tile J, row block rb and
+// lane l, the NK = 4 NB consecutive floats A'[16 rb + l%16][4 kc + l/16],
+// kc = 0..NK-1, where A' is the zero-padded R16 x R16 block mapping the input
+// vector (tile data, then moments) to the output vector (tile result, then
+// next moments).  size: NT * R16 * R16 floats.
+inline size_t mfma_table_floats(int NT, int NB) { return (size_t)NT * 256 * NB * NB; }
 
 // How a stage multiplies by the diagonal phases of the split step.
 struct PhaseArgs {
@@ -43,14 +54,61 @@ struct PhaseArgs {
 template <typename T>
 hipError_t set_lds_limits(size_t fstage_bytes, size_t mstage_bytes);
 
+// Pointers read from descriptor structs are generic (flat) to the compiler;
+// flat loads also count against the LDS counter, so an LDS wait would drain
+// them.  Kernels cast such pointers to the global address space.
+#define DSBT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const T DSBT_GLOBAL* as_global(const T* p) {
+    return (const T DSBT_GLOBAL*)p;
+}
+template <typename T>
+__device__ __forceinline__ T DSBT_GLOBAL* as_global_rw(T* p) {
+    return (T DSBT_GLOBAL*)p;
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() is a workgroup
+// release fence on all memory, which makes every thread wait for its
+// outstanding global loads (prefetches included) before the barrier; the
+// kernels here only exchange data through LDS, so the fence is limited to it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Launchers.  T = float (complex64 data) or double (complex128 data).
 template <typename T>
 hipError_t launch_fstage(const FChan* d_chans, int nch, int maxN, const void* src, void* dst,
                          bool inverse, PhaseArgs ph, hipStream_t s);
 
+// Sine/cosine stage for channels that all have N points (compile-time FFT size).
+template <typename T>
+hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
+                           PhaseArgs ph, hipStream_t s);
+template <typename T>
+hipError_t set_lds_limits_fstage_n();
+
 template <typename T>
 hipError_t launch_mstage(const MItem* d_items, int nitems, int maxR, const void* src, void* dst,
                          bool inverse, PhaseArgs ph, hipStream_t s);
+
+// Moment stage on the matrix cores (FP32 data).  waves = 4 when every item
+// has NB <= 4, else 8.  Every item has 8 NCB channel slots (off[]): slots past
+// nch repeat a real channel, whose results they then write again unchanged.
+// Phases (ph.use) are supported on the forward direction only.
+// lds: bytes of dynamic LDS, mfma_lds_bytes_for() maximised over the items.
+hipError_t launch_mstage_mfma(const MItem* d_items, int nitems, int waves, size_t lds, const void* src,
+                              void* dst, bool inverse, PhaseArgs ph, hipStream_t s);
+// Tile B that the matrix-core kernel is built for, given the padded block size
+// 16 NB (NB = 4 or 8: B = 32 or 64; the rows past B + k are zero padding).
+__host__ __device__ constexpr int mfma_tile_for(int NB) { return 8 * NB; }
+// 8-channel column blocks per item: enough row x column blocks for the waves.
+__host__ __device__ constexpr int mfma_ncb(int waves, int NB) { return NB * 2 <= waves ? 2 : 1; }
+inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
+    return sizeof(float) * (size_t)(2 * NCB * 16 * NB * 16 + 2 * NCB * B * 16);
+}
+hipError_t set_lds_limits_mfma();
 
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into
 // scratch[nch], then out[0] = their sum (FP64).

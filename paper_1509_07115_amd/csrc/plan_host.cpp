@@ -112,7 +112,9 @@ void tile_basis(int ell, int t, double* out) {
 }
 
 int auto_tile(int ell, int N) {
-    int B = 16;
+    // B >= 32: the tile steps form a serial chain per channel, so fewer, wider
+    // tiles (N/B steps) beat the smaller (B + k)^2 / B block cost of B = 16
+    int B = 32;
     while (B < n0_of(ell)) B *= 2;
     return std::min(B, N);
 }
@@ -192,6 +194,31 @@ void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int n
     for (int i = 1; i < nt; ++i) pool.emplace_back(work);
     work();
     for (auto& th : pool) th.join();
+}
+
+void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p, int NT, int NB, bool inverse,
+                         std::vector<double>& out) {
+    const int R = B + k, R16 = 16 * NB, NK = 4 * NB;
+    if (R > R16) throw std::invalid_argument("arrange_mfma_blocks: block larger than the padded size");
+    out.assign((size_t)NT * R16 * R16, 0.0);
+    const double w0 = std::sqrt(0.5);
+    for (int J = 0; J < NT; ++J) {
+        const double* M = blocks.data() + (size_t)J * R * R;
+        for (int rb = 0; rb < NB; ++rb) {
+            for (int l = 0; l < 64; ++l) {
+                const int row = 16 * rb + (l % 16);
+                double* o = out.data() + (((size_t)J * NB + rb) * 64 + l) * NK;
+                for (int kc = 0; kc < NK; ++kc) {
+                    const int q = 4 * kc + l / 16;
+                    if (row >= R || q >= R) continue;
+                    double v = inverse ? M[(size_t)q * R + row] : M[(size_t)row * R + q];
+                    // slot 0 of tile 0 is m = 0 for odd l, weighted by w_0
+                    if (J == 0 && p == 0 && (inverse ? row == 0 : q == 0)) v *= w0;
+                    o[kc] = v;
+                }
+            }
+        }
+    }
 }
 
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {

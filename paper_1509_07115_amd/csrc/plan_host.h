@@ -33,13 +33,20 @@ void dlop_values(int d, int M, int xmax, double* out);
 // the half-grid inner product (weight 1/2 at m = 0); out is [k][t].
 void tile_basis(int ell, int t, double* out);
 
-// Smallest admissible power-of-two tile (>= n0, >= 16) for l, capped at N.
+// Smallest admissible power-of-two tile (>= n0, >= 32) for l, capped at N.
 int auto_tile(int ell, int N);
 
 // Moment-tile blocks for (ell, B) over NT tiles, row-major M_J[r][q], R = B + k.
 // Rows of T are the same for every N, so one table serves every N = NT' B <= NT B.
 // `nthreads` host threads are used (0 = hardware concurrency).
 void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int nthreads);
+
+// Rearrange row-major blocks into the matrix-core operand layout (see
+// MItem::mf_f in kernels.h): A' = M_J (forward) or M_J^T (inverse), padded to
+// R16 = 16 NB, with the weight w_0 = 1/sqrt(2) of odd l folded into the slot-0
+// column (forward) or row (inverse) of tile 0.
+void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p, int NT, int NB, bool inverse,
+                         std::vector<double>& out);
 
 // FP64 twiddles exp(-2 pi i t / N), t < N, and exp(-i pi k / (2N)), k < N, as
 // interleaved (re, im).
