@@ -1,0 +1,173 @@
+"""Benchmark: batched complex64 DSBT forward + inverse on one MI355X.
+
+Workload: N = 2048 radial points, rmax = 100, l = 0..63 with all 2l+1 m
+channels (4096 channels, 8.4 M radial points), each channel a seeded sum of four
+Gaussians r^(l+1) exp(-a (r - r0)^2) with complex amplitudes (synthetic data).
+One step = one forward transform and one inverse transform of the whole batch,
+inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3, "valu_fp32_TFLOPs_nonpacked": 78.6}
+
+
+def algorithmic_counts(channels):
+    """Per launch of each stage, from the per-point operation model of the method:
+    sine/cosine stage 5 log2 N + 8 flops, moment stage 12 ceil(l/2) flops,
+    each stage reading and writing 8 bytes per point (complex64)."""
+    pts = sum(N for N, _, _, _ in channels)
+    f_sincos = sum(N * (5 * math.log2(N) + 8) for N, _, _, _ in channels)
+    f_moment = sum(N * 12 * ((l + 1) // 2) for N, l, _, _ in channels)
+    return pts, f_sincos, f_moment, 16.0 * pts
+
+
+def cpu_baseline(w, reps=15):
+    """Time the FP64 oracle (dense F and T) on whole l groups of the workload."""
+    import numpy as np
+    from oracle import dsbt as odsbt
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    groups = {}
+    for N, l, _, off in w.channels:
+        groups.setdefault(l, []).append(off)
+    N = w.channels[0][0]
+    sample_ells = (63, 47, 31, 15, 62, 46, 30, 14)
+    blocks = {}
+    for l in sample_ells:
+        blocks[l] = np.stack([w.psi[o:o + N] for o in groups[l]], axis=1)
+        odsbt.forward(blocks[l][:, :1], l)     # builds and caches F and T (plan time, not timed)
+    pts = sum(N * blocks[l].shape[1] for l in sample_ells) * reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        for l in sample_ells:
+            odsbt.inverse(odsbt.forward(blocks[l], l), l)
+    spent = time.perf_counter() - t
+    return {"value": pts / spent, "unit": "radial points/s", "cores": cores, "kind": "oracle",
+            "sample": f"dense FP64 oracle forward+inverse, {reps} passes over the l groups {list(sample_ells)} "
+                      f"with all m ({pts // reps} points per pass, N={N}), {spent:.1f} s; matrix build excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1509_07115_amd import Plan, _lib, workloads
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1509_07115_amd import build
+        build.build()
+
+    w = workloads.batched_all_m()
+    plan = Plan(w.channels)
+    x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+    b = plan.empty()
+    y = plan.empty()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.forward(x, b)
+        plan.inverse(b, y)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-stage HIP events on the launch stream
+    plan.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.forward(x, b)
+        plan.inverse(b, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    stages = plan.profile_read()
+    plan.profile(False)
+    ms_step = total_ms / args.steps
+    pts, f_sincos, f_moment, bytes_stage = algorithmic_counts(w.channels)
+    value = pts / (ms_step * 1e-3)
+
+    # dominant stage and its roofline (algorithmic flops / bytes per launch)
+    (ms_f, n_f), (ms_m, n_m) = stages["sincos"], stages["moment"]
+    avg_f, avg_m = ms_f / max(n_f, 1), ms_m / max(n_m, 1)
+    if avg_m >= avg_f:
+        achieved = f_moment / (avg_m * 1e-3) / 1e12
+        roof = {"kernel": "moment stage (dsbt::mstage_mfma)", "bound": "mfma", "achieved": achieved,
+                "peak": PEAK["mfma_fp32_TFLOPs"], "unit": "TFLOP/s", "frac": achieved / PEAK["mfma_fp32_TFLOPs"],
+                "traffic": None, "avg_launch_ms": avg_m,
+                "hbm_GBps_algorithmic": bytes_stage / (avg_m * 1e-3) / 1e9}
+    else:
+        achieved = bytes_stage / (avg_f * 1e-3) / 1e9
+        roof = {"kernel": "sine/cosine stage (dsbt::fstage_n)", "bound": "hbm", "achieved": achieved,
+                "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": achieved / PEAK["hbm_GBps"], "traffic": None,
+                "avg_launch_ms": avg_f}
+    roof["stages_ms_per_launch"] = {"sincos": avg_f, "moment": avg_m}
+
+    # accuracy on sampled l groups against the FP64 oracle
+    from oracle import dsbt as odsbt
+    bh = b.cpu().numpy().astype(np.complex128)
+    worst = 0.0
+    for N, l, _, off in w.channels:
+        if l in (1, 32, 63):
+            ref = odsbt.forward(w.psi[off:off + N], l)
+            worst = max(worst, float(np.linalg.norm(bh[off:off + N] - ref) / np.linalg.norm(ref)))
+    rt = float((y - x).abs().max().item() / x.abs().max().item())
+
+    out = {
+        "metric": "complex64 DSBT fwd+inv radial points/sec vs plain GPU form, at <=1e-5 rel err",
+        "value": value, "unit": "radial points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded Gaussian sums)",
+        "config": {"workload": "batched all-m DSBT, N=2048, rmax=100, l=0..63 with 2l+1 m each (4096 channels), "
+                               "complex64 data, FP64-built plan", "channels": len(w.channels), "N": 2048,
+                   "points": pts, "parallelism": "single GPU"},
+        "transforms_per_s": 2 * len(w.channels) / (ms_step * 1e-3),
+        "max_rel_err_vs_oracle": worst, "roundtrip_max_rel": rt,
+        "roofline": roof,
+    }
+    if not args.no_plain:
+        pplan = Plan(w.channels, mode="plain")
+        pplan.forward(x, b)
+        pplan.inverse(b, y)
+        torch.cuda.synchronize()
+        reps = 2
+        e0.record(stream)
+        for _ in range(reps):
+            pplan.forward(x, b)
+            pplan.inverse(b, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / reps
+        out["plain_gpu_form"] = {"value": pts / (pms * 1e-3), "ms_per_step": pms,
+                                 "form": "one launch per channel and stage (4 launches per channel per step)"}
+        out["speedup_vs_plain"] = out["value"] / out["plain_gpu_form"]["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,17 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
 dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
                              const void* lam_t, const void* lam_t1, double* out, void* stream);
 
+/* Stage timing.  With profiling enabled, every stage launch made by
+ * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is
+ * bracketed by HIP events recorded on the launch stream.  enable != 0 clears
+ * the accumulators; enable == 0 stops recording.  Adds two event records per
+ * launch. */
+dsbt_status dsbt_profile_enable(dsbt_plan p, int32_t enable);
+enum { DSBT_STAGE_SINCOS = 0, DSBT_STAGE_MOMENT = 1, DSBT_NUM_STAGES = 2 };
+/* Synchronises on the recorded events and returns, per stage (index as above,
+ * nstages <= DSBT_NUM_STAGES), the summed milliseconds and the launch count. */
+dsbt_status dsbt_profile_read(dsbt_plan p, double* ms, int64_t* launches, int32_t nstages);
+
 /* Host FP64 moment tables of one (N, l, B) for testing the plan without a GPU.
  * Writes R*R*NT doubles, R = B + ceil(l/2), NT = N/B: block J (row-major,
  * M[r][q]) maps [g_J ; mu_J] to [b_J ; mu_{J+1}] for the tile of slots

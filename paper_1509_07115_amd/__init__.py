@@ -155,6 +155,17 @@ class Plan:
                                               _stream_handle(stream)), "dsbt_step_grad_s")
         return out
 
+    def profile(self, enable: bool = True):
+        """Start (clearing) or stop per-stage HIP-event timing (``dsbt_profile_enable``)."""
+        _lib.check(self._lib.dsbt_profile_enable(self._h, 1 if enable else 0), "dsbt_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage: (milliseconds summed, launches)} for "sincos" and "moment" (``dsbt_profile_read``)."""
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int64 * 2)()
+        _lib.check(self._lib.dsbt_profile_read(self._h, ms, n, 2), "dsbt_profile_read")
+        return {"sincos": (ms[0], n[0]), "moment": (ms[1], n[1])}
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.dsbt_plan_destroy(self._h)

@@ -23,7 +23,8 @@ STATUS_NAMES = {
 EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_kinetic_step",
-    "dsbt_step_grad_s", "dsbt_host_ftb_tables", "dsbt_status_string", "dsbt_last_error",
+    "dsbt_step_grad_s", "dsbt_profile_enable", "dsbt_profile_read", "dsbt_host_ftb_tables",
+    "dsbt_status_string", "dsbt_last_error",
 ]
 
 
@@ -70,6 +71,8 @@ def load() -> ctypes.CDLL:
         "dsbt_set_potential": (i32, [P, ctypes.POINTER(dbl), dbl]),
         "dsbt_kinetic_step": (i32, [P, P, i32, P, i32, P]),
         "dsbt_step_grad_s": (i32, [P, P, P, P, P, P, P]),
+        "dsbt_profile_enable": (i32, [P, i32]),
+        "dsbt_profile_read": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "dsbt_host_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),

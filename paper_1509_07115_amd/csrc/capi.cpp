@@ -125,6 +125,21 @@ struct dsbt_plan_s {
     double* d_vangle = nullptr;
     double* d_scratch = nullptr;
 
+    // stage timing (dsbt_profile_enable)
+    bool profiling = false;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_events;   // (stage, start, stop)
+    std::vector<hipEvent_t> event_pool;
+    hipEvent_t take_event() {
+        hipEvent_t e = nullptr;
+        if (!event_pool.empty()) {
+            e = event_pool.back();
+            event_pool.pop_back();
+        } else {
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+        }
+        return e;
+    }
+
     // graph cache for dsbt_kinetic_step
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -146,6 +161,13 @@ struct dsbt_plan_s {
         graph = nullptr;
         for (void* p : allocs) (void)hipFree(p);
         allocs.clear();
+        for (auto& t : prof_events) {
+            (void)hipEventDestroy(std::get<1>(t));
+            (void)hipEventDestroy(std::get<2>(t));
+        }
+        prof_events.clear();
+        for (auto e : event_pool) (void)hipEventDestroy(e);
+        event_pool.clear();
     }
 };
 
@@ -414,24 +436,45 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
 }
 
+// Runs `launch` between two recorded events when profiling is on.
+template <typename F>
+void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (!P->profiling || hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        launch();
+        return;
+    }
+    hipEvent_t a = P->take_event(), b = P->take_event();
+    hip_check(hipEventRecord(a, s), "hipEventRecord");
+    launch();
+    hip_check(hipEventRecord(b, s), "hipEventRecord");
+    P->prof_events.emplace_back(stage, a, b);
+}
+
 template <typename T>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
     if (P->d_items_mf)
-        hip_check(dsbt::launch_mstage_mfma(P->d_items_mf, (int)P->h_items_mf.size(), P->mf_waves, P->mf_lds, src, dst,
-                                           inverse, ph, s), "mstage_mfma");
+        timed(P, DSBT_STAGE_MOMENT, s, [&] {
+            hip_check(dsbt::launch_mstage_mfma(P->d_items_mf, (int)P->h_items_mf.size(), P->mf_waves, P->mf_lds, src,
+                                               dst, inverse, ph, s), "mstage_mfma");
+        });
     if (P->d_items_v1)
-        hip_check(dsbt::launch_mstage<T>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph, s),
-                  "mstage");
+        timed(P, DSBT_STAGE_MOMENT, s, [&] {
+            hip_check(dsbt::launch_mstage<T>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph,
+                                             s), "mstage");
+        });
 }
 
 template <typename T>
 void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool inverse, hipStream_t s,
                         dsbt::PhaseArgs ph) {
-    if (P->items1_mf[c])
-        hip_check(dsbt::launch_mstage_mfma(P->d_items1 + c, 1, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s),
-                  "mstage_mfma");
-    else
-        hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
+    timed(P, DSBT_STAGE_MOMENT, s, [&] {
+        if (P->items1_mf[c])
+            hip_check(dsbt::launch_mstage_mfma(P->d_items1 + c, 1, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s),
+                      "mstage_mfma");
+        else
+            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
+    });
 }
 
 template <typename T>
@@ -440,14 +483,18 @@ void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
     const int nch = (int)P->ch.size();
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
-            hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, src, dst, false, pv, s), "fstage");
+            timed(P, DSBT_STAGE_SINCOS, s, [&] {
+                hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, src, dst, false, pv, s), "fstage");
+            });
             enqueue_mstage_one<T>(P, c, dst, dst, false, s, pk);
         }
         return;
     }
     for (auto& r : P->n_ranges)
-        hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src, dst,
-                                           false, pv, s), "fstage");
+        timed(P, DSBT_STAGE_SINCOS, s, [&] {
+            hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src,
+                                               dst, false, pv, s), "fstage");
+        });
     enqueue_mstage<T>(P, dst, dst, false, s, pk);
 }
 
@@ -458,14 +505,18 @@ void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
             enqueue_mstage_one<T>(P, c, src, dst, true, s, none);
-            hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
+            timed(P, DSBT_STAGE_SINCOS, s, [&] {
+                hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
+            });
         }
         return;
     }
     enqueue_mstage<T>(P, src, dst, true, s, none);
     for (auto& r : P->n_ranges)
-        hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst, dst,
-                                           true, pv, s), "fstage");
+        timed(P, DSBT_STAGE_SINCOS, s, [&] {
+            hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst,
+                                               dst, true, pv, s), "fstage");
+        });
 }
 
 template <typename T>
@@ -738,6 +789,43 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
         else
             hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
                                                  st), "grad_s");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_profile_enable(dsbt_plan p, int32_t enable) {
+    if (!p) return fail(DSBT_ERR_INVALID_ARG, "plan is NULL");
+    return guarded([&]() -> dsbt_status {
+        if (enable) {
+            for (auto& t : p->prof_events) {
+                p->event_pool.push_back(std::get<1>(t));
+                p->event_pool.push_back(std::get<2>(t));
+            }
+            p->prof_events.clear();
+        }
+        p->profiling = enable != 0;
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_profile_read(dsbt_plan p, double* ms, int64_t* launches, int32_t nstages) {
+    if (!p || !ms || !launches || nstages < 0 || nstages > DSBT_NUM_STAGES)
+        return fail(DSBT_ERR_INVALID_ARG, "bad profile arguments");
+    return guarded([&]() -> dsbt_status {
+        for (int i = 0; i < nstages; ++i) {
+            ms[i] = 0.0;
+            launches[i] = 0;
+        }
+        for (auto& t : p->prof_events) {
+            const int st = std::get<0>(t);
+            hip_check(hipEventSynchronize(std::get<2>(t)), "hipEventSynchronize");
+            float e = 0.0f;
+            hip_check(hipEventElapsedTime(&e, std::get<1>(t), std::get<2>(t)), "hipEventElapsedTime");
+            if (st < nstages) {
+                ms[st] += e;
+                launches[st] += 1;
+            }
+        }
         return DSBT_OK;
     });
 }
