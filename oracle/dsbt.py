@@ -147,6 +147,7 @@ def dlop(ell: int, M: int, xmax: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 @functools.lru_cache(maxsize=64)
+@functools.lru_cache(maxsize=16)
 def fourier_matrix(N: int, ell: int, sign: bool = True) -> np.ndarray:
     """F[j, i], row j = n - p_l (n = p_l..N_l), column i = 0..N-1 (r_{i+1}).
 
@@ -214,13 +215,21 @@ def dsbt_matrix(N: int, ell: int, sign: bool = True) -> np.ndarray:
 # transforms
 # ---------------------------------------------------------------------------
 
+def _apply(M: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """M x for a real matrix M: complex x is transformed linearly, real and
+    imaginary parts separately (the same products as a complex product)."""
+    if np.iscomplexobj(x):
+        return (M @ x.real) + 1j * (M @ x.imag)
+    return M @ x
+
+
 def forward(psi: np.ndarray, ell: int, sign: bool = True) -> np.ndarray:
     """b = T (F psi) for psi of shape (N,) or (N, C); complex or real, FP64."""
     N = psi.shape[0]
-    return ftb_matrix(N, ell) @ (fourier_matrix(N, ell, sign) @ psi)
+    return _apply(ftb_matrix(N, ell), _apply(fourier_matrix(N, ell, sign), psi))
 
 
 def inverse(b: np.ndarray, ell: int, sign: bool = True) -> np.ndarray:
     """psi = F^T (T^T b): the inverse because both factors are orthogonal."""
     N = b.shape[0]
-    return fourier_matrix(N, ell, sign).T @ (ftb_matrix(N, ell).T @ b)
+    return _apply(fourier_matrix(N, ell, sign).T, _apply(ftb_matrix(N, ell).T, b))

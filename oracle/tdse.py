@@ -27,7 +27,7 @@ import numpy as np
 from . import dsbt
 from .sbf import corrected_momenta
 
-__all__ = ["kinetic_energies", "hamiltonian", "step", "propagate", "loss_and_grad"]
+__all__ = ["kinetic_energies", "hamiltonian", "step", "propagate", "loss_and_grad", "loss_and_grad_blocks"]
 
 
 def kinetic_energies(N: int, rmax: float, ell: int, corrected: bool = False) -> np.ndarray:
@@ -94,3 +94,27 @@ def loss_and_grad(psi0: np.ndarray, phi: np.ndarray, ell: int, V: np.ndarray, E:
         acc = np.conj(lam_next) * states[t + 1] + np.conj(lam) * states[t]
         gs[t] = 0.5 * dt * float(np.sum(Vb * acc.imag))
     return L, lam, gs
+
+
+def loss_and_grad_blocks(blocks, dt: float, s: np.ndarray):
+    """L = |<phi|psi_T>|^2 over several channel blocks and its gradients.
+
+    blocks: list of (ell, V, E, psi0, phi) with psi0, phi of shape (N,) or (N, C)
+    (channels of one l).  The overlap z sums over every block, so the adjoint
+    of each block starts from 2 z phi.  Returns (L, [grad psi0 per block], grad s).
+    """
+    states = [propagate(p0, ell, V, E, dt, s, keep=True) for ell, V, E, p0, _ in blocks]
+    z = sum(np.vdot(b[4], st[-1]) for b, st in zip(blocks, states))
+    L = float(abs(z) ** 2)
+    gs = np.zeros(len(s))
+    grads = []
+    for (ell, V, E, p0, phi), st in zip(blocks, states):
+        lam = 2.0 * z * np.asarray(phi, dtype=np.complex128)
+        Vb = V[:, None] if np.ndim(p0) == 2 else V
+        for t in range(len(s) - 1, -1, -1):
+            lam_next = lam
+            lam = step(lam_next, ell, V, E, dt, s[t], adjoint=True)
+            acc = np.conj(lam_next) * st[t + 1] + np.conj(lam) * st[t]
+            gs[t] += 0.5 * dt * float(np.sum(Vb * acc.imag))
+        grads.append(lam)
+    return L, grads, gs

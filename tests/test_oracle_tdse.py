@@ -126,3 +126,40 @@ def test_adjoint_matches_finite_differences():
         # PyTorch convention: dL = Re(<grad, d psi>)
         assert abs(fd - np.real(np.vdot(gpsi, d))) < 1e-7 * max(1.0, abs(fd))
     assert 0.0 <= L <= 1.0
+
+
+def test_block_adjoint_reduces_to_single_and_matches_fd():
+    # one block: the same as loss_and_grad; two blocks (l = 2 and l = 3, shared
+    # overlap z): central finite differences on s and on psi0
+    rng = np.random.default_rng(21)
+    dt, s = 0.05, rng.uniform(0.9, 1.1, size=4)
+    blocks = []
+    for ell, N in ((2, 32), (3, 32)):
+        V, E, psi0 = _setup(N=N, rmax=8.0, ell=ell, seed=ell)
+        phi = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        blocks.append((ell, V, E, psi0, phi / 2.0))
+    L1, g1, s1 = tdse.loss_and_grad_blocks(blocks[:1], dt, s)
+    L0, gp0, gs0 = tdse.loss_and_grad(blocks[0][3], blocks[0][4], 2, blocks[0][1], blocks[0][2], dt, s)
+    assert abs(L1 - L0) < 1e-15 and np.max(np.abs(g1[0] - gp0)) < 1e-15 and np.max(np.abs(s1 - gs0)) < 1e-15
+
+    L, gp, gs = tdse.loss_and_grad_blocks(blocks, dt, s)
+
+    def loss(ps, ss):
+        z = sum(np.vdot(b[4], tdse.propagate(p, b[0], b[1], b[2], dt, ss)) for b, p in zip(blocks, ps))
+        return abs(z) ** 2
+
+    base = [b[3] for b in blocks]
+    h = 1e-6
+    for t in range(len(s)):
+        sp, sm = s.copy(), s.copy()
+        sp[t] += h
+        sm[t] -= h
+        fd = (loss(base, sp) - loss(base, sm)) / (2 * h)
+        assert abs(fd - gs[t]) < 1e-7 * max(1.0, abs(fd))
+    for k in range(2):
+        d = rng.standard_normal(32) + 1j * rng.standard_normal(32)
+        pp, pm = list(base), list(base)
+        pp[k] = base[k] + h * d
+        pm[k] = base[k] - h * d
+        fd = (loss(pp, s) - loss(pm, s)) / (2 * h)
+        assert abs(fd - np.real(np.vdot(gp[k], d))) < 1e-7 * max(1.0, abs(fd))
