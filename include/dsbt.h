@@ -136,7 +136,9 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt);
 
 enum {
     DSBT_STEP_ADJOINT = 1,   /* apply U^H (conjugated phases), steps in reverse order */
-    DSBT_STEP_GRAPH = 2,     /* capture the nsteps launches once in a hipGraph and replay it */
+    DSBT_STEP_GRAPH = 2,     /* capture the nsteps launches once in a hipGraph and replay it; the
+                                strengths are first copied (on `stream`) into a plan buffer the graph
+                                reads, so only a new psi, nsteps or flags value captures again */
     DSBT_STEP_RESIDENT = 4   /* one launch that keeps each channel in LDS for all steps */
 };
 

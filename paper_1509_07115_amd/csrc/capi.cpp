@@ -51,12 +51,11 @@ int ilog2(int n) {
     return l;
 }
 
-// Phase factor exp(-i a) rounded to FP32 with |z| as close to one as the four
-// neighbouring roundings allow (keeps the step unitary to FP32 rounding).
-float2 unit_phase(double a) {
-    const double twopi = 6.283185307179586476925286766559;
-    a -= twopi * std::nearbyint(a / twopi);
-    const double c = std::cos(a), s = -std::sin(a);
+// A unit complex number (c, s) rounded to FP32 with |z| as close to one as the
+// neighbouring roundings allow.  Rounding cos and sin separately leaves
+// |z|^2 - 1 of the order of the FP32 epsilon with a fixed sign per table
+// entry, which repeated steps would accumulate into a norm drift.
+float2 unit_pair(double c, double s) {
     const float c0 = (float)c, s0 = (float)s;
     float best_c = c0, best_s = s0;
     double best = 1e300;
@@ -79,6 +78,32 @@ float2 unit_phase(double a) {
     return make_float2(best_c, best_s);
 }
 
+// Phase factor exp(-i a), the angle reduced mod 2 pi in FP64.
+float2 unit_phase(double a) {
+    const double twopi = 6.283185307179586476925286766559;
+    a -= twopi * std::nearbyint(a / twopi);
+    return unit_pair(std::cos(a), -std::sin(a));
+}
+
+
+// exp(-i a) for every angle a, reduced mod 2 pi in FP64: FP64 pairs for
+// complex128 plans, the nearest unit-modulus FP32 pairs for complex64 plans.
+std::vector<unsigned char> phase_table(const std::vector<double>& ang, bool fp64) {
+    const double twopi = 6.283185307179586476925286766559;
+    std::vector<unsigned char> out(ang.size() * (fp64 ? sizeof(double2) : sizeof(float2)));
+    for (size_t i = 0; i < ang.size(); ++i) {
+        if (fp64) {
+            const double a = ang[i] - twopi * std::nearbyint(ang[i] / twopi);
+            const double2 z = make_double2(std::cos(a), -std::sin(a));
+            std::memcpy(out.data() + i * sizeof(double2), &z, sizeof(z));
+        } else {
+            const float2 z = unit_phase(ang[i]);
+            std::memcpy(out.data() + i * sizeof(float2), &z, sizeof(z));
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 struct dsbt_plan_s {
@@ -95,7 +120,7 @@ struct dsbt_plan_s {
         int N, ell, p, k, B, R, NT;
         double rmax;
         std::vector<int> chans;
-        float2* d_kphase = nullptr;  // per slot, after set_potential
+        void* d_kphase = nullptr;    // per slot (complex of the data precision), after set_potential
     };
     std::vector<Group> groups;
 
@@ -121,7 +146,7 @@ struct dsbt_plan_s {
     // potential
     bool has_potential = false;
     double dt = 0.0;
-    float2* d_vphase = nullptr;
+    void* d_vphase = nullptr;     // complex of the data precision
     double* d_vangle = nullptr;
     double* d_scratch = nullptr;
 
@@ -144,6 +169,8 @@ struct dsbt_plan_s {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     std::tuple<void*, int, const float*, int> graph_key{nullptr, 0, nullptr, 0};
+    float* d_sgraph = nullptr;    // strengths staged for graph replays
+    int sgraph_cap = 0;
 
     void* dalloc(size_t bytes) {
         void* p = nullptr;
@@ -172,6 +199,26 @@ struct dsbt_plan_s {
 };
 
 namespace {
+
+// Complex table (re, im pairs) of unit numbers in the data precision.
+template <typename T>
+void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s) {
+    std::vector<T> h(v.size());
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+        if constexpr (sizeof(T) == sizeof(float)) {
+            const float2 z = unit_pair(v[i], v[i + 1]);
+            h[i] = z.x;
+            h[i + 1] = z.y;
+        } else {
+            h[i] = v[i];
+            h[i + 1] = v[i + 1];
+        }
+    }
+    void* d = P->dalloc(h.size() * sizeof(T));
+    hip_check(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+    return d;
+}
 
 template <typename T>
 void* upload_converted(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s) {
@@ -290,7 +337,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         if (twd.count(g.N)) continue;
         std::vector<double> tw, post;
         dsbt::fft_twiddles(g.N, tw, post);
-        twd[g.N] = {upload_converted<T>(P, tw, s), upload_converted<T>(P, post, s)};
+        twd[g.N] = {upload_unit_table<T>(P, tw, s), upload_unit_table<T>(P, post, s)};
     }
     // channel descriptors
     P->h_fchans.resize(nch);
@@ -429,9 +476,8 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     P->d_items_v1 = upload_items(P->h_items_v1);
     P->d_items1 = upload_items(P->h_items1);
     P->d_scratch = (double*)P->dalloc(sizeof(double) * (nch + 1));
-    const size_t f_lds = P->elem_bytes * (size_t)P->maxN;
     const size_t m_lds = P->elem_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
-    hip_check(dsbt::set_lds_limits<T>(f_lds, m_lds), "set LDS limits");
+    hip_check(dsbt::set_lds_limits<T>(m_lds), "set LDS limits");
     hip_check(dsbt::set_lds_limits_mfma(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
 }
@@ -662,44 +708,45 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DSBT_ERR_INVALID_ARG, "dt must be positive");
     return guarded([&]() -> dsbt_status {
         const int64_t n = p->elems;
-        std::vector<float2> ph(n, make_float2(1.0f, 0.0f));
+        const bool fp64 = p->precision == DSBT_C128;
         std::vector<double> ang(n, 0.0);
         for (auto& x : p->ch) {
             for (int i = 0; i < x.N; ++i) {
                 const double v = V[x.offset + i];
                 if (!std::isfinite(v)) throw StatusError(DSBT_ERR_INVALID_ARG, "non-finite potential");
                 ang[x.offset + i] = v * dt / 2.0;
-                ph[x.offset + i] = unit_phase(v * dt / 2.0);
             }
         }
+        const std::vector<unsigned char> ph = phase_table(ang, fp64);
         if (!p->d_vphase) {
-            p->d_vphase = (float2*)p->dalloc(sizeof(float2) * n);
+            p->d_vphase = p->dalloc(ph.size());
             p->d_vangle = (double*)p->dalloc(sizeof(double) * n);
         }
-        hip_check(hipMemcpy(p->d_vphase, ph.data(), sizeof(float2) * n, hipMemcpyHostToDevice), "vphase");
+        hip_check(hipMemcpy(p->d_vphase, ph.data(), ph.size(), hipMemcpyHostToDevice), "vphase");
         hip_check(hipMemcpy(p->d_vangle, ang.data(), sizeof(double) * n, hipMemcpyHostToDevice), "vangle");
         // kinetic phases per group: K = (n dk)^2/2 for regular rows, (N dk)^2/2 for completion rows
         const double pi = 3.14159265358979323846;
         for (auto& g : p->groups) {
             const double dk = pi / g.rmax;
-            std::vector<float2> kp(g.N);
+            std::vector<double> ka(g.N);
             for (int j = 0; j < g.N; ++j) {
                 const int nidx = j + g.p;
                 const double kn = (j < g.k) ? g.N * dk : nidx * dk;
-                kp[j] = unit_phase(0.5 * kn * kn * dt);
+                ka[j] = 0.5 * kn * kn * dt;
             }
-            if (!g.d_kphase) g.d_kphase = (float2*)p->dalloc(sizeof(float2) * g.N);
-            hip_check(hipMemcpy(g.d_kphase, kp.data(), sizeof(float2) * g.N, hipMemcpyHostToDevice), "kphase");
+            const std::vector<unsigned char> kp = phase_table(ka, fp64);
+            if (!g.d_kphase) g.d_kphase = p->dalloc(kp.size());
+            hip_check(hipMemcpy(g.d_kphase, kp.data(), kp.size(), hipMemcpyHostToDevice), "kphase");
         }
         // refresh descriptors with the phase pointers
         for (size_t c = 0; c < p->ch.size(); ++c) {
-            p->h_fchans[c].vphase = p->d_vphase + p->ch[c].offset;
+            p->h_fchans[c].vphase = static_cast<const unsigned char*>(p->d_vphase) + p->elem_bytes * p->ch[c].offset;
             p->h_fchans[c].vangle = p->d_vangle + p->ch[c].offset;
         }
         hip_check(hipMemcpy(p->d_fchans, p->h_fchans.data(), sizeof(dsbt::FChan) * p->ch.size(),
                             hipMemcpyHostToDevice), "fchans");
         upload_fchans_n(p);
-        std::map<int64_t, float2*> by_off;
+        std::map<int64_t, void*> by_off;
         for (auto& g : p->groups)
             for (int c : g.chans) by_off[p->ch[c].offset] = g.d_kphase;
         auto refresh = [&](std::vector<dsbt::MItem>& v, dsbt::MItem* d) {
@@ -742,6 +789,17 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
         if (!(flags & DSBT_STEP_GRAPH)) {
             enqueue(st);
             return DSBT_OK;
+        }
+        // The strengths are staged into a plan buffer that the graph reads, so a
+        // replay with other strengths (same psi, nsteps, flags) reuses the graph.
+        if (s) {
+            if (p->sgraph_cap < nsteps) {
+                p->d_sgraph = static_cast<float*>(p->dalloc(sizeof(float) * (size_t)nsteps));
+                p->sgraph_cap = nsteps;
+            }
+            hip_check(hipMemcpyAsync(p->d_sgraph, s, sizeof(float) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
+                      "stage strengths");
+            s = p->d_sgraph;
         }
         auto key = std::make_tuple(psi, (int)nsteps, s, (int)flags);
         if (!p->graph_exec || p->graph_key != key) {

@@ -12,8 +12,8 @@
 // Layout: a block handles CPB channels of N points with N/8 threads each; each
 // thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
 // pass for the remaining factor), data stay in LDS with one pad slot per 32
-// complex values.  Twiddles: one load per butterfly from the FP64-built table
-// exp(-2 pi i t/N), its powers by complex multiplication.
+// complex values.  Twiddles: every power read from the FP64-built table
+// exp(-2 pi i t/N), whose FP32 entries are the unit-modulus roundings.
 #include "kernels.h"
 
 namespace dsbt {
@@ -28,6 +28,27 @@ template <typename V> __device__ __forceinline__ V f_mul(V a, V b) {
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 template <typename V, typename S> __device__ __forceinline__ V f_scale(V a, S s) { return {a.x * s, a.y * s}; }
+
+// Multiplication by a constant c = hi + lo that is not representable in FP32
+// (sqrt(1/2), sqrt(2/N) for even log2 N): a x hi + x lo.  A product with the
+// rounded constant alone scales every value by the same relative error, which
+// repeated transforms would accumulate into a norm drift; the split product
+// leaves only the final rounding.  FP64 data use hi alone (lo = 0).
+template <typename T> struct Split {
+    T hi, lo;
+};
+template <typename T>
+__device__ __forceinline__ Split<T> split_const(double c) {
+    const T hi = (T)c;
+    return {hi, (T)(c - (double)hi)};
+}
+template <typename T>
+__device__ __forceinline__ T s_mul(T x, Split<T> c) {
+    if constexpr (sizeof(T) == sizeof(float)) return __builtin_fmaf(x, c.lo, x * c.hi);
+    else return x * c.hi;
+}
+template <typename V, typename T>
+__device__ __forceinline__ V f_scale(V a, Split<T> c) { return {s_mul(a.x, c), s_mul(a.y, c)}; }
 template <typename V> __device__ __forceinline__ V f_negi(V a) { return {a.y, -a.x}; }   // -i a
 template <typename V> __device__ __forceinline__ V f_posi(V a) { return {-a.y, a.x}; }   // +i a
 
@@ -55,10 +76,11 @@ __device__ __forceinline__ void dft8(V* v) {
     V e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
     dft4<T>(e);
     dft4<T>(o);
-    const T h = (T)0.70710678118654752440;
-    const V o1 = {(o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h};   // o1 * exp(-i pi/4)
-    const V o2 = f_negi(o[2]);                                     // o2 * exp(-i pi/2)
-    const V o3 = {(o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h};  // o3 * exp(-3 i pi/4)
+    constexpr double hd = 0.70710678118654752440;
+    constexpr Split<T> h{(T)hd, (T)(hd - (double)(T)hd)};
+    const V o1 = {s_mul(o[1].x + o[1].y, h), s_mul(o[1].y - o[1].x, h)};   // o1 * exp(-i pi/4)
+    const V o2 = f_negi(o[2]);                                             // o2 * exp(-i pi/2)
+    const V o3 = {s_mul(o[3].y - o[3].x, h), -s_mul(o[3].x + o[3].y, h)};  // o3 * exp(-3 i pi/4)
     v[0] = f_add(e[0], o[0]);
     v[4] = f_sub(e[0], o[0]);
     v[1] = f_add(e[1], o1);
@@ -83,13 +105,12 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
         for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(j + r * NR)];
         const int jm = j & (Ns - 1);
         if (Ns > 1) {
-            const V w = tw[jm * (N / (Ns * R))];
-            V wr = w;
+            // w^r read from the table: powers formed by repeated FP32 products
+            // carry a magnitude bias of the order of the FP32 epsilon that is
+            // the same for every butterfly of a pass with few distinct w
+            const int st = jm * (N / (Ns * R));
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                v[u][r] = f_mul(v[u][r], wr);
-                if (r + 1 < R) wr = f_mul(wr, w);
-            }
+            for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], tw[r * st]);
         }
         if constexpr (R == 8) dft8<T>(v[u]);
         else if constexpr (R == 4) dft4<T>(v[u]);
@@ -127,7 +148,7 @@ template <>
 __device__ __forceinline__ float2 phase_factor<float2>(const FChan& c, int i, const PhaseArgs& ph) {
     float2 z;
     if (ph.scale == nullptr) {
-        z = c.vphase[i];
+        z = static_cast<const float2*>(c.vphase)[i];
     } else {
         double a = (double)ph.scale[ph.step] * c.vangle[i];
         const double twopi = 6.283185307179586476925286766559;
@@ -143,7 +164,7 @@ template <>
 __device__ __forceinline__ double2 phase_factor<double2>(const FChan& c, int i, const PhaseArgs& ph) {
     double2 z;
     if (ph.scale == nullptr) {
-        z = make_double2((double)c.vphase[i].x, (double)c.vphase[i].y);
+        z = static_cast<const double2*>(c.vphase)[i];
     } else {
         double a = (double)ph.scale[ph.step] * c.vangle[i];
         const double twopi = 6.283185307179586476925286766559;
@@ -174,7 +195,9 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     const FChan c = chans[live ? cidx : nch - 1];
     const V* tw = reinterpret_cast<const V*>(c.tw);
     const V* post = reinterpret_cast<const V*>(c.post);
-    const T s0 = (T)c.sign * sqrt((T)1 / (T)N), s1 = (T)c.sign * sqrt((T)2 / (T)N);
+    // orthonormal scales sqrt(1/N) (k = 0) and sqrt(2/N), with the sign, in FP64
+    const double d0 = (double)c.sign * sqrt(1.0 / N), d1 = (double)c.sign * sqrt(2.0 / N);
+    const Split<T> sc0 = split_const<T>(INV ? d0 : 0.5 * d0), sc1 = split_const<T>(INV ? d1 : 0.5 * d1);
     if constexpr (!INV) {
         if (live) {
             const V* x = src + c.off;
@@ -198,7 +221,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
                 // w a + conj(w) b
                 V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
-                X = f_scale(X, (T)0.5 * (k == 0 ? s0 : s1));
+                X = f_scale(X, k == 0 ? sc0 : sc1);
                 y[c.p ? (N - 1 - k) : k] = X;
             }
         }
@@ -209,7 +232,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
             for (int u = 0; u < 8; ++u) {
                 const int j = t + u * TPC;
                 const int k = c.p ? (N - 1 - j) : j;
-                buf[pidx(k)] = f_scale(f[j], k == 0 ? s0 : s1);
+                buf[pidx(k)] = f_scale(f[j], k == 0 ? sc0 : sc1);
             }
         }
         lds_barrier();

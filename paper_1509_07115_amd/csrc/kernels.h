@@ -16,7 +16,7 @@ struct FChan {
     float sign;           // (-1)^ceil(l/2), or +1 for the printed F
     const void* tw;       // exp(-2 pi i t/N), t < N, complex of the data precision
     const void* post;     // exp(-i pi t/(2N)), t < N
-    const float2* vphase; // unit-modulus exp(-i V tau/2) per point, or nullptr
+    const void* vphase;   // unit-modulus exp(-i V tau/2) per point (complex of the data precision), or nullptr
     const double* vangle; // V tau/2 per point (FP64), or nullptr
 };
 
@@ -27,7 +27,7 @@ struct MItem {
     const void* tab_i;     // NT blocks, A[q][r] = M_J[q][r]
     const float* mf_f;     // MFMA operand layout of the forward blocks (FP32 plans), or nullptr
     const float* mf_i;     // MFMA operand layout of the inverse blocks
-    const float2* kphase;  // unit-modulus exp(-i K_n tau) per slot, or nullptr
+    const void* kphase;    // unit-modulus exp(-i K_n tau) per slot (complex of the data precision), or nullptr
     int B, k, R, NT, p, nch;
     int NB;                // 16-row blocks of the padded block size R16 = 16 NB (1, 2, 4 or 8)
     int NCB;               // 8-channel column blocks of the item (mfma_ncb on the matrix-core path)
@@ -52,7 +52,7 @@ struct PhaseArgs {
 // Raise the dynamic-LDS limit of the transform kernels (call before launching
 // or capturing; not a stream operation).
 template <typename T>
-hipError_t set_lds_limits(size_t fstage_bytes, size_t mstage_bytes);
+hipError_t set_lds_limits(size_t mstage_bytes);
 
 // Pointers read from descriptor structs are generic (flat) to the compiler;
 // flat loads also count against the LDS counter, so an LDS wait would drain
@@ -78,9 +78,6 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Launchers.  T = float (complex64 data) or double (complex128 data).
-template <typename T>
-hipError_t launch_fstage(const FChan* d_chans, int nch, int maxN, const void* src, void* dst,
-                         bool inverse, PhaseArgs ph, hipStream_t s);
 
 // Sine/cosine stage for channels that all have N points (compile-time FFT size).
 template <typename T>

@@ -18,6 +18,9 @@ Workloads (all inputs FP64 on the host, in channel order):
 * ``tdse``               N = 4096, rmax = 200, l = 0..31 with all m (1024 channels):
   r exp(-r) in (0, 0) plus Gaussian sums of norm 1e-3 elsewhere, total norm 1;
   V = -1/sqrt(r^2 + 0.01) + l(l+1)/(2 r^2).
+* ``adjoint``            N = 2048, rmax = 100, l = 0..15 with all m (256 channels),
+  psi0 and V as in ``tdse``; 200 strengths s_t ~ U[0.9, 1.1], dt = 0.01, and a
+  target phi with N(0,1) + i N(0,1) entries, norm 1 (loss |<phi|psi_T>|^2).
 """
 from __future__ import annotations
 
@@ -27,7 +30,8 @@ from typing import List, Tuple
 
 import numpy as np
 
-__all__ = ["Workload", "gaussian_orbitals", "batched_all_m", "uneven", "tdse", "grid", "gaussian_sum"]
+__all__ = ["Workload", "gaussian_orbitals", "batched_all_m", "uneven", "tdse", "adjoint", "grid",
+           "gaussian_sum"]
 
 
 @dataclass
@@ -129,3 +133,15 @@ def tdse(seed: int = 4, N: int = 4096, rmax: float = 200.0, lmax: int = 31, dt: 
     psi /= np.linalg.norm(psi)
     return Workload(f"split step N={N} rmax={rmax} lmax={lmax} ({len(channels)} channels)", channels, psi,
                     {"V": np.concatenate(Vs), "dt": dt})
+
+
+def adjoint(seed: int = 5, N: int = 2048, rmax: float = 100.0, lmax: int = 15, nsteps: int = 200,
+            dt: float = 0.01) -> Workload:
+    w = tdse(seed=seed, N=N, rmax=rmax, lmax=lmax, dt=dt)
+    rng = np.random.default_rng(seed + 1000)
+    s = rng.uniform(0.9, 1.1, nsteps)
+    phi = rng.standard_normal(w.elems) + 1j * rng.standard_normal(w.elems)
+    phi /= np.linalg.norm(phi)
+    w.name = f"adjoint N={N} rmax={rmax} lmax={lmax} ({len(w.channels)} channels, {nsteps} steps)"
+    w.extra.update({"s": s, "phi": phi})
+    return w
