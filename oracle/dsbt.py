@@ -219,7 +219,10 @@ def _apply(M: np.ndarray, x: np.ndarray) -> np.ndarray:
     """M x for a real matrix M: complex x is transformed linearly, real and
     imaginary parts separately (the same products as a complex product)."""
     if np.iscomplexobj(x):
-        return (M @ x.real) + 1j * (M @ x.imag)
+        # interleaved (re, im) columns of a contiguous complex128 array
+        xc = np.ascontiguousarray(x, dtype=np.complex128)
+        cols = xc.view(np.float64).reshape(x.shape[0], -1)
+        return np.ascontiguousarray(M @ cols).view(np.complex128).reshape(x.shape)
     return M @ x
 
 
