@@ -20,20 +20,74 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3, "valu_fp32_TFLOPs_nonpacked": 78.6}
+PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3}
+
+# HBM traffic of one moment-stage launch (forward and inverse averaged) on this
+# workload, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this
+# script, each scaled by what the same counter reads for a device copy of known
+# size (--copy-calibration).  The record holds the SHA-256 of the kernel's
+# sources at the time of the measurement; after any change to them the figure
+# no longer applies and the roofline reports traffic as null.
+MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_mfma.hip", "paper_1509_07115_amd/csrc/kernels.h"],
+                  "sha256": None, "fetch_bytes": None, "write_bytes": None}
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def algorithmic_counts(channels):
-    """Per launch of each stage, from the per-point operation model of the method:
-    sine/cosine stage 5 log2 N + 8 flops, moment stage 12 ceil(l/2) flops,
-    each stage reading and writing 8 bytes per point (complex64)."""
+    """Per launch of each stage, from the operation model of the method.
+
+    Points: sum of N.  Flops per point: 5 log2 N + 8 for the sine/cosine stage
+    (an N-point complex FFT plus the pre/post steps), 12 ceil(l/2) for the
+    moment stage (a complex x real update, contraction and completion row per
+    moment).  Bytes: 16 per point for each stage (complex64 in and out) plus
+    the tables once per launch: for the moment stage the minimal state
+    ceil(l/2) + 1 FP32 words per row for each distinct l (up to its largest N)
+    and ceil(l/2) N words of completion rows per distinct (l, N); for the
+    sine/cosine stage two complex64 tables of N entries per distinct N.
+    """
     pts = sum(N for N, _, _, _ in channels)
     f_sincos = sum(N * (5 * math.log2(N) + 8) for N, _, _, _ in channels)
     f_moment = sum(N * 12 * ((l + 1) // 2) for N, l, _, _ in channels)
-    return pts, f_sincos, f_moment, 16.0 * pts
+    maxn_l, pairs, ns = {}, set(), set()
+    for N, l, _, _ in channels:
+        maxn_l[l] = max(maxn_l.get(l, 0), N)
+        pairs.add((N, l))
+        ns.add(N)
+    tab_m = 4 * (sum(((l + 1) // 2 + 1) * n for l, n in maxn_l.items()) + sum(((l + 1) // 2) * N for N, l in pairs))
+    tab_f = sum(2 * 8 * N for N in ns)
+    return {"points": pts, "flops_sincos": f_sincos, "flops_moment": f_moment,
+            "bytes_sincos": 16.0 * pts + tab_f, "bytes_moment": 16.0 * pts + tab_m}
 
 
-def cpu_baseline(w, reps=15):
+def roofline(kind, flops, nbytes, avg_ms, traffic):
+    """The binding roofline of a kernel (the larger time at peak) and the
+    achieved rate on it from the live average launch time."""
+    t_hbm = nbytes / (PEAK["hbm_GBps"] * 1e9)
+    t_mfma = flops / (PEAK["mfma_fp32_TFLOPs"] * 1e12)
+    s = avg_ms * 1e-3
+    if t_hbm >= t_mfma:
+        a = nbytes / s / 1e9
+        r = {"bound": "hbm", "achieved": a, "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": a / PEAK["hbm_GBps"]}
+    else:
+        a = flops / s / 1e12
+        r = {"bound": "mfma", "achieved": a, "peak": PEAK["mfma_fp32_TFLOPs"], "unit": "TFLOP/s",
+             "frac": a / PEAK["mfma_fp32_TFLOPs"]}
+    r.update({"traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+              "kernel": kind, "avg_launch_ms": avg_ms, "algorithmic_bytes": nbytes, "algorithmic_flops": flops,
+              "mfma_TFLOPs_algorithmic": flops / s / 1e12, "hbm_GBps_algorithmic": nbytes / s / 1e9,
+              "time_at_peak_ms": {"hbm": t_hbm * 1e3, "mfma": t_mfma * 1e3}})
+    return r
+
+
+def cpu_baseline(w, reps=40):
     """Time the FP64 oracle (dense F and T) on whole l groups of the workload."""
     import numpy as np
     from oracle import dsbt as odsbt
@@ -60,6 +114,10 @@ def cpu_baseline(w, reps=15):
     return {"value": pts / spent, "unit": "radial points/s", "cores": cores, "kind": "oracle",
             "sample": f"dense FP64 oracle forward+inverse, {reps} passes over the l groups {list(sample_ells)} "
                       f"with all m ({pts // reps} points per pass, N={N}), {spent:.1f} s; matrix build excluded"}
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -93,6 +151,7 @@ def main():
         from paper_1509_07115_amd import build
         build.build()
 
+    progress("building the workload and the plan")
     w = workloads.batched_all_m()
     plan = Plan(w.channels)
     x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
@@ -104,6 +163,7 @@ def main():
         plan.inverse(b, y)
     torch.cuda.synchronize()
 
+    progress("warmup done; timing")
     # timed region: K steps, per-stage HIP events on the launch stream
     plan.profile(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -118,25 +178,23 @@ def main():
     stages = plan.profile_read()
     plan.profile(False)
     ms_step = total_ms / args.steps
-    pts, f_sincos, f_moment, bytes_stage = algorithmic_counts(w.channels)
+    alg = algorithmic_counts(w.channels)
+    pts = alg["points"]
     value = pts / (ms_step * 1e-3)
 
     # dominant stage and its roofline (algorithmic flops / bytes per launch)
     (ms_f, n_f), (ms_m, n_m) = stages["sincos"], stages["moment"]
     avg_f, avg_m = ms_f / max(n_f, 1), ms_m / max(n_m, 1)
     if avg_m >= avg_f:
-        achieved = f_moment / (avg_m * 1e-3) / 1e12
-        roof = {"kernel": "moment stage (dsbt::mstage_mfma)", "bound": "mfma", "achieved": achieved,
-                "peak": PEAK["mfma_fp32_TFLOPs"], "unit": "TFLOP/s", "frac": achieved / PEAK["mfma_fp32_TFLOPs"],
-                "traffic": None, "avg_launch_ms": avg_m,
-                "hbm_GBps_algorithmic": bytes_stage / (avg_m * 1e-3) / 1e9}
+        traffic = None
+        if MOMENT_TRAFFIC["sha256"] and MOMENT_TRAFFIC["sha256"] == sources_sha256(MOMENT_TRAFFIC["sources"]):
+            traffic = MOMENT_TRAFFIC["fetch_bytes"] + MOMENT_TRAFFIC["write_bytes"]
+        roof = roofline("moment stage (dsbt::mstage_mfma)", alg["flops_moment"], alg["bytes_moment"], avg_m, traffic)
     else:
-        achieved = bytes_stage / (avg_f * 1e-3) / 1e9
-        roof = {"kernel": "sine/cosine stage (dsbt::fstage_n)", "bound": "hbm", "achieved": achieved,
-                "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": achieved / PEAK["hbm_GBps"], "traffic": None,
-                "avg_launch_ms": avg_f}
+        roof = roofline("sine/cosine stage (dsbt::fstage_n)", alg["flops_sincos"], alg["bytes_sincos"], avg_f, None)
     roof["stages_ms_per_launch"] = {"sincos": avg_f, "moment": avg_m}
 
+    progress(f"timed {args.steps} steps: {ms_step:.4f} ms per step; checking l = 1, 32, 63 against the oracle")
     # accuracy on sampled l groups against the FP64 oracle
     from oracle import dsbt as odsbt
     bh = b.cpu().numpy().astype(np.complex128)
@@ -160,6 +218,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_plain:
+        progress("timing the plain per-channel form")
         pplan = Plan(w.channels, mode="plain")
         pplan.forward(x, b)
         pplan.inverse(b, y)
@@ -176,6 +235,7 @@ def main():
                                  "form": "one launch per channel and stage (4 launches per channel per step)"}
         out["speedup_vs_plain"] = out["value"] / out["plain_gpu_form"]["value"]
     if not args.no_cpu_baseline:
+        progress("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
 

@@ -12,8 +12,9 @@
 // Layout: a block handles CPB channels of N points with N/8 threads each; each
 // thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
 // pass for the remaining factor), data stay in LDS with one pad slot per 32
-// complex values.  Twiddles: every power read from the FP64-built table
-// exp(-2 pi i t/N), whose FP32 entries are the unit-modulus roundings.
+// complex values.  Twiddles: per pass a table of every power a butterfly
+// needs, one 16-byte aligned row per butterfly class, built in FP64 (the
+// FP32 entries are the unit-modulus roundings).
 #include "kernels.h"
 
 namespace dsbt {
@@ -91,6 +92,23 @@ __device__ __forceinline__ void dft8(V* v) {
     v[7] = f_sub(e[3], o3);
 }
 
+// R consecutive complex values from a 16-byte aligned row.
+template <typename T, int R>
+__device__ __forceinline__ void load_row(const typename CV<T>::t* row, typename CV<T>::t* out) {
+    if constexpr (sizeof(T) == sizeof(float)) {
+        const float4* q = reinterpret_cast<const float4*>(row);
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            const float4 a = q[i];
+            out[2 * i] = make_float2(a.x, a.y);
+            out[2 * i + 1] = make_float2(a.z, a.w);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) out[i] = row[i];
+    }
+}
+
 // One Stockham pass of radix R on the channel at buf (padded indexing);
 // thread t of the channel owns butterflies j = t + u N/8, u < 8/R.
 template <typename T, int N, int R>
@@ -105,12 +123,14 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
         for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(j + r * NR)];
         const int jm = j & (Ns - 1);
         if (Ns > 1) {
-            // w^r read from the table: powers formed by repeated FP32 products
-            // carry a magnitude bias of the order of the FP32 epsilon that is
-            // the same for every butterfly of a pass with few distinct w
-            const int st = jm * (N / (Ns * R));
+            // row jm of the pass table holds w^r, r < R, w = exp(-2 pi i jm/(Ns R));
+            // powers formed by repeated FP32 products would carry a magnitude
+            // bias of the order of the FP32 epsilon, the same for every
+            // butterfly of a pass with few distinct w
+            V wv[R];
+            load_row<T, R>(tw + jm * R, wv);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], tw[r * st]);
+            for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], wv[r]);
         }
         if constexpr (R == 8) dft8<T>(v[u]);
         else if constexpr (R == 4) dft4<T>(v[u]);
@@ -128,17 +148,19 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
     lds_barrier();
 }
 
+// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R.
 template <typename T, int N>
 __device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<T>::t* tw, int t) {
     constexpr int L = __builtin_ctz(N);
-    int Ns = 1;
+    int Ns = 1, off = 0;
 #pragma unroll
     for (int s = 0; s < L / 3; ++s) {
-        fft_pass<T, N, 8>(buf, Ns, tw, t);
+        fft_pass<T, N, 8>(buf, Ns, tw + off, t);
+        if (Ns > 1) off += Ns * 8;
         Ns *= 8;
     }
-    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw, t);
-    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw, t);
+    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw + off, t);
+    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw + off, t);
 }
 
 template <typename V>

@@ -14,7 +14,7 @@ struct FChan {
     int N, log2N;
     int p;                // 1: even l (DST-II), 0: odd l (DCT-II)
     float sign;           // (-1)^ceil(l/2), or +1 for the printed F
-    const void* tw;       // exp(-2 pi i t/N), t < N, complex of the data precision
+    const void* tw;       // FFT pass tables (fft_twiddles), complex of the data precision
     const void* post;     // exp(-i pi t/(2N)), t < N
     const void* vphase;   // unit-modulus exp(-i V tau/2) per point (complex of the data precision), or nullptr
     const double* vangle; // V tau/2 per point (FP64), or nullptr

@@ -222,13 +222,28 @@ void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p,
 }
 
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
-    tw.resize(2 * (size_t)N);
-    post.resize(2 * (size_t)N);
     const double pi = 3.14159265358979323846;
+    // Stockham passes of radix 8, then one of radix 2 or 4; the pass with
+    // span Ns (> 1) and radix R has Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R))
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    std::vector<std::pair<int, int>> passes;   // (Ns, R)
+    int Ns = 1;
+    for (int s = 0; s < L / 3; ++s, Ns *= 8) passes.emplace_back(Ns, 8);
+    if (L % 3) passes.emplace_back(Ns, L % 3 == 1 ? 2 : 4);
+    tw.clear();
+    for (auto [ns, R] : passes) {
+        if (ns == 1) continue;
+        for (int jm = 0; jm < ns; ++jm)
+            for (int r = 0; r < R; ++r) {
+                const double a = -2.0 * pi * (double)((int64_t)r * jm) / (double)(ns * R);
+                tw.push_back(std::cos(a));
+                tw.push_back(std::sin(a));
+            }
+    }
+    if (tw.empty()) tw.assign(2, 1.0), tw[1] = 0.0;
+    post.resize(2 * (size_t)N);
     for (int t = 0; t < N; ++t) {
-        const double a = -2.0 * pi * t / N;
-        tw[2 * t] = std::cos(a);
-        tw[2 * t + 1] = std::sin(a);
         const double b = -pi * t / (2.0 * N);
         post[2 * t] = std::cos(b);
         post[2 * t + 1] = std::sin(b);

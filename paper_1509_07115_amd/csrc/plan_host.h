@@ -48,8 +48,10 @@ void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int n
 void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p, int NT, int NB, bool inverse,
                          std::vector<double>& out);
 
-// FP64 twiddles exp(-2 pi i t / N), t < N, and exp(-i pi k / (2N)), k < N, as
-// interleaved (re, im).
+// FP64 tables of the size-N transform as interleaved (re, im): tw, the pass
+// tables of the FFT (for each Stockham pass with span Ns > 1 and radix R, in
+// pass order, Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R)); radix 8 then
+// one radix-2 or radix-4 pass), and post, exp(-i pi k/(2N)), k < N.
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post);
 
 }  // namespace dsbt
