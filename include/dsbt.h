@@ -91,7 +91,8 @@ typedef struct {
     int32_t kinetic;      /* DSBT_K_PLAIN (default) or DSBT_K_CORRECTED */
     int32_t sign;         /* DSBT_SIGN_C (default): b_n ~ c_l(k_n) sqrt(w_n) */
     int32_t mode;         /* DSBT_MODE_BATCHED (default) or DSBT_MODE_PLAIN */
-    int32_t plan_where;   /* where the FP64 plan tables are generated */
+    int32_t plan_where;   /* DSBT_PLAN_ON_DEVICE (default): the FP64 DLOP recurrences and tile
+                             blocks are computed by GPU kernels; DSBT_PLAN_ON_HOST: by host threads */
     int32_t tile;         /* moment tile B (power of two >= ceil((l+1)/2)); 0 = automatic */
     int32_t chans_per_block; /* channels per workgroup in the transform stage; 0 = automatic */
     int32_t reserved[9];
@@ -173,6 +174,14 @@ dsbt_status dsbt_profile_read(dsbt_plan p, double* ms, int64_t* launches, int32_
  * [J B, J B + B).  If out is NULL or out_len is too small only *needed is set. */
 dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
                                  int64_t out_len, int64_t* needed);
+
+/* The same blocks computed by the device plan generator (the FP64 kernels that
+ * dsbt_plan_create runs with DSBT_PLAN_ON_DEVICE) on the current HIP device,
+ * l <= 255; `stream` orders the work and is synchronised before return.  The
+ * generator allocates its scratch (about (N^2/2 + ceil(l/2) N^2/(2B)) doubles)
+ * for the call and frees it.  Returns DSBT_ERR_NO_DEVICE without a device. */
+dsbt_status dsbt_device_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
+                                   int64_t out_len, int64_t* needed, void* stream);
 
 const char* dsbt_status_string(dsbt_status s);
 const char* dsbt_last_error(void);

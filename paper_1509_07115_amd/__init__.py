@@ -41,10 +41,12 @@ class Plan:
     channels: sequence of (N, ell, rmax, offset) tuples (offset in complex elements).
     precision: "c64" (complex64 data, FP32 arithmetic) or "c128".
     mode: "batched" (default) or "plain" (one launch per channel and stage).
+    plan_where: "device" (default, FP64 plan kernels on the GPU) or "host".
     """
 
     def __init__(self, channels: Sequence, precision: str = "c64", mode: str = "batched", tile: int = 0,
-                 chans_per_block: int = 0, sign: bool = True, stream=None, _create=True):
+                 chans_per_block: int = 0, sign: bool = True, plan_where: str = "device", stream=None,
+                 _create=True):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         self.precision = precision
@@ -54,19 +56,20 @@ class Plan:
         arr = (_lib.Channel * len(self.channels))()
         for i, (N, ell, rmax, off) in enumerate(self.channels):
             arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
-        opts = self._opts(precision, mode, tile, chans_per_block, sign)
+        opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where)
         _lib.check(self._lib.dsbt_plan_create(ctypes.byref(self._h), arr, len(self.channels), ctypes.byref(opts),
                                               _stream_handle(stream)), "dsbt_plan_create")
         self._info()
 
     @staticmethod
-    def _opts(precision, mode, tile, chans_per_block, sign):
+    def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device"):
         o = _lib.PlanOpts()
         o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128}[precision]
         o.mode = {"batched": _lib.DSBT_MODE_BATCHED, "plain": _lib.DSBT_MODE_PLAIN}[mode]
         o.tile = int(tile)
         o.chans_per_block = int(chans_per_block)
         o.sign = _lib.DSBT_SIGN_C if sign else _lib.DSBT_SIGN_PRINTED_F
+        o.plan_where = {"device": _lib.DSBT_PLAN_ON_DEVICE, "host": _lib.DSBT_PLAN_ON_HOST}[plan_where]
         return o
 
     @classmethod
@@ -186,6 +189,20 @@ def host_ftb_tables(N: int, ell: int, B: int) -> np.ndarray:
     out = np.empty(need.value, dtype=np.float64)
     _lib.check(lib.dsbt_host_ftb_tables(N, ell, B, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                         need.value, ctypes.byref(need)), "dsbt_host_ftb_tables")
+    k = (ell + 1) // 2
+    R = B + k
+    return out.reshape(N // B, R, R)
+
+
+def device_ftb_tables(N: int, ell: int, B: int, stream=None) -> np.ndarray:
+    """The same blocks from the FP64 GPU plan generator (``dsbt_device_ftb_tables``)."""
+    lib = _lib.load()
+    need = ctypes.c_int64()
+    _lib.check(lib.dsbt_device_ftb_tables(N, ell, B, None, 0, ctypes.byref(need), None), "dsbt_device_ftb_tables")
+    out = np.empty(need.value, dtype=np.float64)
+    _lib.check(lib.dsbt_device_ftb_tables(N, ell, B, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          need.value, ctypes.byref(need), _stream_handle(stream)),
+               "dsbt_device_ftb_tables")
     k = (ell + 1) // 2
     R = B + k
     return out.reshape(N // B, R, R)

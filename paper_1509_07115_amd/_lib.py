@@ -12,6 +12,7 @@ DSBT_C64, DSBT_C128 = 0, 1
 DSBT_K_PLAIN, DSBT_K_CORRECTED = 0, 1
 DSBT_SIGN_C, DSBT_SIGN_PRINTED_F = 0, 1
 DSBT_MODE_BATCHED, DSBT_MODE_PLAIN = 0, 1
+DSBT_PLAN_ON_DEVICE, DSBT_PLAN_ON_HOST = 0, 1
 DSBT_STEP_ADJOINT, DSBT_STEP_GRAPH, DSBT_STEP_RESIDENT = 1, 2, 4
 
 STATUS_NAMES = {
@@ -24,6 +25,7 @@ EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_kinetic_step",
     "dsbt_step_grad_s", "dsbt_profile_enable", "dsbt_profile_read", "dsbt_host_ftb_tables",
+    "dsbt_device_ftb_tables",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -74,6 +76,7 @@ def load() -> ctypes.CDLL:
         "dsbt_profile_enable": (i32, [P, i32]),
         "dsbt_profile_read": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "dsbt_host_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]),
+        "dsbt_device_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64), P]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),
     }

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "plan_device.h"
 #include "plan_host.h"
 
 namespace {
@@ -220,6 +221,30 @@ void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_
     return d;
 }
 
+// Temporary device buffer for the plan generator, freed on scope exit.
+struct DeviceScratch {
+    double* ptr = nullptr;
+    void alloc(size_t doubles) {
+        if (doubles == 0) return;
+        hipError_t e = hipMalloc(&ptr, sizeof(double) * doubles);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            throw StatusError(DSBT_ERR_OOM, std::string("plan scratch: ") + hipGetErrorString(e));
+        }
+    }
+    ~DeviceScratch() {
+        if (ptr) (void)hipFree(ptr);
+    }
+};
+
+void device_blocks(int ell, int B, int NT, double* scratch, std::vector<double>& blk, hipStream_t s) {
+    try {
+        dsbt::build_ftb_blocks_device(ell, B, NT, scratch, blk, s);
+    } catch (const std::runtime_error& e) {
+        throw HipError(hipErrorLaunchFailure, e.what());
+    }
+}
+
 template <typename T>
 void* upload_converted(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s) {
     std::vector<T> h(v.size());
@@ -303,11 +328,22 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     struct Tab { const void* f; const void* i; const float* mf; const float* mi; int NB; };
     std::map<int, Tab> tabs;
     const bool fp32 = std::is_same<T, float>::value;
+    // FP64 blocks generated on the device (default) or by host threads
+    DeviceScratch scratch;
+    if (P->opts.plan_where == DSBT_PLAN_ON_DEVICE) {
+        size_t most = 0;
+        for (auto& kv : tileB)
+            most = std::max(most, dsbt::device_plan_scratch_doubles(kv.first, kv.second, maxN[kv.first] / kv.second));
+        scratch.alloc(most);
+    }
     for (auto& kv : tileB) {
         const int ell = kv.first, B = kv.second, NT = maxN[ell] / B;
         const int k = dsbt::n_extra(ell), R = B + k;
         std::vector<double> blk;
-        dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
+        if (P->opts.plan_where == DSBT_PLAN_ON_DEVICE)
+            device_blocks(ell, B, NT, scratch.ptr, blk, s);
+        else
+            dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
         Tab t{nullptr, nullptr, nullptr, nullptr, 0};
         // matrix-core path: B = 32 with R <= 64, or B = 64 with R <= 128
         const int R16 = 2 * B;
@@ -611,6 +647,8 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
         if (opts.kinetic != DSBT_K_PLAIN) return fail(DSBT_ERR_UNSUPPORTED, "corrected kinetic momenta not built in");
         if (opts.mode != DSBT_MODE_BATCHED && opts.mode != DSBT_MODE_PLAIN)
             return fail(DSBT_ERR_INVALID_ARG, "unknown mode");
+        if (opts.plan_where != DSBT_PLAN_ON_DEVICE && opts.plan_where != DSBT_PLAN_ON_HOST)
+            return fail(DSBT_ERR_INVALID_ARG, "unknown plan_where");
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(DSBT_ERR_NO_DEVICE, "no HIP device");
         int dev = 0;
@@ -899,6 +937,27 @@ dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
     return guarded([&]() -> dsbt_status {
         std::vector<double> blk;
         dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
+        std::memcpy(out, blk.data(), sizeof(double) * blk.size());
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_device_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out, int64_t out_len,
+                                   int64_t* needed, void* stream) {
+    if (!is_pow2(N) || N < 2) return fail(DSBT_ERR_UNSUPPORTED, "N must be a power of two");
+    if (ell < 0 || ell > 2 * N - 2 || ell > 255) return fail(DSBT_ERR_UNSUPPORTED, "need 0 <= l <= min(2N-2, 255)");
+    if (!is_pow2(B) || B > N || B < dsbt::n0_of(ell)) return fail(DSBT_ERR_UNSUPPORTED, "bad tile");
+    const int R = B + dsbt::n_extra(ell), NT = N / B;
+    const int64_t need = (int64_t)R * R * NT;
+    if (needed) *needed = need;
+    if (!out || out_len < need) return DSBT_OK;
+    return guarded([&]() -> dsbt_status {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(DSBT_ERR_NO_DEVICE, "no HIP device");
+        DeviceScratch scratch;
+        scratch.alloc(dsbt::device_plan_scratch_doubles(ell, B, NT));
+        std::vector<double> blk;
+        device_blocks(ell, B, NT, scratch.ptr, blk, (hipStream_t)stream);
         std::memcpy(out, blk.data(), sizeof(double) * blk.size());
         return DSBT_OK;
     });
