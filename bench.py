@@ -29,7 +29,8 @@ PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3}
 # sources at the time of the measurement; after any change to them the figure
 # no longer applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_mfma.hip", "paper_1509_07115_amd/csrc/kernels.h"],
-                  "sha256": None, "fetch_bytes": None, "write_bytes": None}
+                  "sha256": "ace2466f98616e76e2fa109ad5133f57f914169cc6d83144865f49c14dd12838",
+                  "fetch_bytes": 227725088, "write_bytes": 67485248}
 
 
 def sources_sha256(paths):
@@ -87,7 +88,7 @@ def roofline(kind, flops, nbytes, avg_ms, traffic):
     return r
 
 
-def cpu_baseline(w, reps=40):
+def cpu_baseline(w, reps=300):
     """Time the FP64 oracle (dense F and T) on whole l groups of the workload."""
     import numpy as np
     from oracle import dsbt as odsbt
