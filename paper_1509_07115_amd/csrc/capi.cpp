@@ -45,9 +45,6 @@ struct StatusError : std::runtime_error {
     StatusError(dsbt_status s, const std::string& m) : std::runtime_error(m), st(s) {}
 };
 
-// Moment passes over at least this many tiles of B = 32 run as two halves.
-constexpr int kSplitMinTiles = 16;
-
 bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 int ilog2(int n) {
     int l = 0;
@@ -140,9 +137,6 @@ struct dsbt_plan_s {
     // generic kernel (FP64 plans, larger blocks); per-channel items for the
     // plain form
     std::vector<dsbt::MItem> h_items_mf, h_items_v1, h_items1;
-    std::vector<dsbt::FixItem> h_fix_f, h_fix_i;   // corrections of split passes (forward, inverse)
-    dsbt::FixItem* d_fix_f = nullptr;
-    dsbt::FixItem* d_fix_i = nullptr;
     std::vector<char> items1_mf;          // per channel: item uses the matrix-core kernel
     dsbt::MItem* d_items_mf = nullptr;
     dsbt::MItem* d_items_v1 = nullptr;
@@ -333,8 +327,6 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     // moment tables per l
     struct Tab { const void* f; const void* i; const float* mf; const float* mi; int NB; };
     std::map<int, Tab> tabs;
-    struct SplitTab { const float* gf; const float* gi; const float* phi; int H; };
-    std::map<std::pair<int, int>, SplitTab> split_tabs;   // (l, N)
     const bool fp32 = std::is_same<T, float>::value;
     // FP64 blocks generated on the device (default) or by host threads
     DeviceScratch scratch;
@@ -362,25 +354,6 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             t.mf = (const float*)upload_converted<float>(P, arr, s);
             dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, true, arr);
             t.mi = (const float*)upload_converted<float>(P, arr, s);
-            // B = 32: passes over at least kSplitMinTiles tiles run as two halves
-            if (B == 32 && P->opts.mode == DSBT_MODE_BATCHED) {
-                for (auto& g : P->groups) {
-                    const int nt = g.N / B;
-                    if (g.ell != ell || nt < kSplitMinTiles || split_tabs.count({ell, g.N})) continue;
-                    SplitTab st{};
-                    st.H = nt / 2;
-                    std::vector<double> G, phi, a2;
-                    dsbt::split_tables(blk, B, k, dsbt::parity_p(ell), nt, st.H, false, G, phi);
-                    dsbt::arrange_fix_blocks(G, nt - st.H, B, k, a2);
-                    st.gf = (const float*)upload_converted<float>(P, a2, s);
-                    dsbt::arrange_fix_blocks(phi, 1, k, k, a2);
-                    st.phi = (const float*)upload_converted<float>(P, a2, s);
-                    dsbt::split_tables(blk, B, k, dsbt::parity_p(ell), nt, st.H, true, G, phi);
-                    dsbt::arrange_fix_blocks(G, nt - st.H, B, k, a2);
-                    st.gi = (const float*)upload_converted<float>(P, a2, s);
-                    split_tabs[{ell, g.N}] = st;
-                }
-            }
         } else {
             std::vector<double> tr(blk.size());
             for (int J = 0; J < NT; ++J) {
@@ -468,55 +441,12 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             per = 8 * base.NCB;
         }
         if (cpb > 0) per = std::min(per, cpb);
-        base.s0 = 0;
-        base.nst = base.NT;
-        base.flags = dsbt::kWriteCompletion;
-        base.mu_out = nullptr;
-        auto sp = split_tabs.find({g.ell, g.N});
-        const bool split = mf && sp != split_tabs.end();
         for (size_t i0 = 0; i0 < g.chans.size(); i0 += per) {
             dsbt::MItem it = base;
             it.nch = (int)std::min<size_t>(per, g.chans.size() - i0);
             for (int j = 0; j < dsbt::kMaxChanPerItem; ++j)
                 it.off[j] = P->ch[g.chans[i0 + (j < it.nch ? j : 0)]].offset;   // repeat a real channel
-            if (split) {
-                // two halves of the tile chain, corrected afterwards
-                const SplitTab& st = sp->second;
-                const size_t mu_floats = (size_t)it.NCB * 32 * 16;
-                float* mu_a = (float*)P->dalloc(sizeof(float) * mu_floats);
-                float* mu_b = (float*)P->dalloc(sizeof(float) * mu_floats);
-                dsbt::MItem a = it, b = it;
-                a.s0 = 0;
-                a.nst = st.H;
-                a.flags = 0;
-                a.mu_out = mu_a;
-                b.s0 = st.H;
-                b.nst = it.NT - st.H;
-                b.flags = 0;
-                b.mu_out = mu_b;
-                for (const dsbt::MItem* x : {&a, &b}) {
-                    items_mf.push_back(*x);
-                    items_mf_ell.push_back(g.ell);
-                }
-                dsbt::FixItem f{};
-                f.mu_h = mu_a;
-                f.k = it.k;
-                f.p = it.p;
-                f.nch = it.nch;
-                f.NCB = it.NCB;
-                f.NTF = it.NT - st.H;
-                for (int j = 0; j < dsbt::kMaxChanPerItem; ++j) f.off[j] = it.off[j];
-                dsbt::FixItem ff = f, fi = f;
-                ff.g = st.gf;
-                ff.phi = st.phi;
-                ff.mu_end = mu_b;
-                ff.J0 = st.H;
-                fi.g = st.gi;
-                fi.J0 = 0;
-                P->h_fix_f.push_back(ff);
-                P->h_fix_i.push_back(fi);
-                P->mf_lds = std::max(P->mf_lds, dsbt::mfma_lds_bytes_for(it.NB, it.NCB, it.B));
-            } else if (mf) {
+            if (mf) {
                 items_mf.push_back(it);
                 items_mf_ell.push_back(g.ell);
                 P->mf_lds = std::max(P->mf_lds, dsbt::mfma_lds_bytes_for(it.NB, it.NCB, it.B));
@@ -550,7 +480,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             for (size_t j = 0; j < kv.second.size(); j += chunk) {
                 std::vector<int> ids(kv.second.begin() + j, kv.second.begin() + std::min(kv.second.size(), j + chunk));
                 double cost = 0.0;
-                for (int i : ids) cost += (double)items_mf[i].nst * items_mf[i].NB * items_mf[i].NB;
+                for (int i : ids) cost += (double)items_mf[i].NT * items_mf[i].NB * items_mf[i].NB;
                 chunks.emplace_back(cost, ids);
             }
         }
@@ -579,14 +509,6 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         return d;
     };
     P->d_items_mf = upload_items(P->h_items_mf);
-    auto upload_fix = [&](const std::vector<dsbt::FixItem>& v) -> dsbt::FixItem* {
-        if (v.empty()) return nullptr;
-        auto* d = (dsbt::FixItem*)P->dalloc(sizeof(dsbt::FixItem) * v.size());
-        hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::FixItem) * v.size(), hipMemcpyHostToDevice), "fix items");
-        return d;
-    };
-    P->d_fix_f = upload_fix(P->h_fix_f);
-    P->d_fix_i = upload_fix(P->h_fix_i);
     P->d_items_v1 = upload_items(P->h_items_v1);
     P->d_items1 = upload_items(P->h_items1);
     P->d_scratch = (double*)P->dalloc(sizeof(double) * (nch + 1));
@@ -617,12 +539,6 @@ void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hi
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
             hip_check(dsbt::launch_mstage_mfma(P->d_items_mf, (int)P->h_items_mf.size(), P->mf_waves, P->mf_lds, src,
                                                dst, inverse, ph, s), "mstage_mfma");
-        });
-    dsbt::FixItem* fix = inverse ? P->d_fix_i : P->d_fix_f;
-    if (fix)
-        timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(dsbt::launch_mstage_fix(fix, (int)(inverse ? P->h_fix_i.size() : P->h_fix_f.size()), dst,
-                                              inverse, ph, s), "mstage_fix");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -877,11 +793,6 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
             if (d) hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::MItem) * v.size(), hipMemcpyHostToDevice), "items");
         };
         refresh(p->h_items_mf, p->d_items_mf);
-        for (auto& f : p->h_fix_f)
-            if (f.nch > 0) f.kphase = by_off[f.off[0]];
-        if (p->d_fix_f)
-            hip_check(hipMemcpy(p->d_fix_f, p->h_fix_f.data(), sizeof(dsbt::FixItem) * p->h_fix_f.size(),
-                                hipMemcpyHostToDevice), "fix items");
         refresh(p->h_items_v1, p->d_items_v1);
         refresh(p->h_items1, p->d_items1);
         p->has_potential = true;

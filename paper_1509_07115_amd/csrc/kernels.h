@@ -31,33 +31,8 @@ struct MItem {
     int B, k, R, NT, p, nch;
     int NB;                // 16-row blocks of the padded block size R16 = 16 NB (1, 2, 4 or 8)
     int NCB;               // 8-channel column blocks of the item (mfma_ncb on the matrix-core path)
-    // Matrix-core path: the item runs steps s0 .. s0+nst-1 of the pass (step s
-    // is tile s forward, tile NT-1-s inverse).  A range that starts past step
-    // 0 starts from zero moments; mu_out (when set) receives the moments after
-    // its last step as [NCB][32][16] floats (rows past k zero); the forward
-    // completion rows are written only with kWriteCompletion.
-    int s0, nst, flags;
-    float* mu_out;
     int64_t off[kMaxChanPerItem];
 };
-constexpr int kWriteCompletion = 1;
-
-// Correction of a moment pass split at step H (matrix-core path, B = 32):
-// the steps from H on started from zero moments, so their tile results lack
-// the rank-k term G_J mu_H (forward: G_J = E_J D_{J-1} .. D_H for tiles J >= H;
-// inverse: G_J = Q_J^T D_{J+1}^T .. D_{H'-1}^T for tiles J < H' = NT - H), and
-// the forward completion rows are (-1)^p (mu_NT^0 + Phi mu_H), Phi = D_{NT-1} .. D_H.
-struct FixItem {
-    const float* g;        // tiles of the corrected range in order J = J0 .. J0+NTF-1: per tile, row block
-                           // (2) and lane, 8 floats G_J[16 rb + l%16][4 kc + l/16] (K padded to 32)
-    const float* phi;      // forward: Phi as 2 row blocks x 64 lanes x 8 floats (same layout), else nullptr
-    const float* mu_h;     // [NCB][32][16]: mu_H from the first range
-    const float* mu_end;   // [NCB][32][16]: moments after the second range (forward completion), or nullptr
-    const void* kphase;    // forward kinetic phases (as MItem), or nullptr
-    int J0, NTF, k, p, nch, NCB;
-    int64_t off[kMaxChanPerItem];
-};
-
 
 // MFMA operand layout of one direction's blocks: for tile J, row block rb and
 // lane l, the NK = 4 NB consecutive floats A'[16 rb + l%16][4 kc + l/16],
@@ -131,11 +106,6 @@ inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
     return sizeof(float) * (size_t)(2 * NCB * 16 * NB * 16 + 2 * NCB * B * 16);
 }
 hipError_t set_lds_limits_mfma();
-// Correction of split passes: adds G_J mu_H for every FixItem to the pass
-// output `data` in place (and the forward completion rows); phases as for
-// the moment stage.
-hipError_t launch_mstage_fix(const FixItem* d_items, int nitems, void* data, bool inverse, PhaseArgs ph,
-                             hipStream_t s);
 
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into
 // scratch[nch], then out[0] = their sum (FP64).

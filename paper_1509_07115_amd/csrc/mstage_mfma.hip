@@ -51,7 +51,7 @@ struct MfmaTile {
     float* Yt;   // [2][NCB][B][16]: tile results
     const float DSBT_GLOBAL* tab;
     const f2 DSBT_GLOBAL* kphase;
-    int k, NT, S0, NST, tid, lane, rb;
+    int k, NT, tid, lane, rb;
     int cbs[UMAX];
     bool conj;
     f4 a[SETS][NK / 4];    // operand sets of SETS consecutive tiles
@@ -65,8 +65,6 @@ struct MfmaTile {
         : it(it_), src(as_global(reinterpret_cast<const f2*>(s_))), dst(as_global_rw(reinterpret_cast<f2*>(d_))) {
         k = it.k;
         NT = it.NT;
-        S0 = it.s0;
-        NST = it.nst;
         tid = threadIdx.x;
         lane = tid & 63;
         const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
@@ -94,14 +92,14 @@ struct MfmaTile {
             sidx[i] = s;
         }
     }
-    __device__ int tile_of(int step) const { return INV ? NT - 1 - (S0 + step) : S0 + step; }
+    __device__ int tile_of(int step) const { return INV ? NT - 1 - step : step; }
     __device__ float* xt(int par, int cb, int row) const { return Xt + ((par * NCB + cb) * R16 + row) * 16; }
     __device__ float* yt(int par, int cb, int row) const { return Yt + ((par * NCB + cb) * B + row) * 16; }
     static __device__ f2 cm(f2 x, f2 y) { return f2{x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x}; }
 
     template <int S>
     __device__ void load(int step) {   // issue the loads of one tile (clamped to the last) into set S
-        const int J = tile_of(step < NST ? step : NST - 1);
+        const int J = tile_of(step < NT ? step : NT - 1);
         const f4 DSBT_GLOBAL* ap = reinterpret_cast<const f4 DSBT_GLOBAL*>(tab + (((size_t)J * NB + rb) * 64 + lane) * NK);
 #pragma unroll
         for (int i = 0; i < NK / 4; ++i) a[S][i] = ap[i];
@@ -192,7 +190,7 @@ struct MfmaTile {
     template <int I>
     __device__ void tail(int st) {   // the last NT mod SETS tiles
         if constexpr (I < SETS - 1) {
-            if (st + I < NST) step<I>(st + I);
+            if (st + I < NT) step<I>(st + I);
             tail<I + 1>(st);
         }
     }
@@ -202,7 +200,7 @@ struct MfmaTile {
         for (int e = tid; e < 2 * NCB * R16 * 16; e += NTH) Xt[e] = 0.0f;
         prologue<0>();
         lds_barrier();
-        if (INV && S0 == 0) {
+        if constexpr (INV) {
             for (int e = tid; e < NCH * k; e += NTH) {
                 const int ch = e / k, kk = e % k;
                 const f2 v = src[it.off[ch] + kk];
@@ -214,19 +212,11 @@ struct MfmaTile {
         stage_data<0>(0);
         lds_barrier();
         int st = 0;
-        for (; st + SETS <= NST; st += SETS) steps<0>(st);
+        for (; st + SETS <= NT; st += SETS) steps<0>(st);
         tail<0>(st);
-        if (it.mu_out) {   // moments after the last step: Xt[NST & 1] rows B .. B+k
-            const float* X = Xt + (NST & 1) * NCB * R16 * 16;
-            float DSBT_GLOBAL* mo = as_global_rw(it.mu_out);
-            for (int e = tid; e < NCB * 32 * 16; e += NTH) {
-                const int cb = e / 512, r = (e / 16) & 31, c = e & 15;
-                mo[e] = r < k ? X[(cb * R16 + B + r) * 16 + c] : 0.0f;
-            }
-        }
-        if (!INV && (it.flags & kWriteCompletion)) {
+        if constexpr (!INV) {
             // completion rows, written by the thread that wrote the same slot of tile 0
-            const float* X = Xt + (NST & 1) * NCB * R16 * 16;
+            const float* X = Xt + (NT & 1) * NCB * R16 * 16;
 #pragma unroll
             for (int i = 0; i < GM; ++i) {
                 if (sidx[i] >= k) continue;

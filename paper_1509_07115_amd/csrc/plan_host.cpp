@@ -221,68 +221,6 @@ void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p,
     }
 }
 
-void split_tables(const std::vector<double>& blocks, int B, int k, int p, int NT, int H, bool inverse,
-                  std::vector<double>& G, std::vector<double>& phi) {
-    const int R = B + k;
-    auto M = [&](int J, int r, int c) { return blocks[((size_t)J * R + r) * R + c]; };
-    std::vector<double> X((size_t)k * k, 0.0), Y((size_t)k * k);
-    for (int a = 0; a < k; ++a) X[(size_t)a * k + a] = 1.0;
-    const int nt = NT - H;   // tiles corrected (forward H .. NT-1, inverse 0 .. NT-H-1)
-    G.assign((size_t)nt * B * k, 0.0);
-    if (!inverse) {
-        for (int J = H; J < NT; ++J) {
-            double* g = G.data() + (size_t)(J - H) * B * k;
-            for (int r = 0; r < B; ++r)
-                for (int c = 0; c < k; ++c) {
-                    double s = 0.0;
-                    for (int a = 0; a < k; ++a) s += M(J, r, B + a) * X[(size_t)a * k + c];
-                    g[(size_t)r * k + c] = s;
-                }
-            for (int a = 0; a < k; ++a)   // X <- D_J X
-                for (int c = 0; c < k; ++c) {
-                    double s = 0.0;
-                    for (int b = 0; b < k; ++b) s += M(J, B + a, B + b) * X[(size_t)b * k + c];
-                    Y[(size_t)a * k + c] = s;
-                }
-            std::swap(X, Y);
-        }
-        phi = X;
-    } else {
-        for (int J = NT - H - 1; J >= 0; --J) {
-            double* g = G.data() + (size_t)J * B * k;
-            for (int s = 0; s < B; ++s)
-                for (int c = 0; c < k; ++c) {
-                    double v = 0.0;
-                    for (int a = 0; a < k; ++a) v += M(J, B + a, s) * X[(size_t)a * k + c];
-                    g[(size_t)s * k + c] = v;
-                }
-            if (J == 0 && p == 0)   // odd l: slot 0 of tile 0 is m = 0, weighted by w_0
-                for (int c = 0; c < k; ++c) g[c] *= std::sqrt(0.5);
-            for (int a = 0; a < k; ++a)   // X <- D_J^T X
-                for (int c = 0; c < k; ++c) {
-                    double v = 0.0;
-                    for (int b = 0; b < k; ++b) v += M(J, B + b, B + a) * X[(size_t)b * k + c];
-                    Y[(size_t)a * k + c] = v;
-                }
-            std::swap(X, Y);
-        }
-        phi.clear();
-    }
-}
-
-void arrange_fix_blocks(const std::vector<double>& mats, int nmat, int rows, int k, std::vector<double>& out) {
-    if (rows > 32 || k > 32) throw std::invalid_argument("arrange_fix_blocks: block larger than 32 x 32");
-    out.assign((size_t)nmat * 2 * 64 * 8, 0.0);
-    for (int t = 0; t < nmat; ++t)
-        for (int rb = 0; rb < 2; ++rb)
-            for (int l = 0; l < 64; ++l)
-                for (int kc = 0; kc < 8; ++kc) {
-                    const int r = 16 * rb + (l % 16), c = 4 * kc + l / 16;
-                    if (r < rows && c < k)
-                        out[(((size_t)t * 2 + rb) * 64 + l) * 8 + kc] = mats[((size_t)t * rows + r) * k + c];
-                }
-}
-
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
     const double pi = 3.14159265358979323846;
     // Stockham passes of radix 8, then one of radix 2 or 4; the pass with

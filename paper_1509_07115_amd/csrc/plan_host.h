@@ -48,21 +48,6 @@ void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int n
 void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p, int NT, int NB, bool inverse,
                          std::vector<double>& out);
 
-// Tables that correct a moment pass split at step H (matrix-core path):
-// forward, G_J = E_J Phi_J for tiles J = H .. NT-1 with Phi_H = I,
-// Phi_{J+1} = D_J Phi_J, and phi = Phi_NT; inverse, G_J = Q_J^T Psi_{J+1} for
-// tiles J = 0 .. NT-H-1 with Psi_{NT-H} = I, Psi_J = D_J^T Psi_{J+1} (and the
-// odd-l weight w_0 on row 0 of G_0).  E, D, Q are the blocks of M_J
-// (rows/columns B.. are the moments).  G: tiles in increasing J, B x k each,
-// row-major; phi: k x k.
-void split_tables(const std::vector<double>& blocks, int B, int k, int p, int NT, int H, bool inverse,
-                  std::vector<double>& G, std::vector<double>& phi);
-
-// Operand layout of row-major matrices of `rows` (<= 32) x k (<= 32) for the
-// correction kernel: per matrix, row block rb (2) and lane l, 8 floats
-// A[16 rb + l%16][4 kc + l/16], zero outside the matrix.
-void arrange_fix_blocks(const std::vector<double>& mats, int nmat, int rows, int k, std::vector<double>& out);
-
 // FP64 tables of the size-N transform as interleaved (re, im): tw, the pass
 // tables of the FFT (for each Stockham pass with span Ns > 1 and radix R, in
 // pass order, Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R)); radix 8 then

@@ -107,24 +107,13 @@ def test_c64_parity_small(N, ells, mode):
     assert per_channel_rel(y, refi, chans).max() < 2e-6
 
 
-def test_plain_and_batched_agree():
-    # the batched form runs passes over >= 16 tiles as two halves plus a
-    # correction, so it agrees with the plain form to rounding, not bitwise;
-    # each form is deterministic
+def test_plain_and_batched_agree_bitwise():
     w = workloads.batched_all_m(seed=7, N=512, rmax=25.0, ells=[0, 3, 8, 21])
     x = to_dev(w.psi, torch.complex64)
-    pa = Plan(w.channels)
-    a = pa.forward(x)
+    a = Plan(w.channels).forward(x)
     b = Plan(w.channels, mode="plain").forward(x)
-    a2 = pa.forward(x)
     torch.cuda.synchronize()
-    assert torch.equal(a, a2)
-    assert (a - b).abs().max().item() <= 1e-6 * b.abs().max().item()
-    for ell_inv in (False, True):
-        ya = pa.inverse(a) if ell_inv else a
-        yb = Plan(w.channels, mode="plain").inverse(b) if ell_inv else b
-        torch.cuda.synchronize()
-        assert (ya - yb).abs().max().item() <= 1e-6 * yb.abs().max().item()
+    assert torch.equal(a, b)
 
 
 def test_in_place_and_offsets_with_gaps():
