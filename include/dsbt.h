@@ -23,8 +23,8 @@
  * uses the diagonal kinetic energy K_n = k_nl^2 / 2 of eq. KinMat.
  *
  * Data layout.  Every data buffer is a device pointer to packed interleaved
- * complex values (re, im) -- complex64 (float2) for DSBT_C64 plans, complex128
- * (double2) for DSBT_C128 plans -- the same memory layout as torch.complex64 /
+ * complex values (re, im) -- complex64 (float2) for DSBT_C64 and DSBT_C64_FP64
+ * plans, complex128 (double2) for DSBT_C128 plans -- the same memory layout as torch.complex64 /
  * torch.complex128.  Channel c occupies elements [offset_c, offset_c + N_c).
  * Coefficient vectors b are stored in slot order j = n - p_l, n = p_l..N_l,
  * where p_l = 1 for even l and 0 for odd l (eq. k_grid).
@@ -80,14 +80,18 @@ typedef struct {
     int64_t offset;
 } dsbt_channel;
 
-enum { DSBT_C64 = 0, DSBT_C128 = 1 };               /* data precision */
+/* data precision: complex64 data with FP32 arithmetic (FP32 tables from the
+ * FP64 plan), complex128 data with FP64 arithmetic, or complex64 data with FP64
+ * arithmetic and tables (rounded to FP32 only where data is stored; for long
+ * propagations, where FP32 rounding of the constants biases the norm) */
+enum { DSBT_C64 = 0, DSBT_C128 = 1, DSBT_C64_FP64 = 2 };
 enum { DSBT_K_PLAIN = 0, DSBT_K_CORRECTED = 1 };     /* k_nl = n dk, or eq. kcorr roots */
 enum { DSBT_SIGN_C = 0, DSBT_SIGN_PRINTED_F = 1 };   /* F with / without (-1)^ceil(l/2) */
 enum { DSBT_MODE_BATCHED = 0, DSBT_MODE_PLAIN = 1 }; /* batched launches / one launch per channel and stage */
 enum { DSBT_PLAN_ON_DEVICE = 0, DSBT_PLAN_ON_HOST = 1 };
 
 typedef struct {
-    int32_t precision;    /* DSBT_C64 (default) or DSBT_C128 */
+    int32_t precision;    /* DSBT_C64 (default), DSBT_C128 or DSBT_C64_FP64 */
     int32_t kinetic;      /* DSBT_K_PLAIN (default) or DSBT_K_CORRECTED */
     int32_t sign;         /* DSBT_SIGN_C (default): b_n ~ c_l(k_n) sqrt(w_n) */
     int32_t mode;         /* DSBT_MODE_BATCHED (default) or DSBT_MODE_PLAIN */

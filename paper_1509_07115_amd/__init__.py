@@ -39,7 +39,8 @@ class Plan:
     """A DSBT plan over a set of radial channels (``dsbt_plan_create``).
 
     channels: sequence of (N, ell, rmax, offset) tuples (offset in complex elements).
-    precision: "c64" (complex64 data, FP32 arithmetic) or "c128".
+    precision: "c64" (complex64 data, FP32 arithmetic), "c128", or "c64x"
+    (complex64 data, FP64 arithmetic and tables).
     mode: "batched" (default) or "plain" (one launch per channel and stage).
     plan_where: "device" (default, FP64 plan kernels on the GPU) or "host".
     """
@@ -64,7 +65,7 @@ class Plan:
     @staticmethod
     def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device"):
         o = _lib.PlanOpts()
-        o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128}[precision]
+        o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128, "c64x": _lib.DSBT_C64_FP64}[precision]
         o.mode = {"batched": _lib.DSBT_MODE_BATCHED, "plain": _lib.DSBT_MODE_PLAIN}[mode]
         o.tile = int(tile)
         o.chans_per_block = int(chans_per_block)
@@ -92,7 +93,7 @@ class Plan:
     @property
     def dtype(self):
         import torch
-        return torch.complex64 if self.precision == "c64" else torch.complex128
+        return torch.complex128 if self.precision == "c128" else torch.complex64
 
     def _check_buf(self, t, name):
         import torch

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsbt.so")
 
 DSBT_OK = 0
-DSBT_C64, DSBT_C128 = 0, 1
+DSBT_C64, DSBT_C128, DSBT_C64_FP64 = 0, 1, 2
 DSBT_K_PLAIN, DSBT_K_CORRECTED = 0, 1
 DSBT_SIGN_C, DSBT_SIGN_PRINTED_F = 0, 1
 DSBT_MODE_BATCHED, DSBT_MODE_PLAIN = 0, 1

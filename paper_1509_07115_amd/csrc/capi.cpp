@@ -113,7 +113,8 @@ struct dsbt_plan_s {
     dsbt_plan_opts opts{};
     std::vector<dsbt_channel> ch;
     int64_t elems = 0;
-    size_t elem_bytes = 8;
+    size_t elem_bytes = 8;   // data element in memory
+    size_t cmp_bytes = 8;    // complex value in the arithmetic precision (tables, LDS, phases)
     int maxN = 0, maxR = 0;
 
     // groups of channels with equal (N, l, rmax)
@@ -262,7 +263,7 @@ dsbt_status validate_channels(const dsbt_channel* ch, int nch, int precision, si
         const dsbt_channel& x = ch[c];
         if (!is_pow2(x.N) || x.N < 16 || x.N > 8192)
             return fail(DSBT_ERR_UNSUPPORTED, "channel " + std::to_string(c) + ": N must be a power of two in [16, 8192]");
-        const size_t lds = (size_t)x.N * (precision == DSBT_C128 ? 16 : 8);
+        const size_t lds = (size_t)x.N * (precision == DSBT_C64 ? 8 : 16);
         if (lds > max_lds)
             return fail(DSBT_ERR_UNSUPPORTED, "channel " + std::to_string(c) + ": N too large for LDS at this precision");
         if (x.ell < 0 || x.ell > 2 * x.N - 2 || x.ell > 255)
@@ -512,7 +513,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     P->d_items_v1 = upload_items(P->h_items_v1);
     P->d_items1 = upload_items(P->h_items1);
     P->d_scratch = (double*)P->dalloc(sizeof(double) * (nch + 1));
-    const size_t m_lds = P->elem_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
+    const size_t m_lds = P->cmp_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
     hip_check(dsbt::set_lds_limits<T>(m_lds), "set LDS limits");
     hip_check(dsbt::set_lds_limits_mfma(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
@@ -533,7 +534,7 @@ void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
     P->prof_events.emplace_back(stage, a, b);
 }
 
-template <typename T>
+template <typename T, typename S>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -542,12 +543,12 @@ void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hi
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(dsbt::launch_mstage<T>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph,
+            hip_check(dsbt::launch_mstage<T, S>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph,
                                              s), "mstage");
         });
 }
 
-template <typename T>
+template <typename T, typename S>
 void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool inverse, hipStream_t s,
                         dsbt::PhaseArgs ph) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -555,60 +556,60 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
             hip_check(dsbt::launch_mstage_mfma(P->d_items1 + c, 1, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s),
                       "mstage_mfma");
         else
-            hip_check(dsbt::launch_mstage<T>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
+            hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
     });
 }
 
-template <typename T>
+template <typename T, typename S>
 void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv,
                      dsbt::PhaseArgs pk) {
     const int nch = (int)P->ch.size();
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
             timed(P, DSBT_STAGE_SINCOS, s, [&] {
-                hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, src, dst, false, pv, s), "fstage");
+                hip_check(dsbt::launch_fstage_n<T, S>(P->ch[c].N, P->d_fchans + c, 1, src, dst, false, pv, s), "fstage");
             });
-            enqueue_mstage_one<T>(P, c, dst, dst, false, s, pk);
+            enqueue_mstage_one<T, S>(P, c, dst, dst, false, s, pk);
         }
         return;
     }
     for (auto& r : P->n_ranges)
         timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src,
+            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src,
                                                dst, false, pv, s), "fstage");
         });
-    enqueue_mstage<T>(P, dst, dst, false, s, pk);
+    enqueue_mstage<T, S>(P, dst, dst, false, s, pk);
 }
 
-template <typename T>
+template <typename T, typename S>
 void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv) {
     const int nch = (int)P->ch.size();
     dsbt::PhaseArgs none{};
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
-            enqueue_mstage_one<T>(P, c, src, dst, true, s, none);
+            enqueue_mstage_one<T, S>(P, c, src, dst, true, s, none);
             timed(P, DSBT_STAGE_SINCOS, s, [&] {
-                hip_check(dsbt::launch_fstage_n<T>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
+                hip_check(dsbt::launch_fstage_n<T, S>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
             });
         }
         return;
     }
-    enqueue_mstage<T>(P, src, dst, true, s, none);
+    enqueue_mstage<T, S>(P, src, dst, true, s, none);
     for (auto& r : P->n_ranges)
         timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_n<T>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst,
+            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst,
                                                dst, true, pv, s), "fstage");
         });
 }
 
-template <typename T>
+template <typename T, typename S>
 void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool adjoint, hipStream_t s) {
     for (int u = 0; u < nsteps; ++u) {
         const int t = adjoint ? (nsteps - 1 - u) : u;
         dsbt::PhaseArgs pv{1, adjoint ? 1 : 0, sc, t};
         dsbt::PhaseArgs pk{1, adjoint ? 1 : 0, nullptr, 0};
-        enqueue_forward<T>(P, psi, psi, s, pv, pk);
-        enqueue_inverse<T>(P, psi, psi, s, pv);
+        enqueue_forward<T, S>(P, psi, psi, s, pv, pk);
+        enqueue_inverse<T, S>(P, psi, psi, s, pv);
     }
 }
 
@@ -642,7 +643,7 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
     return guarded([&]() -> dsbt_status {
         dsbt_plan_opts opts{};
         if (o) opts = *o;
-        if (opts.precision != DSBT_C64 && opts.precision != DSBT_C128)
+        if (opts.precision != DSBT_C64 && opts.precision != DSBT_C128 && opts.precision != DSBT_C64_FP64)
             return fail(DSBT_ERR_INVALID_ARG, "unknown precision");
         if (opts.kinetic != DSBT_K_PLAIN) return fail(DSBT_ERR_UNSUPPORTED, "corrected kinetic momenta not built in");
         if (opts.mode != DSBT_MODE_BATCHED && opts.mode != DSBT_MODE_PLAIN)
@@ -664,14 +665,15 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
         P->opts = opts;
         P->precision = opts.precision;
         P->elem_bytes = opts.precision == DSBT_C128 ? 16 : 8;
+        P->cmp_bytes = opts.precision == DSBT_C64 ? 8 : 16;
         P->ch.assign(ch, ch + nch);
         for (auto& x : P->ch) P->elems = std::max<int64_t>(P->elems, x.offset + x.N);
         try {
             hipStream_t s = (hipStream_t)stream;
-            if (P->precision == DSBT_C128)
-                build_plan<double>(P, s);
-            else
+            if (P->precision == DSBT_C64)
                 build_plan<float>(P, s);
+            else
+                build_plan<double>(P, s);   // complex128, or complex64 data with FP64 arithmetic
             hip_check(hipStreamSynchronize(s), "plan sync");
         } catch (...) {
             P->release();
@@ -722,9 +724,11 @@ dsbt_status dsbt_forward(dsbt_plan p, const void* psi, void* b, void* stream) {
     return guarded([&]() -> dsbt_status {
         dsbt::PhaseArgs none{};
         if (p->precision == DSBT_C128)
-            enqueue_forward<double>(p, psi, b, (hipStream_t)stream, none, none);
+            enqueue_forward<double, double>(p, psi, b, (hipStream_t)stream, none, none);
+        else if (p->precision == DSBT_C64_FP64)
+            enqueue_forward<double, float>(p, psi, b, (hipStream_t)stream, none, none);
         else
-            enqueue_forward<float>(p, psi, b, (hipStream_t)stream, none, none);
+            enqueue_forward<float, float>(p, psi, b, (hipStream_t)stream, none, none);
         return DSBT_OK;
     });
 }
@@ -734,9 +738,11 @@ dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream) {
     return guarded([&]() -> dsbt_status {
         dsbt::PhaseArgs none{};
         if (p->precision == DSBT_C128)
-            enqueue_inverse<double>(p, b, psi, (hipStream_t)stream, none);
+            enqueue_inverse<double, double>(p, b, psi, (hipStream_t)stream, none);
+        else if (p->precision == DSBT_C64_FP64)
+            enqueue_inverse<double, float>(p, b, psi, (hipStream_t)stream, none);
         else
-            enqueue_inverse<float>(p, b, psi, (hipStream_t)stream, none);
+            enqueue_inverse<float, float>(p, b, psi, (hipStream_t)stream, none);
         return DSBT_OK;
     });
 }
@@ -746,7 +752,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DSBT_ERR_INVALID_ARG, "dt must be positive");
     return guarded([&]() -> dsbt_status {
         const int64_t n = p->elems;
-        const bool fp64 = p->precision == DSBT_C128;
+        const bool fp64 = p->precision != DSBT_C64;   // phases in the arithmetic precision
         std::vector<double> ang(n, 0.0);
         for (auto& x : p->ch) {
             for (int i = 0; i < x.N; ++i) {
@@ -778,7 +784,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
         }
         // refresh descriptors with the phase pointers
         for (size_t c = 0; c < p->ch.size(); ++c) {
-            p->h_fchans[c].vphase = static_cast<const unsigned char*>(p->d_vphase) + p->elem_bytes * p->ch[c].offset;
+            p->h_fchans[c].vphase = static_cast<const unsigned char*>(p->d_vphase) + p->cmp_bytes * p->ch[c].offset;
             p->h_fchans[c].vangle = p->d_vangle + p->ch[c].offset;
         }
         hip_check(hipMemcpy(p->d_fchans, p->h_fchans.data(), sizeof(dsbt::FChan) * p->ch.size(),
@@ -820,9 +826,11 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
         const bool adj = (flags & DSBT_STEP_ADJOINT) != 0;
         auto enqueue = [&](hipStream_t q) {
             if (p->precision == DSBT_C128)
-                enqueue_steps<double>(p, psi, nsteps, s, adj, q);
+                enqueue_steps<double, double>(p, psi, nsteps, s, adj, q);
+            else if (p->precision == DSBT_C64_FP64)
+                enqueue_steps<double, float>(p, psi, nsteps, s, adj, q);
             else
-                enqueue_steps<float>(p, psi, nsteps, s, adj, q);
+                enqueue_steps<float, float>(p, psi, nsteps, s, adj, q);
         };
         if (!(flags & DSBT_STEP_GRAPH)) {
             enqueue(st);

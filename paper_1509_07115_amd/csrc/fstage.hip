@@ -201,10 +201,17 @@ __device__ __forceinline__ double2 phase_factor<double2>(const FChan& c, int i, 
 
 constexpr int fstage_threads(int N) { return N / 8 >= 256 ? N / 8 : 256; }
 
-template <typename T, int N, bool INV>
+// Complex value conversion between the storage and the arithmetic precision.
+template <typename V, typename W> __device__ __forceinline__ V to_prec(W w) {
+    return {(decltype(V{}.x))w.x, (decltype(V{}.x))w.y};
+}
+
+// T: arithmetic and table precision; S: data precision in memory.
+template <typename T, typename S, int N, bool INV>
 __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
-                                                const typename CV<T>::t* src, typename CV<T>::t* dst, PhaseArgs ph) {
+                                                const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph) {
     using V = typename CV<T>::t;
+    using SV = typename CV<S>::t;
     constexpr int TPC = N / 8;              // threads per channel
     constexpr int PADN = N + N / 32;        // padded LDS slots per channel
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -222,11 +229,11 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     const Split<T> sc0 = split_const<T>(INV ? d0 : 0.5 * d0), sc1 = split_const<T>(INV ? d1 : 0.5 * d1);
     if constexpr (!INV) {
         if (live) {
-            const V* x = src + c.off;
+            const SV* x = src + c.off;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = t + u * TPC;
-                V a = x[i];
+                V a = to_prec<V>(x[i]);
                 if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
                 if (c.p && (i & 1)) a = {-a.x, -a.y};
                 buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))] = a;
@@ -235,7 +242,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         lds_barrier();
         fft_n<T, N>(buf, tw, t);
         if (live) {
-            V* y = dst + c.off;
+            SV* y = dst + c.off;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int k = t + u * TPC;
@@ -244,17 +251,17 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 // w a + conj(w) b
                 V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
                 X = f_scale(X, k == 0 ? sc0 : sc1);
-                y[c.p ? (N - 1 - k) : k] = X;
+                y[c.p ? (N - 1 - k) : k] = to_prec<SV>(X);
             }
         }
     } else {
         if (live) {
-            const V* f = src + c.off;
+            const SV* f = src + c.off;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int j = t + u * TPC;
                 const int k = c.p ? (N - 1 - j) : j;
-                buf[pidx(k)] = f_scale(f[j], k == 0 ? sc0 : sc1);
+                buf[pidx(k)] = f_scale(to_prec<V>(f[j]), k == 0 ? sc0 : sc1);
             }
         }
         lds_barrier();
@@ -276,14 +283,14 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         lds_barrier();
         fft_n<T, N>(buf, tw, t);
         if (live) {
-            V* x = dst + c.off;
+            SV* x = dst + c.off;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = t + u * TPC;
                 V a = buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))];
                 if (c.p && (i & 1)) a = {-a.x, -a.y};
                 if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
-                x[i] = a;
+                x[i] = to_prec<SV>(a);
             }
         }
     }
@@ -296,44 +303,37 @@ static inline void fstage_shape(int N, int& cpb, int& threads) {
     threads = tpc * cpb;
 }
 
-template <typename T, bool INV>
+template <typename T, typename S, bool INV>
 static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void* dst, PhaseArgs ph, hipStream_t s) {
     using V = typename CV<T>::t;
+    using SV = typename CV<S>::t;
     int cpb, threads;
     fstage_shape(N, cpb, threads);
     const int blocks = (nch + cpb - 1) / cpb;
     const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
 #define DSBT_FN(NN)                                                                                     \
     case NN:                                                                                            \
-        hipLaunchKernelGGL((fstage_n<T, NN, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,   \
-                           (const V*)src, (V*)dst, ph);                                                 \
+        hipLaunchKernelGGL((fstage_n<T, S, NN, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb, \
+                           (const SV*)src, (SV*)dst, ph);                                               \
         break;
     switch (N) {
         DSBT_FN(16) DSBT_FN(32) DSBT_FN(64) DSBT_FN(128) DSBT_FN(256) DSBT_FN(512) DSBT_FN(1024)
-        DSBT_FN(2048)
-        case 4096:
-            hipLaunchKernelGGL((fstage_n<T, 4096, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,
-                               (const V*)src, (V*)dst, ph);
-            break;
-        case 8192:
-            hipLaunchKernelGGL((fstage_n<T, 8192, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb,
-                               (const V*)src, (V*)dst, ph);
-            break;
+        DSBT_FN(2048) DSBT_FN(4096) DSBT_FN(8192)
         default: return hipErrorInvalidValue;
     }
 #undef DSBT_FN
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s) {
     if (nch <= 0) return hipSuccess;
-    return inverse ? launch_n<T, true>(N, d_chans, nch, src, dst, ph, s)
-                   : launch_n<T, false>(N, d_chans, nch, src, dst, ph, s);
+    return inverse ? launch_n<T, S, true>(N, d_chans, nch, src, dst, ph, s)
+                   : launch_n<T, S, false>(N, d_chans, nch, src, dst, ph, s);
 }
 
-template <typename T, bool INV>
+template <typename T, typename S, bool INV>
 static hipError_t lds_attr_all() {
     using V = typename CV<T>::t;
     hipError_t e = hipSuccess;
@@ -343,28 +343,36 @@ static hipError_t lds_attr_all() {
         const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    set((const void*)fstage_n<T, 16, INV>, 16);
-    set((const void*)fstage_n<T, 32, INV>, 32);
-    set((const void*)fstage_n<T, 64, INV>, 64);
-    set((const void*)fstage_n<T, 128, INV>, 128);
-    set((const void*)fstage_n<T, 256, INV>, 256);
-    set((const void*)fstage_n<T, 512, INV>, 512);
-    set((const void*)fstage_n<T, 1024, INV>, 1024);
-    set((const void*)fstage_n<T, 2048, INV>, 2048);
-    set((const void*)fstage_n<T, 4096, INV>, 4096);
-    set((const void*)fstage_n<T, 8192, INV>, 8192);
+    set((const void*)fstage_n<T, S, 16, INV>, 16);
+    set((const void*)fstage_n<T, S, 32, INV>, 32);
+    set((const void*)fstage_n<T, S, 64, INV>, 64);
+    set((const void*)fstage_n<T, S, 128, INV>, 128);
+    set((const void*)fstage_n<T, S, 256, INV>, 256);
+    set((const void*)fstage_n<T, S, 512, INV>, 512);
+    set((const void*)fstage_n<T, S, 1024, INV>, 1024);
+    set((const void*)fstage_n<T, S, 2048, INV>, 2048);
+    set((const void*)fstage_n<T, S, 4096, INV>, 4096);
+    set((const void*)fstage_n<T, S, 8192, INV>, 8192);
     return e;
 }
 
 template <typename T>
 hipError_t set_lds_limits_fstage_n() {
-    hipError_t e = lds_attr_all<T, false>();
-    if (e != hipSuccess) return e;
-    return lds_attr_all<T, true>();
+    hipError_t e = lds_attr_all<T, T, false>();
+    if (e == hipSuccess) e = lds_attr_all<T, T, true>();
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (e == hipSuccess) e = lds_attr_all<double, float, false>();
+        if (e == hipSuccess) e = lds_attr_all<double, float, true>();
+    }
+    return e;
 }
 
-template hipError_t launch_fstage_n<float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs, hipStream_t);
-template hipError_t launch_fstage_n<double>(int, const FChan*, int, const void*, void*, bool, PhaseArgs, hipStream_t);
+template hipError_t launch_fstage_n<float, float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs,
+                                                  hipStream_t);
+template hipError_t launch_fstage_n<double, double>(int, const FChan*, int, const void*, void*, bool, PhaseArgs,
+                                                    hipStream_t);
+template hipError_t launch_fstage_n<double, float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs,
+                                                   hipStream_t);
 template hipError_t set_lds_limits_fstage_n<float>();
 template hipError_t set_lds_limits_fstage_n<double>();
 

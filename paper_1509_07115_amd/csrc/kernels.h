@@ -79,14 +79,17 @@ __device__ __forceinline__ void lds_barrier() {
 
 // Launchers.  T = float (complex64 data) or double (complex128 data).
 
-// Sine/cosine stage for channels that all have N points (compile-time FFT size).
-template <typename T>
+// Sine/cosine stage for channels that all have N points (compile-time FFT
+// size); T arithmetic and table precision, S data precision.
+template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s);
 template <typename T>
 hipError_t set_lds_limits_fstage_n();
 
-template <typename T>
+// Generic moment stage: T arithmetic and table precision, S data precision
+// (float/float, double/double, or double arithmetic on complex64 data).
+template <typename T, typename S>
 hipError_t launch_mstage(const MItem* d_items, int nitems, int maxR, const void* src, void* dst,
                          bool inverse, PhaseArgs ph, hipStream_t s);
 

@@ -9,6 +9,8 @@
 // channels with the same (l, N) share each load of a table entry.
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace dsbt {
 
 template <typename T> struct C2;
@@ -33,12 +35,19 @@ template <typename V> __device__ __forceinline__ V cmul_posi(V a) { return {-a.y
 // LDS holds X[c][0..R): the tile data (B) followed by the moments (k).
 // ---------------------------------------------------------------------------
 
-template <typename T, int RP>
+// Complex value conversion between the storage and the arithmetic precision.
+template <typename V, typename W> __device__ __forceinline__ V cvt(W w) {
+    return {(decltype(V{}.x))w.x, (decltype(V{}.x))w.y};
+}
+
+// T: arithmetic (and table) precision; S: data precision in memory.
+template <typename T, typename S, int RP>
 __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items,
-                                                 const typename C2<T>::t* src,
-                                                 typename C2<T>::t* dst,
+                                                 const typename C2<S>::t* src,
+                                                 typename C2<S>::t* dst,
                                                  int inverse, PhaseArgs ph) {
     using V = typename C2<T>::t;
+    using SV = typename C2<S>::t;
     constexpr int NS = kBlock / RP;
     constexpr int CPT = (kMaxChanPerItem + NS - 1) / NS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -56,7 +65,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
         const int ch = e / k, kk = e % k;
         V v = {(T)0, (T)0};
         if (inverse) {
-            v = src[it.off[ch] + kk];
+            v = cvt<V>(src[it.off[ch] + kk]);
             if (ph.use && it.kphase) {
                 V z = static_cast<const V*>(it.kphase)[kk];
                 if (ph.conj) z.y = -z.y;
@@ -72,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
         for (int e = tid; e < nch * B; e += kBlock) {
             const int ch = e / B, s = e % B;
             const int slot = J * B + s;
-            V v = src[it.off[ch] + slot];
+            V v = cvt<V>(src[it.off[ch] + slot]);
             if (!inverse) {
                 if (slot == 0) v = cscale(v, w0);
             } else if (ph.use && it.kphase) {
@@ -122,7 +131,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
                     } else if (slot == 0) {
                         v = cscale(v, w0);
                     }
-                    dst[it.off[ch] + slot] = v;
+                    dst[it.off[ch] + slot] = cvt<SV>(v);
                 }
             }
         }
@@ -137,7 +146,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
                 if (ph.conj) z.y = -z.y;
                 v = cmul(v, z);
             }
-            dst[it.off[ch] + kk] = v;
+            dst[it.off[ch] + kk] = cvt<SV>(v);
         }
     }
 }
@@ -189,21 +198,22 @@ __global__ void __launch_bounds__(kBlock) sum_partials(const double* __restrict_
 // launchers
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, typename S>
 hipError_t launch_mstage(const MItem* d_items, int nitems, int maxR, const void* src, void* dst,
                          bool inverse, PhaseArgs ph, hipStream_t s) {
+    using SV = typename C2<S>::t;
     using V = typename C2<T>::t;
     if (nitems <= 0) return hipSuccess;
     const size_t lds = sizeof(V) * (size_t)kMaxChanPerItem * maxR;
     if (maxR <= 64) {
-        hipLaunchKernelGGL((mstage<T, 64>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const V*)src,
-                           (V*)dst, inverse ? 1 : 0, ph);
+        hipLaunchKernelGGL((mstage<T, S, 64>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const SV*)src,
+                           (SV*)dst, inverse ? 1 : 0, ph);
     } else if (maxR <= 128) {
-        hipLaunchKernelGGL((mstage<T, 128>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const V*)src,
-                           (V*)dst, inverse ? 1 : 0, ph);
+        hipLaunchKernelGGL((mstage<T, S, 128>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const SV*)src,
+                           (SV*)dst, inverse ? 1 : 0, ph);
     } else {
-        hipLaunchKernelGGL((mstage<T, 256>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const V*)src,
-                           (V*)dst, inverse ? 1 : 0, ph);
+        hipLaunchKernelGGL((mstage<T, S, 256>), dim3(nitems), dim3(kBlock), lds, s, d_items, (const SV*)src,
+                           (SV*)dst, inverse ? 1 : 0, ph);
     }
     return hipGetLastError();
 }
@@ -220,18 +230,29 @@ hipError_t launch_grad_s(const FChan* d_chans, int nch, const void* p0, const vo
 
 template <typename T>
 hipError_t set_lds_limits(size_t mstage_bytes) {
-    hipError_t e;
-    e = hipFuncSetAttribute((const void*)mstage<T, 64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mstage_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)mstage<T, 128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mstage_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)mstage<T, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mstage_bytes);
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mstage_bytes);
+    };
+    set((const void*)mstage<T, T, 64>);
+    set((const void*)mstage<T, T, 128>);
+    set((const void*)mstage<T, T, 256>);
+    if constexpr (std::is_same<T, double>::value) {
+        set((const void*)mstage<double, float, 64>);
+        set((const void*)mstage<double, float, 128>);
+        set((const void*)mstage<double, float, 256>);
+    }
+    return e;
 }
 
 template hipError_t set_lds_limits<float>(size_t);
 template hipError_t set_lds_limits<double>(size_t);
-template hipError_t launch_mstage<float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs, hipStream_t);
-template hipError_t launch_mstage<double>(const MItem*, int, int, const void*, void*, bool, PhaseArgs, hipStream_t);
+template hipError_t launch_mstage<float, float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                hipStream_t);
+template hipError_t launch_mstage<double, double>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                  hipStream_t);
+template hipError_t launch_mstage<double, float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                 hipStream_t);
 template hipError_t launch_grad_s<float>(const FChan*, int, const void*, const void*, const void*, const void*,
                                          double*, double*, hipStream_t);
 template hipError_t launch_grad_s<double>(const FChan*, int, const void*, const void*, const void*, const void*,
