@@ -92,7 +92,8 @@ enum { DSBT_PLAN_ON_DEVICE = 0, DSBT_PLAN_ON_HOST = 1 };
 
 typedef struct {
     int32_t precision;    /* DSBT_C64 (default), DSBT_C128 or DSBT_C64_FP64 */
-    int32_t kinetic;      /* DSBT_K_PLAIN (default) or DSBT_K_CORRECTED */
+    int32_t kinetic;      /* DSBT_K_PLAIN (default) or DSBT_K_CORRECTED: momenta of the kinetic
+                             diagonal, see dsbt_kinetic_momenta */
     int32_t sign;         /* DSBT_SIGN_C (default): b_n ~ c_l(k_n) sqrt(w_n) */
     int32_t mode;         /* DSBT_MODE_BATCHED (default) or DSBT_MODE_PLAIN */
     int32_t plan_where;   /* DSBT_PLAN_ON_DEVICE (default): the FP64 DLOP recurrences and tile
@@ -186,6 +187,15 @@ dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
  * for the call and frees it.  Returns DSBT_ERR_NO_DEVICE without a device. */
 dsbt_status dsbt_device_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
                                    int64_t out_len, int64_t* needed, void* stream);
+
+/* The momenta k_n of the kinetic diagonal K_n = k_n^2/2 that dsbt_set_potential
+ * uses for a channel (N, ell, rmax), in slot order (N doubles written to k):
+ * the completion rows n < n_0 take N dk (their energy is the top of the grid);
+ * regular rows take n dk (DSBT_K_PLAIN, eq. tilde_k_grid) or x_j / rmax
+ * (DSBT_K_CORRECTED, eq. kcorr), x_j the j-th positive root, j = n - n_0 + 1,
+ * of chi_l(x) = x j_l(x) for even l and of chi_l'(x) for odd l (Sec. 3).
+ * Host computation in FP64. */
+dsbt_status dsbt_kinetic_momenta(int32_t N, int32_t ell, double rmax, int32_t kinetic, double* k);
 
 const char* dsbt_status_string(dsbt_status s);
 const char* dsbt_last_error(void);

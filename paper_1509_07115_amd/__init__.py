@@ -43,11 +43,12 @@ class Plan:
     (complex64 data, FP64 arithmetic and tables).
     mode: "batched" (default) or "plain" (one launch per channel and stage).
     plan_where: "device" (default, FP64 plan kernels on the GPU) or "host".
+    kinetic: "plain" (k_n = n dk) or "corrected" (roots of eq. kcorr) momenta of the step.
     """
 
     def __init__(self, channels: Sequence, precision: str = "c64", mode: str = "batched", tile: int = 0,
-                 chans_per_block: int = 0, sign: bool = True, plan_where: str = "device", stream=None,
-                 _create=True):
+                 chans_per_block: int = 0, sign: bool = True, plan_where: str = "device", kinetic: str = "plain",
+                 stream=None, _create=True):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         self.precision = precision
@@ -57,13 +58,13 @@ class Plan:
         arr = (_lib.Channel * len(self.channels))()
         for i, (N, ell, rmax, off) in enumerate(self.channels):
             arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
-        opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where)
+        opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where, kinetic)
         _lib.check(self._lib.dsbt_plan_create(ctypes.byref(self._h), arr, len(self.channels), ctypes.byref(opts),
                                               _stream_handle(stream)), "dsbt_plan_create")
         self._info()
 
     @staticmethod
-    def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device"):
+    def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device", kinetic="plain"):
         o = _lib.PlanOpts()
         o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128, "c64x": _lib.DSBT_C64_FP64}[precision]
         o.mode = {"batched": _lib.DSBT_MODE_BATCHED, "plain": _lib.DSBT_MODE_PLAIN}[mode]
@@ -71,6 +72,7 @@ class Plan:
         o.chans_per_block = int(chans_per_block)
         o.sign = _lib.DSBT_SIGN_C if sign else _lib.DSBT_SIGN_PRINTED_F
         o.plan_where = {"device": _lib.DSBT_PLAN_ON_DEVICE, "host": _lib.DSBT_PLAN_ON_HOST}[plan_where]
+        o.kinetic = {"plain": _lib.DSBT_K_PLAIN, "corrected": _lib.DSBT_K_CORRECTED}[kinetic]
         return o
 
     @classmethod
@@ -207,3 +209,13 @@ def device_ftb_tables(N: int, ell: int, B: int, stream=None) -> np.ndarray:
     k = (ell + 1) // 2
     R = B + k
     return out.reshape(N // B, R, R)
+
+
+def kinetic_momenta(N: int, ell: int, rmax: float, kinetic: str = "plain") -> np.ndarray:
+    """Momenta of the kinetic diagonal in slot order (``dsbt_kinetic_momenta``), host FP64."""
+    lib = _lib.load()
+    out = np.empty(N, dtype=np.float64)
+    kin = {"plain": _lib.DSBT_K_PLAIN, "corrected": _lib.DSBT_K_CORRECTED}[kinetic]
+    _lib.check(lib.dsbt_kinetic_momenta(N, ell, float(rmax), kin, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "dsbt_kinetic_momenta")
+    return out

@@ -25,7 +25,7 @@ EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_kinetic_step",
     "dsbt_step_grad_s", "dsbt_profile_enable", "dsbt_profile_read", "dsbt_host_ftb_tables",
-    "dsbt_device_ftb_tables",
+    "dsbt_device_ftb_tables", "dsbt_kinetic_momenta",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
         "dsbt_profile_read": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "dsbt_host_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]),
         "dsbt_device_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64), P]),
+        "dsbt_kinetic_momenta": (i32, [i32, i32, dbl, i32, ctypes.POINTER(dbl)]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),
     }

@@ -645,7 +645,8 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
         if (o) opts = *o;
         if (opts.precision != DSBT_C64 && opts.precision != DSBT_C128 && opts.precision != DSBT_C64_FP64)
             return fail(DSBT_ERR_INVALID_ARG, "unknown precision");
-        if (opts.kinetic != DSBT_K_PLAIN) return fail(DSBT_ERR_UNSUPPORTED, "corrected kinetic momenta not built in");
+        if (opts.kinetic != DSBT_K_PLAIN && opts.kinetic != DSBT_K_CORRECTED)
+            return fail(DSBT_ERR_INVALID_ARG, "unknown kinetic option");
         if (opts.mode != DSBT_MODE_BATCHED && opts.mode != DSBT_MODE_PLAIN)
             return fail(DSBT_ERR_INVALID_ARG, "unknown mode");
         if (opts.plan_where != DSBT_PLAN_ON_DEVICE && opts.plan_where != DSBT_PLAN_ON_HOST)
@@ -772,10 +773,14 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
         const double pi = 3.14159265358979323846;
         for (auto& g : p->groups) {
             const double dk = pi / g.rmax;
-            std::vector<double> ka(g.N);
+            std::vector<double> ka(g.N), kc;
+            if (p->opts.kinetic == DSBT_K_CORRECTED) {
+                kc.resize(g.N);
+                dsbt::corrected_momenta(g.N, g.ell, g.rmax, kc.data());
+            }
             for (int j = 0; j < g.N; ++j) {
                 const int nidx = j + g.p;
-                const double kn = (j < g.k) ? g.N * dk : nidx * dk;
+                const double kn = !kc.empty() ? kc[j] : ((j < g.k) ? g.N * dk : nidx * dk);
                 ka[j] = 0.5 * kn * kn * dt;
             }
             const std::vector<unsigned char> kp = phase_table(ka, fp64);
@@ -967,6 +972,24 @@ dsbt_status dsbt_device_ftb_tables(int32_t N, int32_t ell, int32_t B, double* ou
         std::vector<double> blk;
         device_blocks(ell, B, NT, scratch.ptr, blk, (hipStream_t)stream);
         std::memcpy(out, blk.data(), sizeof(double) * blk.size());
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_kinetic_momenta(int32_t N, int32_t ell, double rmax, int32_t kinetic, double* k) {
+    if (!k) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!is_pow2(N) || N < 2) return fail(DSBT_ERR_UNSUPPORTED, "N must be a power of two");
+    if (ell < 0 || ell > 2 * N - 2 || ell > 255) return fail(DSBT_ERR_UNSUPPORTED, "need 0 <= l <= min(2N-2, 255)");
+    if (!(rmax > 0.0)) return fail(DSBT_ERR_INVALID_ARG, "rmax must be positive");
+    if (kinetic != DSBT_K_PLAIN && kinetic != DSBT_K_CORRECTED) return fail(DSBT_ERR_INVALID_ARG, "unknown kinetic option");
+    return guarded([&]() -> dsbt_status {
+        const double dk = 3.14159265358979323846 / rmax;
+        const int p = dsbt::parity_p(ell), kx = dsbt::n_extra(ell);
+        if (kinetic == DSBT_K_CORRECTED) {
+            dsbt::corrected_momenta(N, ell, rmax, k);
+        } else {
+            for (int j = 0; j < N; ++j) k[j] = (j < kx) ? N * dk : (j + p) * dk;
+        }
         return DSBT_OK;
     });
 }

@@ -221,6 +221,83 @@ void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p,
     }
 }
 
+// j_l(x) and j_{l+1}(x), x > 0, FP64: upward recurrence from j_0, j_1 where it
+// is stable (x well above l), else Miller's downward recurrence normalised by
+// j_0 (or j_1 near a zero of j_0).
+static void sph_bessel_pair(int l, double x, double& jl, double& jl1) {
+    const double s = std::sin(x), c = std::cos(x);
+    const double j0 = s / x, j1 = s / (x * x) - c / x;
+    if (x > l + 25.0) {
+        double a = j0, b = j1;
+        for (int n = 1; n <= l; ++n) {
+            const double nb = (2.0 * n + 1.0) / x * b - a;
+            a = b;
+            b = nb;
+        }
+        jl = a;
+        jl1 = b;
+        return;
+    }
+    const int L = l + 30 + (int)(x + 10.0 * std::sqrt(l + x + 10.0));
+    double fp = 0.0, f = 1e-300, f0 = 0.0, f1 = 0.0, fl = 0.0, fl1 = 0.0;
+    for (int n = L; n >= 1; --n) {   // f is f_n, fp is f_{n+1}; produce f_{n-1}
+        if (n == l + 1) fl1 = f;
+        if (n == l) fl = f;
+        if (n == 1) f1 = f;
+        const double fm = (2.0 * n + 1.0) / x * f - fp;
+        fp = f;
+        f = fm;
+        if (std::fabs(f) > 1e250) {   // rescale everything kept so far
+            f *= 1e-250;
+            fp *= 1e-250;
+            fl *= 1e-250;
+            fl1 *= 1e-250;
+            f1 *= 1e-250;
+        }
+    }
+    f0 = f;
+    if (l == 0) fl = f0;
+    const double scale = std::fabs(j0) > std::fabs(j1) ? j0 / f0 : j1 / f1;
+    jl = fl * scale;
+    jl1 = fl1 * scale;
+}
+
+void corrected_momenta(int N, int ell, double rmax, double* k) {
+    const int p = parity_p(ell), kx = n_extra(ell), n0 = n0_of(ell);
+    const int need = N + p - 1 - n0 + 1;   // regular rows n0 .. N_l
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < kx; ++j) k[j] = N * pi / rmax;   // completion rows keep the top momentum
+    // even l: roots of chi_l(x) = x j_l(x); odd l: roots of chi_l'(x) = (l+1) j_l(x) - x j_{l+1}(x)
+    auto f = [&](double x) {
+        double a, b;
+        sph_bessel_pair(ell, x, a, b);
+        return p ? x * a : (ell + 1.0) * a - x * b;
+    };
+    const double h = 0.05;
+    double x0 = 1e-3, f0 = f(x0);
+    int found = 0;
+    while (found < need) {
+        const double x1 = x0 + h, f1 = f(x1);
+        if ((f0 < 0.0 && f1 > 0.0) || (f0 > 0.0 && f1 < 0.0)) {
+            double a = x0, b = x1, fa = f0;
+            for (int it = 0; it < 80 && b - a > 1e-14 * b; ++it) {
+                const double m = 0.5 * (a + b), fm = f(m);
+                if ((fa < 0.0) == (fm < 0.0)) {
+                    a = m;
+                    fa = fm;
+                } else {
+                    b = m;
+                }
+            }
+            k[kx + found] = 0.5 * (a + b) / rmax;
+            ++found;
+        }
+        x0 = x1;
+        f0 = f1;
+        if (x0 > (N + ell + 8.0) * pi) throw std::runtime_error("corrected momenta: root scan ran past its range");
+    }
+}
+
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
     const double pi = 3.14159265358979323846;
     // Stockham passes of radix 8, then one of radix 2 or 4; the pass with

@@ -48,6 +48,12 @@ void build_ftb_blocks(int ell, int B, int NT, std::vector<double>& blocks, int n
 void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p, int NT, int NB, bool inverse,
                          std::vector<double>& out);
 
+// Momenta k of the kinetic diagonal in slot order (N values): the completion
+// rows take N dk; regular row n takes x_j / rmax with x_j the j-th positive
+// root (j = n - n0 + 1) of chi_l(x) = x j_l(x) for even l or of chi_l'(x) for
+// odd l (Sec. 3, eq. kcorr), FP64, bracketed on a scan from x = 0 and bisected.
+void corrected_momenta(int N, int ell, double rmax, double* k);
+
 // FP64 tables of the size-N transform as interleaved (re, im): tw, the pass
 // tables of the FFT (for each Stockham pass with span Ns > 1 and radix R, in
 // pass order, Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R)); radix 8 then

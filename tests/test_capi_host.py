@@ -91,3 +91,20 @@ def test_host_tables_are_independent_of_N(built_lib):
     a = host_ftb_tables(128, 21, 16)
     b = host_ftb_tables(512, 21, 16)
     assert np.array_equal(a, b[: a.shape[0]])
+
+
+@pytest.mark.parametrize("N,ell,rmax", [(64, 0, 12.8), (64, 1, 12.8), (64, 2, 12.8), (128, 7, 25.6),
+                                        (256, 31, 51.2), (512, 64, 102.4), (1024, 127, 204.8)])
+def test_corrected_momenta_match_oracle_roots(built_lib, N, ell, rmax):
+    # eq. kcorr: the library's FP64 root scan and bisection against the oracle's
+    # scan and Brent refinement of SciPy's spherical_jn
+    from oracle import sbf
+    from paper_1509_07115_amd import kinetic_momenta
+    k = kinetic_momenta(N, ell, rmax, "corrected")
+    kx = odsbt.n_extra(ell)
+    assert np.all(k[:kx] == N * odsbt.delta_k(rmax))
+    ref = sbf.corrected_momenta(N, rmax, ell)
+    assert np.max(np.abs(k[kx:] - ref)) < 1e-10 * np.max(ref)
+    plain = kinetic_momenta(N, ell, rmax, "plain")
+    p = odsbt.parity_p(ell)
+    assert np.allclose(plain[kx:], np.arange(kx + p, N + p) * odsbt.delta_k(rmax), rtol=1e-15, atol=0)

@@ -225,3 +225,22 @@ def test_tdse_1000_steps_c64_fp64_arithmetic_norm():
     n2 = float(torch.sum(torch.abs(x.to(torch.complex128)) ** 2).item())
     print(f"complex64 data, FP64 arithmetic: norm drift after 1000 steps {abs(n2 - 1.0):.3e}")
     assert abs(n2 - 1.0) < 1e-6, n2
+
+
+@pytest.mark.parametrize("precision,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_corrected_kinetic_step_matches_oracle(precision, tol):
+    # the step with the corrected momenta of eq. kcorr (completion rows keep
+    # (N dk)^2/2) against the dense oracle step with the same energies
+    w = workloads.tdse(seed=6, N=256, rmax=25.6, lmax=4, dt=0.01, small=0.1)
+    plan = Plan(w.channels, precision=precision, kinetic="corrected")
+    plan.set_potential(w.extra["V"], w.extra["dt"])
+    x = dev(w.psi, plan.dtype)
+    plan.kinetic_step(x, 5)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy().astype(np.complex128)
+    for N, ell, rmax, off in w.channels:
+        V = w.extra["V"][off:off + N]
+        E = tdse.kinetic_energies(N, rmax, ell, corrected=True)
+        ref = tdse.propagate(w.psi[off:off + N], ell, V, E, w.extra["dt"], np.ones(5))
+        err = np.linalg.norm(got[off:off + N] - ref) / np.linalg.norm(ref)
+        assert err < tol, (ell, err)
