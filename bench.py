@@ -117,6 +117,83 @@ def cpu_baseline(w, reps=300):
                       f"with all m ({pts // reps} points per pass, N={N}), {spent:.1f} s; matrix build excluded"}
 
 
+def _timed(fn, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_workloads(progress):
+    """The uneven batch, the 1000-step split-operator propagation and the adjoint
+    pass (synthetic seeded inputs of the same shapes), timed on the GPU."""
+    import time as _t
+    import numpy as np
+    import torch
+    from paper_1509_07115_amd import Plan, workloads
+    from paper_1509_07115_amd.autograd import propagate
+    res = {}
+    # uneven batch: 512 transforms, N in 512..8192, l in 0..127, rmax = 0.05 N
+    progress("uneven batch")
+    w = workloads.uneven()
+    t = _t.perf_counter()
+    plan = Plan(w.channels)
+    t_plan = _t.perf_counter() - t
+    x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+    b, y = plan.empty(), plan.empty()
+    step = lambda: (plan.forward(x, b), plan.inverse(b, y))
+    step()
+    ms = _timed(step, 10)
+    rt = float(max(torch.linalg.vector_norm(y[o:o + N] - x[o:o + N]).item() / torch.linalg.vector_norm(x[o:o + N]).item()
+                   for N, _, _, o in w.channels))
+    res["uneven_batch"] = {"workload": w.name, "points": w.points, "ms_per_fwd_inv": ms,
+                           "points_per_s": w.points / (ms * 1e-3), "transforms_per_s": len(w.channels) / (ms * 1e-3),
+                           "plan_s_fp64_on_gpu": t_plan, "roundtrip_max_rel": rt}
+    del plan, x, b, y
+    # split-operator propagation: 1000 steps from a captured graph
+    progress("1000-step split-operator propagation")
+    w = workloads.tdse()
+    for prec in ("c64", "c64x"):
+        plan = Plan(w.channels, precision=prec)
+        plan.set_potential(w.extra["V"], w.extra["dt"])
+        x0 = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+        x = x0.clone()
+        plan.kinetic_step(x, 1000, graph=True)      # captures, runs once
+        x.copy_(x0)
+        ms = _timed(lambda: plan.kinetic_step(x, 1000, graph=True), 1)
+        n2 = float(torch.sum(torch.abs(x.to(torch.complex128)) ** 2).item())
+        res[f"tdse_1000_steps_{prec}"] = {"workload": w.name, "ms_per_1000_steps": ms, "norm_drift": abs(n2 - 1.0)}
+        del plan
+    # adjoint through 200 steps, checkpoints every 20, against the plain per-channel form
+    progress("adjoint pass")
+    w = workloads.adjoint()
+    plan = Plan(w.channels)
+    plan.set_potential(w.extra["V"], w.extra["dt"])
+    phi = torch.from_numpy(w.extra["phi"]).to(torch.complex64).cuda()
+    s = torch.from_numpy(w.extra["s"]).to(torch.float32).cuda()
+
+    def grad_pass(pl):
+        p0 = torch.from_numpy(w.psi).to(torch.complex64).cuda().requires_grad_(True)
+        st = s.clone().requires_grad_(True)
+        z = torch.vdot(phi, propagate(pl, p0, st, checkpoint_every=20))
+        ((z * z.conj()).real).backward()
+    grad_pass(plan)
+    ms = _timed(lambda: grad_pass(plan), 2)
+    pplan = Plan(w.channels, mode="plain")
+    pplan.set_potential(w.extra["V"], w.extra["dt"])
+    xp = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+    ms_plain_20 = _timed(lambda: pplan.kinetic_step(xp, 20), 1)
+    ms_batched_20 = _timed(lambda: plan.kinetic_step(xp, 20), 3)
+    res["adjoint_200_steps"] = {"workload": w.name, "ms_per_loss_and_gradient": ms,
+                                "ms_per_step_batched": ms_batched_20 / 20, "ms_per_step_plain_form": ms_plain_20 / 20}
+    return res
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -128,6 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (uneven batch, 1000-step TDSE, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of 256 MiB (for scaling memory counters)")
     args = ap.parse_args()
@@ -235,6 +314,8 @@ def main():
         out["plain_gpu_form"] = {"value": pts / (pms * 1e-3), "ms_per_step": pms,
                                  "form": "one launch per channel and stage (4 launches per channel per step)"}
         out["speedup_vs_plain"] = out["value"] / out["plain_gpu_form"]["value"]
+    if not args.no_extra:
+        out["other_workloads"] = other_workloads(progress)
     if not args.no_cpu_baseline:
         progress("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
