@@ -28,9 +28,8 @@ PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3}
 # size (--copy-calibration).  The record holds the SHA-256 of the kernel's
 # sources at the time of the measurement; after any change to them the figure
 # no longer applies and the roofline reports traffic as null.
-MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_mfma.hip", "paper_1509_07115_amd/csrc/kernels.h"],
-                  "sha256": "ace2466f98616e76e2fa109ad5133f57f914169cc6d83144865f49c14dd12838",
-                  "fetch_bytes": 227725088, "write_bytes": 67485248}
+MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h"],
+                  "sha256": "", "fetch_bytes": None, "write_bytes": None}
 
 
 def sources_sha256(paths):
@@ -269,7 +268,7 @@ def main():
         traffic = None
         if MOMENT_TRAFFIC["sha256"] and MOMENT_TRAFFIC["sha256"] == sources_sha256(MOMENT_TRAFFIC["sources"]):
             traffic = MOMENT_TRAFFIC["fetch_bytes"] + MOMENT_TRAFFIC["write_bytes"]
-        roof = roofline("moment stage (dsbt::mstage_mfma)", alg["flops_moment"], alg["bytes_moment"], avg_m, traffic)
+        roof = roofline("moment stage (dsbt::mstage_chain)", alg["flops_moment"], alg["bytes_moment"], avg_m, traffic)
     else:
         roof = roofline("sine/cosine stage (dsbt::fstage_n)", alg["flops_sincos"], alg["bytes_sincos"], avg_f, None)
     roof["stages_ms_per_launch"] = {"sincos": avg_f, "moment": avg_m}

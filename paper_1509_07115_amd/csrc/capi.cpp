@@ -468,12 +468,30 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     std::stable_sort(items_v1.begin(), items_v1.end(), [](const dsbt::MItem& a, const dsbt::MItem& b) {
         return (double)a.NT * a.R * a.R * a.nch > (double)b.NT * b.R * b.R * b.nch;
     });
-    // matrix-core kernel: workgroup b runs on XCD b % 8.  Items of one l are cut
-    // into chunks of up to 4 (they read the same table at the same time, so a
-    // chunk shares that XCD's L2), chunks are dealt to the XCDs heaviest first
-    // by least accumulated cost, and the per-XCD lists are interleaved.
+    // matrix-core kernel: workgroup b runs on XCD b % 8, and the XCD hands its
+    // workgroups to its compute units in turn, so blocks b, b + 8 C, b + 16 C
+    // (C compute units per XCD) share a compute unit while all are resident.
+    // Items of one l are cut into chunks of up to 4 (they read the same table
+    // at the same time, so a chunk shares that XCD's L2), chunks are dealt to
+    // the XCDs heaviest first by least accumulated cost; within an XCD the items
+    // are dealt to compute units the same way, and round r of the XCD's list
+    // holds the r-th heaviest item of every compute unit.
     {
         const int nx = 8, chunk = 4;
+        int ncu = 256;
+        {
+            int dev = 0;
+            hipDeviceProp_t pr;
+            if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
+                pr.multiProcessorCount >= nx)
+                ncu = pr.multiProcessorCount;
+        }
+        const int cpx = ncu / nx;
+        // matrix instructions per tile: the four-wave pipeline skips zero blocks
+        auto cost_of = [&](const dsbt::MItem& it) {
+            if (P->mf_waves == 4) return (double)it.NT * (it.k > 16 ? 56.0 : 32.0);
+            return (double)it.NT * it.NB * it.NB;
+        };
         std::vector<std::pair<double, std::vector<int>>> chunks;
         std::map<int, std::vector<int>> by_ell;
         for (size_t i = 0; i < items_mf.size(); ++i) by_ell[items_mf_ell[i]].push_back((int)i);
@@ -481,7 +499,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             for (size_t j = 0; j < kv.second.size(); j += chunk) {
                 std::vector<int> ids(kv.second.begin() + j, kv.second.begin() + std::min(kv.second.size(), j + chunk));
                 double cost = 0.0;
-                for (int i : ids) cost += (double)items_mf[i].NT * items_mf[i].NB * items_mf[i].NB;
+                for (int i : ids) cost += cost_of(items_mf[i]);
                 chunks.emplace_back(cost, ids);
             }
         }
@@ -494,11 +512,30 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             for (int i : ch.second) bins[x].push_back(i);
             load[x] += ch.first;
         }
+        std::vector<std::vector<int>> order(nx);   // per XCD, in block order; -1: idle slot
+        for (int x = 0; x < nx; ++x) {
+            std::vector<int> ids = bins[x];
+            std::stable_sort(ids.begin(), ids.end(),
+                             [&](int a, int b) { return cost_of(items_mf[a]) > cost_of(items_mf[b]); });
+            std::vector<std::vector<int>> cu(cpx);
+            std::vector<double> cl(cpx, 0.0);
+            for (int i : ids) {
+                const int c = (int)(std::min_element(cl.begin(), cl.end()) - cl.begin());
+                cu[c].push_back(i);
+                cl[c] += cost_of(items_mf[i]);
+            }
+            size_t rounds = 0;
+            for (auto& v : cu) rounds = std::max(rounds, v.size());
+            for (size_t r = 0; r < rounds; ++r)
+                for (int c = 0; c < cpx; ++c) order[x].push_back(r < cu[c].size() ? cu[c][r] : -1);
+            while (!order[x].empty() && order[x].back() < 0) order[x].pop_back();
+        }
         size_t depth = 0;
-        for (auto& b : bins) depth = std::max(depth, b.size());
+        for (auto& o : order) depth = std::max(depth, o.size());
         std::vector<dsbt::MItem> placed(depth * nx, dsbt::MItem{});   // nch = 0: idle slot
         for (int x = 0; x < nx; ++x)
-            for (size_t j = 0; j < bins[x].size(); ++j) placed[j * nx + x] = items_mf[bins[x][j]];
+            for (size_t j = 0; j < order[x].size(); ++j)
+                if (order[x][j] >= 0) placed[j * nx + x] = items_mf[order[x][j]];
         if (items_mf.empty()) placed.clear();
         P->h_items_mf = placed;
     }
@@ -516,6 +553,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     const size_t m_lds = P->cmp_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
     hip_check(dsbt::set_lds_limits<T>(m_lds), "set LDS limits");
     hip_check(dsbt::set_lds_limits_mfma(), "set LDS limits");
+    hip_check(dsbt::set_lds_limits_chain(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
 }
 
@@ -534,12 +572,19 @@ void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
     P->prof_events.emplace_back(stage, a, b);
 }
 
+// Matrix-core moment stage: the four-wave pipeline when every item has B = 32,
+// else the row-block kernel (B = 64 items need 8 waves).
+hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, const void* src, void* dst, bool inverse,
+                     dsbt::PhaseArgs ph, hipStream_t s) {
+    if (P->mf_waves == 4) return dsbt::launch_mstage_chain(items, n, src, dst, inverse, ph, s);
+    return dsbt::launch_mstage_mfma(items, n, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s);
+}
+
 template <typename T, typename S>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(dsbt::launch_mstage_mfma(P->d_items_mf, (int)P->h_items_mf.size(), P->mf_waves, P->mf_lds, src,
-                                               dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf(P, P->d_items_mf, (int)P->h_items_mf.size(), src, dst, inverse, ph, s), "mstage_mfma");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -553,8 +598,7 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
                         dsbt::PhaseArgs ph) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
         if (P->items1_mf[c])
-            hip_check(dsbt::launch_mstage_mfma(P->d_items1 + c, 1, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s),
-                      "mstage_mfma");
+            hip_check(launch_mf(P, P->d_items1 + c, 1, src, dst, inverse, ph, s), "mstage_mfma");
         else
             hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
     });

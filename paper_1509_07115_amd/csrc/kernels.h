@@ -109,6 +109,12 @@ inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
     return sizeof(float) * (size_t)(2 * NCB * 16 * NB * 16 + 2 * NCB * B * 16);
 }
 hipError_t set_lds_limits_mfma();
+// Moment stage for items with NB = 4 (B = 32, k <= 32) as a four-wave pipeline
+// per item (Q x, moment chain, two result row blocks); 256 threads, static LDS.
+// Runs in place.  Phases (ph.use) are supported on the forward direction only.
+hipError_t launch_mstage_chain(const MItem* d_items, int nitems, const void* src, void* dst, bool inverse,
+                               PhaseArgs ph, hipStream_t s);
+hipError_t set_lds_limits_chain();
 
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into
 // scratch[nch], then out[0] = their sum (FP64).

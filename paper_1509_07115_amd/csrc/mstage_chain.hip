@@ -1,0 +1,505 @@
+// Moment stage for tiles of B = 32 on the CDNA4 matrix cores, as a pipeline
+// of four waves per item (8 complex channels with the same l and N).
+//
+// Per tile J the tiled moment form (Sec. 2.4-2.5) maps [x_J; mu_J] to
+// [o_J; mu_J+1] with the zero-padded 64 x 64 block A' (M_J forward, M_J^T
+// inverse): rows/columns 0..31 are the tile slots, 32..63 the moments.  The
+// only serial dependence is mu_J+1 = Q x_J + D mu_J, so the work of a tile is
+// split by role:
+//   pre wave     x_J -> LDS (32 contiguous bytes per lane, natural layout),
+//                q_J = Q x_J = A'[32:64, 0:32] x_J -> LDS;
+//   chain wave   mu_J+1 = q_J + A'[32:64, 32:64] mu_J, with mu kept in
+//                registers: the result layout of the matrix instruction is
+//                turned into its operand layout by two lane-swap stages;
+//                mu_J+1 -> LDS;
+//   result waves o_J = A'[16 r : 16 r + 16, :] [x_J; mu_J], r = 0, 1, from
+//                LDS; each 16 x 16 result block is turned through LDS so
+//                that a lane stores two consecutive complex slots of one
+//                channel (16 bytes), with the kinetic phase.
+// The waves run one phase of kPhase tiles apart (pre, chain, results) and
+// meet at one LDS barrier per phase.  All global reads of a tile happen two
+// phases before any write of it, so the stage may run in place.  Global
+// operands are prefetched kPD tiles ahead into kSets register sets, and each
+// role's loop (kSets / kPhase phases per iteration) has no branch: tiles past
+// NT exist only when NT < kSets, a separate instantiation.  So the compiler's
+// memory-counter waits cover just the prefetch distance.  Short phases keep
+// the LDS rings small enough for three items per compute unit.
+//
+// v_mfma_f32_16x16x4_f32 layouts: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16].  The
+// 16 columns are the 8 channels times (re, im).  Operands use the table layout
+// of MItem::mf_f / mf_i with NB = 4 (per row block and lane, the 16 floats
+// A'[16 rb + l%16][4 kc + l/16], kc = 0..15).  Zero blocks are skipped: the
+// in-tile band of T and the moment-to-moment block are triangular (lower
+// forward, upper inverse), and moment columns past k = ceil(l/2) are padding
+// (KB = ceil(k/16) chunks of 16).
+#include "kernels.h"
+
+namespace dsbt {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+// 16-byte global access of two complex64 values, which are 8-byte aligned
+typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+
+constexpr int kPhase = 2;               // tiles per phase
+constexpr int kPD = 3;                  // prefetch distance of the global operands, in tiles
+constexpr int kSets = kPD + 1;          // register sets; set = tile mod kSets
+constexpr int kRep = kSets / kPhase;    // phases per loop iteration
+static_assert(kSets % kPhase == 0, "a loop iteration must cycle through the register sets exactly once");
+constexpr int kXRing = 3 * kPhase;      // tile data: written two phases before it is read
+constexpr int kQRing = 2 * kPhase;      // Q x: read one phase after it is written
+constexpr int kMRing = 3 * kPhase;      // moments: 2 kPhase + 1 slots live
+static_assert(kMRing >= 2 * kPhase + 1, "moment ring too small");
+constexpr int kSlot = 64 * 8;           // floats per Q x / moment slot: 8 per lane
+constexpr int kXCh = 72;                // floats per channel of a data slot (32 complex + padding)
+constexpr int kXSlot = 8 * kXCh;        // data slot: 8 channels, natural layout
+constexpr int kYCol = 20;               // result staging: floats per column (16 rows + padding)
+constexpr int kYWave = 16 * kYCol;
+constexpr int kLdsFloats = kXRing * kXSlot + (kQRing + kMRing) * kSlot + 2 * kYWave;
+
+// Orders this wave's LDS accesses across a point (the hardware keeps one
+// wave's LDS operations in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// (row 4 (l/16) + v, column l%16) in register v  ->  (row 4 j + l/16) in out[j]:
+// a transpose of the 4 x 4 grid (lane quarter, register).  The 32-lane swap
+// exchanges the high bits of the two indices, the 16-lane swap the low bits.
+__device__ __forceinline__ void result_to_operand(f4 m, float* out) {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[0]), __float_as_uint(m[2]), false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[1]), __float_as_uint(m[3]), false, false);
+    const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
+    const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
+    out[0] = __uint_as_float(c[0]);
+    out[1] = __uint_as_float(c[1]);
+    out[2] = __uint_as_float(d[0]);
+    out[3] = __uint_as_float(d[1]);
+}
+
+template <bool INV, bool KPH, int KB, bool TAIL>
+struct Pipe {
+    // chunk kc = A' columns 4 kc .. 4 kc + 3 (0..7 tile data, 8.. moments)
+    static constexpr int MHI = 8 + 4 * KB;
+    static constexpr int R0LO = 0, R0HI = INV ? 8 : 4;      // result rows 0..15, data chunks
+    static constexpr int R1LO = INV ? 4 : 0, R1HI = 8;      // result rows 16..31
+    static constexpr int C2LO = 8, C2HI = INV ? MHI : 12;   // moment rows 0..15, moment chunks
+    static constexpr int C3LO = INV ? 12 : 8, C3HI = MHI;   // moment rows 16..31 (KB = 2)
+    static constexpr int NC2 = (C2HI - C2LO) / 4, NC3 = KB == 2 ? (C3HI - C3LO) / 4 : 0;
+
+    const float DSBT_GLOBAL* src;
+    float DSBT_GLOBAL* dst;
+    const float DSBT_GLOBAL* tab;
+    const f2 DSBT_GLOBAL* kphase;
+    float* xring;
+    float* qring;
+    float* mring;
+    float* yring;
+    int NT, k, p, lane, q, col, nact;
+    int64_t e0;   // float index of (channel col/2, slot 0, re/im col%2)
+    // natural layout: lane l owns channel l/8, slots 4 (l%8) .. 4 (l%8) + 3 of
+    // a tile (pre wave) or 2 (l%8), 2 (l%8) + 1 of a 16-row block (stores)
+    int64_t g0;   // float index of (channel l/8, slot 0)
+    int xnat;     // float offset of this lane's 8 loaded floats in a data slot
+    int xop;      // float offset of operand (slot l/16, column l%16) in a data slot
+    bool conj;
+
+    __device__ Pipe(const MItem& it, const float2* s_, float2* d_, const PhaseArgs& ph, float* lds)
+        : src(as_global(reinterpret_cast<const float*>(s_))), dst(as_global_rw(reinterpret_cast<float*>(d_))) {
+        NT = it.NT;
+        k = it.k;
+        p = it.p;
+        lane = threadIdx.x & 63;
+        q = lane >> 4;
+        col = lane & 15;
+        e0 = 2 * it.off[col >> 1] + (col & 1);
+        conj = ph.conj != 0;
+        tab = as_global(INV ? it.mf_i : it.mf_f);
+        kphase = as_global(reinterpret_cast<const f2*>(it.kphase));
+        g0 = 2 * it.off[lane >> 3];
+        xnat = (lane >> 3) * kXCh + 8 * (lane & 7);
+        xop = (col >> 1) * kXCh + 2 * q + (col & 1);
+        xring = lds;
+        qring = lds + kXRing * kXSlot;
+        mring = qring + kQRing * kSlot;
+        yring = mring + kMRing * kSlot;
+        nact = (NT + kPhase - 1) / kPhase;   // phases in which a role has tiles
+    }
+
+    __device__ int tile(int t) const {
+        const int c = t < NT ? t : NT - 1;
+        return INV ? NT - 1 - c : c;
+    }
+    __device__ const float DSBT_GLOBAL* rows(int J, int rb) const {
+        return tab + ((size_t)(J * 4 + rb) * 64 + lane) * 16;
+    }
+    template <int N>
+    static __device__ void seg(f4* o, const float DSBT_GLOBAL* s) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(s + 4 * i);
+    }
+    // acc += A[:, chunks LO..HI) B, alternating two accumulators; A chunk kc is
+    // float kc - LO of av, B chunk kc is bv[kc - LO]
+    template <int LO, int HI>
+    static __device__ void mac(f4& c0, f4& c1, const f4* av, const float* bv) {
+#pragma unroll
+        for (int kc = LO; kc < HI; ++kc) {
+            const int j = kc - LO;
+            const float x = av[j >> 2][j & 3];
+            if (j & 1) c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[j], c1, 0, 0, 0);
+            else c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[j], c0, 0, 0, 0);
+        }
+    }
+    // x (w.x + i w.y) on the lane pair (re, im) of one complex value
+    static __device__ float phase(float x, f2 w, bool im, bool cj) {
+        const float y = __shfl_xor(x, 1, 64);
+        const float s = cj ? -w.y : w.y;
+        return im ? x * w.x + y * s : x * w.x - y * s;
+    }
+    static __device__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+    static __device__ void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+
+    // ---- pre wave: q_t = Q x_t, x_t -> LDS ----
+    struct Pre {
+        f4 a[kSets][2 * KB];
+        f4 x[kSets][2];
+    };
+    template <int S>
+    __device__ void pre_load(Pre& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);   // loads are issued in tile order (prologue included)
+        const int J = tile(t);
+        seg<2>(r.a[S], rows(J, 2));
+        if constexpr (KB == 2) seg<2>(r.a[S] + 2, rows(J, 3));
+        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + g0 + 64 * (int64_t)J + 8 * (lane & 7));
+        r.x[S][0] = g[0];
+        r.x[S][1] = g[1];
+    }
+    template <int S>
+    __device__ void pre_step(Pre& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
+        pre_load<(S + kPD) % kSets>(r, t + kPD);
+        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        float* qs = qring + (t % kQRing) * kSlot + lane * 8;
+        float* xs = xring + (t % kXRing) * kXSlot;
+        st4(xs + xnat, r.x[S][0]);
+        st4(xs + xnat + 4, r.x[S][1]);
+        wave_lds_fence();
+        float xv[8];
+#pragma unroll
+        for (int kc = 0; kc < 8; ++kc) xv[kc] = xs[xop + 8 * kc];
+        f4 c0 = z, c1 = z;
+        mac<0, 8>(c0, c1, r.a[S], xv);
+        st4(qs, c0 + c1);
+        if constexpr (KB == 2) {
+            f4 n0 = z, n1 = z;
+            mac<0, 8>(n0, n1, r.a[S] + 2, xv);
+            st4(qs + 4, n0 + n1);
+        }
+    }
+    // steps of one phase (tiles t0 .. t0 + kPhase - 1, register sets I0 ..)
+    template <int I0, int I = 0>
+    __device__ void pre_phase(Pre& r, int t0) const {
+        if constexpr (I < kPhase) {
+            pre_step<I0 + I>(r, t0 + I);
+            pre_phase<I0, I + 1>(r, t0);
+        }
+    }
+    // phases ph .. ph + kRep - 1
+    template <int P = 0>
+    __device__ void pre_iter(Pre& r, int ph) const {
+        if constexpr (P < kRep) {
+            pre_phase<P * kPhase>(r, (ph + P) * kPhase);
+            lds_barrier();
+            pre_iter<P + 1>(r, ph);
+        }
+    }
+    __device__ void run_pre() const {
+        Pre r;
+        pre_load<0>(r, 0);
+        pre_load<1>(r, 1);
+        pre_load<2>(r, 2);
+        int ph = 0;
+        for (; ph + kRep <= nact; ph += kRep) pre_iter(r, ph);
+        if constexpr (TAIL) {
+            if (ph < nact) {   // nact < kRep
+                pre_phase<0>(r, ph * kPhase);
+                lds_barrier();
+            }
+        }
+        lds_barrier();
+        lds_barrier();
+    }
+
+    // ---- chain wave: mu_t+1 = q_t + D mu_t ----
+    struct Chain {
+        f4 a[kSets][NC2 + NC3];
+        f4 qg[kPhase][KB];
+        float bm[4 * KB];
+    };
+    template <int S>
+    __device__ void chain_load(Chain& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);
+        const int J = tile(t);
+        seg<NC2>(r.a[S], rows(J, 2) + C2LO);
+        if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, rows(J, 3) + C3LO);
+    }
+    template <int S>
+    __device__ void chain_step(Chain& r, int t) const {
+        if constexpr (TAIL) {
+            if (t >= NT) return;   // bm must keep mu_NT
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        chain_load<(S + kPD) % kSets>(r, t + kPD);
+        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        f4 c0 = r.qg[S % kPhase][0], c1 = z;
+        mac<C2LO, C2HI>(c0, c1, r.a[S], r.bm + (C2LO - 8));
+        const f4 m2 = c0 + c1;
+        f4 m3 = z;
+        if constexpr (KB == 2) {
+            f4 n0 = r.qg[S % kPhase][1], n1 = z;
+            mac<C3LO, C3HI>(n0, n1, r.a[S] + NC2, r.bm + (C3LO - 8));
+            m3 = n0 + n1;
+        }
+        result_to_operand(m2, r.bm);
+        if constexpr (KB == 2) result_to_operand(m3, r.bm + 4);
+        float* ms = mring + ((t + 1) % kMRing) * kSlot + lane * 8;
+        st4(ms, f4{r.bm[0], r.bm[1], r.bm[2], r.bm[3]});
+        if constexpr (KB == 2) st4(ms + 4, f4{r.bm[4], r.bm[5], r.bm[6], r.bm[7]});
+    }
+    template <int I0, int I = 0>
+    __device__ void chain_phase(Chain& r, int t0) const {
+        if constexpr (I < kPhase) {
+            chain_step<I0 + I>(r, t0 + I);
+            chain_phase<I0, I + 1>(r, t0);
+        }
+    }
+    template <int I0>
+    __device__ void chain_phase_body(Chain& r, int t0) const {
+#pragma unroll
+        for (int i = 0; i < kPhase; ++i) {
+            const float* qs = qring + ((t0 + i) % kQRing) * kSlot + lane * 8;
+            r.qg[i][0] = ld4(qs);
+            if constexpr (KB == 2) r.qg[i][1] = ld4(qs + 4);
+        }
+        chain_phase<I0>(r, t0);
+        lds_barrier();
+    }
+    template <int P = 0>
+    __device__ void chain_iter(Chain& r, int ph) const {
+        if constexpr (P < kRep) {
+            chain_phase_body<P * kPhase>(r, (ph + P) * kPhase);
+            chain_iter<P + 1>(r, ph);
+        }
+    }
+    __device__ void run_chain(float* bm_out) const {
+        Chain r;
+        chain_load<0>(r, 0);
+        chain_load<1>(r, 1);
+        chain_load<2>(r, 2);
+        // mu_0: zero forward; inverse (-1)^p times the completion slots 0..k-1 of tile 0
+        const float sgn = p ? -1.0f : 1.0f;
+#pragma unroll
+        for (int j = 0; j < 4 * KB; ++j) {
+            const int row = 4 * j + q;
+            r.bm[j] = (INV && row < k) ? sgn * src[e0 + 2 * row] : 0.0f;
+        }
+        float* ms = mring + lane * 8;
+        st4(ms, f4{r.bm[0], r.bm[1], r.bm[2], r.bm[3]});
+        if constexpr (KB == 2) st4(ms + 4, f4{r.bm[4], r.bm[5], r.bm[6], r.bm[7]});
+        lds_barrier();
+        int ph = 0;
+        for (; ph + kRep <= nact; ph += kRep) chain_iter(r, ph);
+        if constexpr (TAIL) {
+            if (ph < nact) chain_phase_body<0>(r, ph * kPhase);
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < 4 * KB; ++j) bm_out[j] = r.bm[j];
+    }
+
+    // forward completion rows (-1)^p mu_NT into slots 0..k-1 of tile 0
+    // (moment row 4 j + l/16 is bm[j], operand layout)
+    __device__ void completion(const float* bm) const {
+        const float sgn = p ? -1.0f : 1.0f;
+#pragma unroll
+        for (int j = 0; j < 4 * KB; ++j) {
+            const int row = 4 * j + q;
+            float x = sgn * bm[j];
+            if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
+            if (row < k) dst[e0 + 2 * row] = x;
+        }
+    }
+
+    // ---- result waves: rows 16 RB .. 16 RB + 15 of o_t ----
+    template <int RB>
+    struct Out {
+        static constexpr int LO = RB == 0 ? R0LO : R1LO, HI = RB == 0 ? R0HI : R1HI;
+        static constexpr int ND = (HI - LO) / 4;
+        f4 a[kSets][ND + KB];
+        f4 w[kSets];   // kinetic phases of the two stored slots (re, im, re, im)
+        float x[kPhase][8];
+        float mu[kPhase][4 * KB];
+    };
+    template <int RB, int S>
+    __device__ void out_load(Out<RB>& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);
+        const int J = tile(t);
+        const float DSBT_GLOBAL* b = rows(J, RB);
+        seg<Out<RB>::ND>(r.a[S], b + Out<RB>::LO);
+        seg<KB>(r.a[S] + Out<RB>::ND, b + 8);
+        if constexpr (KPH)
+            r.w[S] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
+    }
+    template <int RB, int S>
+    __device__ void out_step(Out<RB>& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);
+        out_load<RB, (S + kPD) % kSets>(r, t + kPD);
+        constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI;
+        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        f4 c0 = z, c1 = z;
+        mac<LO, HI>(c0, c1, r.a[S], r.x[S % kPhase] + LO);
+        mac<8, MHI>(c0, c1, r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
+        const f4 o = c0 + c1;
+        if constexpr (TAIL) {
+            if (t >= NT) return;
+        }
+        // result layout -> (channel l/8, slots 2 (l%8), 2 (l%8) + 1)
+        float* y = yring + RB * kYWave;
+        st4(y + col * kYCol + 4 * q, o);
+        wave_lds_fence();
+        const int c = lane >> 3, s0 = 2 * (lane & 7);
+        const f2 re = *reinterpret_cast<const f2*>(y + 2 * c * kYCol + s0);
+        const f2 im = *reinterpret_cast<const f2*>(y + (2 * c + 1) * kYCol + s0);
+        wave_lds_fence();
+        f4 v = f4{re.x, im.x, re.y, im.y};
+        if constexpr (KPH) {
+            const f4 w = r.w[S];
+            const float s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
+            v = f4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+        }
+        // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
+        const int J = tile(t);
+        *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0 + 64 * (int64_t)J + 2 * (16 * RB + s0)) = v;
+    }
+    template <int RB, int I0, int I = 0>
+    __device__ void out_phase(Out<RB>& r, int t0) const {
+        if constexpr (I < kPhase) {
+            out_step<RB, I0 + I>(r, t0 + I);
+            out_phase<RB, I0, I + 1>(r, t0);
+        }
+    }
+    template <int RB, int I0>
+    __device__ void out_phase_body(Out<RB>& r, int t0) const {
+#pragma unroll
+        for (int i = 0; i < kPhase; ++i) {
+            const float* xs = xring + ((t0 + i) % kXRing) * kXSlot + xop;
+            const float* ms = mring + ((t0 + i) % kMRing) * kSlot + lane * 8;
+            const f4 m0 = ld4(ms);
+#pragma unroll
+            for (int kc = 0; kc < 8; ++kc) r.x[i][kc] = xs[8 * kc];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r.mu[i][j] = m0[j];
+            if constexpr (KB == 2) {
+                const f4 m1 = ld4(ms + 4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) r.mu[i][4 + j] = m1[j];
+            }
+        }
+        out_phase<RB, I0>(r, t0);
+        lds_barrier();
+    }
+    template <int RB, int P = 0>
+    __device__ void out_iter(Out<RB>& r, int ph) const {
+        if constexpr (P < kRep) {
+            out_phase_body<RB, P * kPhase>(r, (ph + P) * kPhase);
+            out_iter<RB, P + 1>(r, ph);
+        }
+    }
+    template <int RB>
+    __device__ void run_out() const {
+        Out<RB> r;
+        out_load<RB, 0>(r, 0);
+        out_load<RB, 1>(r, 1);
+        out_load<RB, 2>(r, 2);
+        lds_barrier();
+        lds_barrier();
+        int ph = 0;
+        for (; ph + kRep <= nact; ph += kRep) out_iter<RB>(r, ph);
+        if constexpr (TAIL) {
+            if (ph < nact) out_phase_body<RB, 0>(r, ph * kPhase);
+        }
+    }
+
+    __device__ void run() const {
+        // roles by wave: pre, chain, then the heavier result block (rows 16..31
+        // forward, 0..15 inverse) and the lighter one.  Consecutive workgroups on
+        // a compute unit start their waves one SIMD further along the sequence
+        // 0, 2, 1, 3, so this order pairs a heavy and a light role on each SIMD.
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        float bm[4 * KB];
+        switch (wave) {
+            case 0: run_pre(); break;
+            case 1: run_chain(bm); break;
+            case 2: run_out<INV ? 0 : 1>(); break;
+            default: run_out<INV ? 1 : 0>(); break;
+        }
+        if constexpr (!INV) {
+            // the result waves' stores of tile 0 are ordered before the
+            // completion rows that replace slots 0..k-1
+            __syncthreads();
+            if (wave == 1) completion(bm);
+        }
+    }
+};
+
+template <bool INV, bool KPH>
+__global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const float2* src, float2* dst,
+                                                    PhaseArgs ph) {
+    extern __shared__ __align__(16) float lds[];
+    const MItem& it = items[blockIdx.x];
+    if (it.nch == 0) return;   // idle slot of the per-XCD schedule
+    const bool tail = it.NT % kSets != 0;
+    if (it.k > 16) {
+        if (tail) Pipe<INV, KPH, 2, true>(it, src, dst, ph, lds).run();
+        else Pipe<INV, KPH, 2, false>(it, src, dst, ph, lds).run();
+    } else {
+        if (tail) Pipe<INV, KPH, 1, true>(it, src, dst, ph, lds).run();
+        else Pipe<INV, KPH, 1, false>(it, src, dst, ph, lds).run();
+    }
+}
+
+}  // namespace
+
+static constexpr size_t kChainLds = sizeof(float) * kLdsFloats;
+
+hipError_t set_lds_limits_chain() {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLds);
+    };
+    set((const void*)mstage_chain<true, false>);
+    set((const void*)mstage_chain<false, true>);
+    set((const void*)mstage_chain<false, false>);
+    return e;
+}
+
+hipError_t launch_mstage_chain(const MItem* d_items, int nitems, const void* src, void* dst, bool inverse,
+                               PhaseArgs ph, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (inverse && ph.use) return hipErrorInvalidValue;   // phases are applied on the forward output only
+    const float2* a = (const float2*)src;
+    float2* b = (float2*)dst;
+    if (inverse)
+        hipLaunchKernelGGL((mstage_chain<true, false>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+    else if (ph.use)
+        hipLaunchKernelGGL((mstage_chain<false, true>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+    else
+        hipLaunchKernelGGL((mstage_chain<false, false>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+    return hipGetLastError();
+}
+
+}  // namespace dsbt
