@@ -143,6 +143,7 @@ struct dsbt_plan_s {
     dsbt::MItem* d_items_v1 = nullptr;
     dsbt::MItem* d_items1 = nullptr;
     int mf_waves = 4;
+    int chain_ncb = 1;   // largest column-block count of the batched four-wave items
     size_t mf_lds = 0;
 
     // potential
@@ -438,7 +439,9 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         const bool mf = t.mf != nullptr;
         int per = dsbt::kMaxChanPerItem;
         if (mf) {
-            base.NCB = dsbt::mfma_ncb(P->mf_waves, base.NB);
+            // the four-wave pipeline takes 16 channels (two column blocks) per
+            // item unless the caller caps the item at 8
+            base.NCB = P->mf_waves == 4 ? (cpb > 0 && cpb <= 8 ? 1 : 2) : dsbt::mfma_ncb(P->mf_waves, base.NB);
             per = 8 * base.NCB;
         }
         if (cpb > 0) per = std::min(per, cpb);
@@ -450,6 +453,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             if (mf) {
                 items_mf.push_back(it);
                 items_mf_ell.push_back(g.ell);
+                P->chain_ncb = std::max(P->chain_ncb, it.NCB);
                 P->mf_lds = std::max(P->mf_lds, dsbt::mfma_lds_bytes_for(it.NB, it.NCB, it.B));
             } else {
                 items_v1.push_back(it);
@@ -458,6 +462,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         for (int c : g.chans) {
             dsbt::MItem it = base;
             it.nch = 1;
+            if (mf && P->mf_waves == 4) it.NCB = 1;
             for (int j = 0; j < dsbt::kMaxChanPerItem; ++j) it.off[j] = P->ch[c].offset;
             P->h_items1[c] = it;
             P->items1_mf[c] = mf ? 1 : 0;
@@ -489,7 +494,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         const int cpx = ncu / nx;
         // matrix instructions per tile: the four-wave pipeline skips zero blocks
         auto cost_of = [&](const dsbt::MItem& it) {
-            if (P->mf_waves == 4) return (double)it.NT * (it.k > 16 ? 56.0 : 32.0);
+            if (P->mf_waves == 4) return (double)it.NT * it.NCB * (it.k > 16 ? 56.0 : 32.0);
             return (double)it.NT * it.NB * it.NB;
         };
         std::vector<std::pair<double, std::vector<int>>> chunks;
@@ -573,10 +578,11 @@ void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
 }
 
 // Matrix-core moment stage: the four-wave pipeline when every item has B = 32,
-// else the row-block kernel (B = 64 items need 8 waves).
-hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, const void* src, void* dst, bool inverse,
-                     dsbt::PhaseArgs ph, hipStream_t s) {
-    if (P->mf_waves == 4) return dsbt::launch_mstage_chain(items, n, src, dst, inverse, ph, s);
+// else the row-block kernel (B = 64 items need 8 waves).  ncb: the largest
+// column-block count of the launched items.
+hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, int ncb, const void* src, void* dst,
+                     bool inverse, dsbt::PhaseArgs ph, hipStream_t s) {
+    if (P->mf_waves == 4) return dsbt::launch_mstage_chain(items, n, ncb, src, dst, inverse, ph, s);
     return dsbt::launch_mstage_mfma(items, n, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s);
 }
 
@@ -584,7 +590,7 @@ template <typename T, typename S>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(launch_mf(P, P->d_items_mf, (int)P->h_items_mf.size(), src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -598,7 +604,7 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
                         dsbt::PhaseArgs ph) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
         if (P->items1_mf[c])
-            hip_check(launch_mf(P, P->d_items1 + c, 1, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
         else
             hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
     });

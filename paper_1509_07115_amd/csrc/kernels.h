@@ -110,11 +110,14 @@ inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
 }
 hipError_t set_lds_limits_mfma();
 // Moment stage for items with NB = 4 (B = 32, k <= 32) as a four-wave pipeline
-// per item (Q x, moment chain, two result row blocks); 256 threads, static LDS.
+// per item (Q x, moment chain, two result row blocks); 256 threads.  An item
+// has NCB = 1 or 2 blocks of 8 channels (off[]: slots past nch repeat a real
+// channel); ncb is the largest NCB of the launched items and sizes the LDS.
 // Runs in place.  Phases (ph.use) are supported on the forward direction only.
-hipError_t launch_mstage_chain(const MItem* d_items, int nitems, const void* src, void* dst, bool inverse,
+hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s);
 hipError_t set_lds_limits_chain();
+size_t chain_lds_bytes(int ncb);
 
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into
 // scratch[nch], then out[0] = their sum (FP64).

@@ -1,5 +1,7 @@
 // Moment stage for tiles of B = 32 on the CDNA4 matrix cores, as a pipeline
-// of four waves per item (8 complex channels with the same l and N).
+// of four waves per item: 8 NCB complex channels with the same l and N, in
+// NCB = 1 or 2 blocks of 16 matrix columns.  Every table operand a lane loads
+// feeds NCB matrix instructions.
 //
 // Per tile J the tiled moment form (Sec. 2.4-2.5) maps [x_J; mu_J] to
 // [o_J; mu_J+1] with the zero-padded 64 x 64 block A' (M_J forward, M_J^T
@@ -27,7 +29,7 @@
 //
 // v_mfma_f32_16x16x4_f32 layouts: lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16].  The
-// 16 columns are the 8 channels times (re, im).  Operands use the table layout
+// 16 columns of block cb are channels 8 cb .. 8 cb + 7 times (re, im).  Operands use the table layout
 // of MItem::mf_f / mf_i with NB = 4 (per row block and lane, the 16 floats
 // A'[16 rb + l%16][4 kc + l/16], kc = 0..15).  Zero blocks are skipped: the
 // in-tile band of T and the moment-to-moment block are triangular (lower
@@ -53,12 +55,15 @@ constexpr int kXRing = 3 * kPhase;      // tile data: written two phases before 
 constexpr int kQRing = 2 * kPhase;      // Q x: read one phase after it is written
 constexpr int kMRing = 3 * kPhase;      // moments: 2 kPhase + 1 slots live
 static_assert(kMRing >= 2 * kPhase + 1, "moment ring too small");
-constexpr int kSlot = 64 * 8;           // floats per Q x / moment slot: 8 per lane
 constexpr int kXCh = 72;                // floats per channel of a data slot (32 complex + padding)
-constexpr int kXSlot = 8 * kXCh;        // data slot: 8 channels, natural layout
 constexpr int kYCol = 20;               // result staging: floats per column (16 rows + padding)
-constexpr int kYWave = 16 * kYCol;
-constexpr int kLdsFloats = kXRing * kXSlot + (kQRing + kMRing) * kSlot + 2 * kYWave;
+
+// LDS floats of an item of ncb column blocks: data ring (natural layout),
+// Q x and moment rings (8 floats per lane and block), result staging of the
+// two result waves
+__host__ __device__ constexpr int chain_lds_floats(int ncb) {
+    return kXRing * 8 * ncb * kXCh + (kQRing + kMRing) * 64 * 8 * ncb + 2 * ncb * 16 * kYCol;
+}
 
 // Orders this wave's LDS accesses across a point (the hardware keeps one
 // wave's LDS operations in order; this keeps the compiler from moving them).
@@ -81,7 +86,7 @@ __device__ __forceinline__ void result_to_operand(f4 m, float* out) {
     out[3] = __uint_as_float(d[1]);
 }
 
-template <bool INV, bool KPH, int KB, bool TAIL>
+template <bool INV, bool KPH, int KB, bool TAIL, int NCB>
 struct Pipe {
     // chunk kc = A' columns 4 kc .. 4 kc + 3 (0..7 tile data, 8.. moments)
     static constexpr int MHI = 8 + 4 * KB;
@@ -90,6 +95,10 @@ struct Pipe {
     static constexpr int C2LO = 8, C2HI = INV ? MHI : 12;   // moment rows 0..15, moment chunks
     static constexpr int C3LO = INV ? 12 : 8, C3HI = MHI;   // moment rows 16..31 (KB = 2)
     static constexpr int NC2 = (C2HI - C2LO) / 4, NC3 = KB == 2 ? (C3HI - C3LO) / 4 : 0;
+    static constexpr int SLOT = 64 * 8 * NCB;               // floats per Q x / moment slot
+    static constexpr int XSLOT = 8 * NCB * kXCh;            // floats per data slot
+    static constexpr int YWAVE = NCB * 16 * kYCol;          // result staging per result wave
+    static constexpr int LPC = 8 / NCB, FPL = 8 * NCB;      // pre-wave loads: lanes per channel, floats per lane
 
     const float DSBT_GLOBAL* src;
     float DSBT_GLOBAL* dst;
@@ -100,12 +109,14 @@ struct Pipe {
     float* mring;
     float* yring;
     int NT, k, p, lane, q, col, nact;
-    int64_t e0;   // float index of (channel col/2, slot 0, re/im col%2)
-    // natural layout: lane l owns channel l/8, slots 4 (l%8) .. 4 (l%8) + 3 of
-    // a tile (pre wave) or 2 (l%8), 2 (l%8) + 1 of a 16-row block (stores)
-    int64_t g0;   // float index of (channel l/8, slot 0)
-    int xnat;     // float offset of this lane's 8 loaded floats in a data slot
-    int xop;      // float offset of operand (slot l/16, column l%16) in a data slot
+    int64_t e0[NCB];   // float index of (channel 8 cb + col/2, slot 0, re/im col%2)
+    // natural layout: the pre wave's lane l loads channel l/LPC, FPL floats
+    // from slot 4 (l%LPC) NCB of a tile; a result wave's lane l stores slots
+    // 2 (l%8), 2 (l%8) + 1 of channel 8 cb + l/8 in a 16-row block
+    int64_t gpre;      // float index of the pre wave's first float in tile 0
+    int64_t g0[NCB];   // float index of (channel 8 cb + l/8, slot 0)
+    int xnat;          // float offset of the pre wave's loaded floats in a data slot
+    int xop[NCB];      // float offset of operand (slot l/16, column l%16 of block cb) in a data slot
     bool conj;
 
     __device__ Pipe(const MItem& it, const float2* s_, float2* d_, const PhaseArgs& ph, float* lds)
@@ -116,17 +127,21 @@ struct Pipe {
         lane = threadIdx.x & 63;
         q = lane >> 4;
         col = lane & 15;
-        e0 = 2 * it.off[col >> 1] + (col & 1);
         conj = ph.conj != 0;
         tab = as_global(INV ? it.mf_i : it.mf_f);
         kphase = as_global(reinterpret_cast<const f2*>(it.kphase));
-        g0 = 2 * it.off[lane >> 3];
-        xnat = (lane >> 3) * kXCh + 8 * (lane & 7);
-        xop = (col >> 1) * kXCh + 2 * q + (col & 1);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            e0[cb] = 2 * it.off[8 * cb + (col >> 1)] + (col & 1);
+            g0[cb] = 2 * it.off[8 * cb + (lane >> 3)];
+            xop[cb] = (8 * cb + (col >> 1)) * kXCh + 2 * q + (col & 1);
+        }
+        gpre = 2 * it.off[lane / LPC] + FPL * (lane % LPC);
+        xnat = (lane / LPC) * kXCh + FPL * (lane % LPC);
         xring = lds;
-        qring = lds + kXRing * kXSlot;
-        mring = qring + kQRing * kSlot;
-        yring = mring + kMRing * kSlot;
+        qring = lds + kXRing * XSLOT;
+        mring = qring + kQRing * SLOT;
+        yring = mring + kMRing * SLOT;
         nact = (NT + kPhase - 1) / kPhase;   // phases in which a role has tiles
     }
 
@@ -142,16 +157,20 @@ struct Pipe {
 #pragma unroll
         for (int i = 0; i < N; ++i) o[i] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(s + 4 * i);
     }
-    // acc += A[:, chunks LO..HI) B, alternating two accumulators; A chunk kc is
-    // float kc - LO of av, B chunk kc is bv[kc - LO]
-    template <int LO, int HI>
-    static __device__ void mac(f4& c0, f4& c1, const f4* av, const float* bv) {
+    // for every block cb: acc[cb] += A[:, chunks LO..HI) B_cb, alternating two
+    // accumulators; A chunk kc is float kc - LO of av, B_cb chunk kc is
+    // bv[BS cb + kc - LO]
+    template <int LO, int HI, int BS>
+    static __device__ void mac(f4* c0, f4* c1, const f4* av, const float* bv) {
 #pragma unroll
         for (int kc = LO; kc < HI; ++kc) {
             const int j = kc - LO;
             const float x = av[j >> 2][j & 3];
-            if (j & 1) c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[j], c1, 0, 0, 0);
-            else c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[j], c0, 0, 0, 0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                if (j & 1) c1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[BS * cb + j], c1[cb], 0, 0, 0);
+                else c0[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[BS * cb + j], c0[cb], 0, 0, 0);
+            }
         }
     }
     // x (w.x + i w.y) on the lane pair (re, im) of one complex value
@@ -162,11 +181,12 @@ struct Pipe {
     }
     static __device__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
     static __device__ void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+    static __device__ f4 zero4() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
 
     // ---- pre wave: q_t = Q x_t, x_t -> LDS ----
     struct Pre {
         f4 a[kSets][2 * KB];
-        f4 x[kSets][2];
+        f4 x[kSets][2 * NCB];
     };
     template <int S>
     __device__ void pre_load(Pre& r, int t) const {
@@ -174,30 +194,36 @@ struct Pipe {
         const int J = tile(t);
         seg<2>(r.a[S], rows(J, 2));
         if constexpr (KB == 2) seg<2>(r.a[S] + 2, rows(J, 3));
-        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + g0 + 64 * (int64_t)J + 8 * (lane & 7));
-        r.x[S][0] = g[0];
-        r.x[S][1] = g[1];
+        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)J);
+#pragma unroll
+        for (int i = 0; i < 2 * NCB; ++i) r.x[S][i] = g[i];
     }
     template <int S>
     __device__ void pre_step(Pre& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
         pre_load<(S + kPD) % kSets>(r, t + kPD);
-        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        float* qs = qring + (t % kQRing) * kSlot + lane * 8;
-        float* xs = xring + (t % kXRing) * kXSlot;
-        st4(xs + xnat, r.x[S][0]);
-        st4(xs + xnat + 4, r.x[S][1]);
-        wave_lds_fence();
-        float xv[8];
+        float* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
+        float* xs = xring + (t % kXRing) * XSLOT;
 #pragma unroll
-        for (int kc = 0; kc < 8; ++kc) xv[kc] = xs[xop + 8 * kc];
-        f4 c0 = z, c1 = z;
-        mac<0, 8>(c0, c1, r.a[S], xv);
-        st4(qs, c0 + c1);
+        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, r.x[S][i]);
+        wave_lds_fence();
+        float xv[NCB * 8];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int kc = 0; kc < 8; ++kc) xv[8 * cb + kc] = xs[xop[cb] + 8 * kc];
+        f4 c0[NCB], c1[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
+        mac<0, 8, 8>(c0, c1, r.a[S], xv);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb, c0[cb] + c1[cb]);
         if constexpr (KB == 2) {
-            f4 n0 = z, n1 = z;
-            mac<0, 8>(n0, n1, r.a[S] + 2, xv);
-            st4(qs + 4, n0 + n1);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
+            mac<0, 8, 8>(c0, c1, r.a[S] + 2, xv);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb + 4, c0[cb] + c1[cb]);
         }
     }
     // steps of one phase (tiles t0 .. t0 + kPhase - 1, register sets I0 ..)
@@ -237,8 +263,8 @@ struct Pipe {
     // ---- chain wave: mu_t+1 = q_t + D mu_t ----
     struct Chain {
         f4 a[kSets][NC2 + NC3];
-        f4 qg[kPhase][KB];
-        float bm[4 * KB];
+        f4 qg[kPhase][NCB][KB];
+        float bm[NCB * 4 * KB];   // block cb: moment row 4 j + l/16 in bm[4 KB cb + j]
     };
     template <int S>
     __device__ void chain_load(Chain& r, int t) const {
@@ -247,6 +273,15 @@ struct Pipe {
         seg<NC2>(r.a[S], rows(J, 2) + C2LO);
         if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, rows(J, 3) + C3LO);
     }
+    __device__ void store_mu(const Chain& r, int t) const {
+        float* ms = mring + (t % kMRing) * SLOT + lane * 8 * NCB;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const float* b = r.bm + 4 * KB * cb;
+            st4(ms + 8 * cb, f4{b[0], b[1], b[2], b[3]});
+            if constexpr (KB == 2) st4(ms + 8 * cb + 4, f4{b[4], b[5], b[6], b[7]});
+        }
+    }
     template <int S>
     __device__ void chain_step(Chain& r, int t) const {
         if constexpr (TAIL) {
@@ -254,21 +289,31 @@ struct Pipe {
         }
         __builtin_amdgcn_sched_barrier(0);
         chain_load<(S + kPD) % kSets>(r, t + kPD);
-        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        f4 c0 = r.qg[S % kPhase][0], c1 = z;
-        mac<C2LO, C2HI>(c0, c1, r.a[S], r.bm + (C2LO - 8));
-        const f4 m2 = c0 + c1;
-        f4 m3 = z;
-        if constexpr (KB == 2) {
-            f4 n0 = r.qg[S % kPhase][1], n1 = z;
-            mac<C3LO, C3HI>(n0, n1, r.a[S] + NC2, r.bm + (C3LO - 8));
-            m3 = n0 + n1;
+        f4 c0[NCB], c1[NCB], m2[NCB], m3[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            c0[cb] = r.qg[S % kPhase][cb][0];
+            c1[cb] = zero4();
         }
-        result_to_operand(m2, r.bm);
-        if constexpr (KB == 2) result_to_operand(m3, r.bm + 4);
-        float* ms = mring + ((t + 1) % kMRing) * kSlot + lane * 8;
-        st4(ms, f4{r.bm[0], r.bm[1], r.bm[2], r.bm[3]});
-        if constexpr (KB == 2) st4(ms + 4, f4{r.bm[4], r.bm[5], r.bm[6], r.bm[7]});
+        mac<C2LO, C2HI, 4 * KB>(c0, c1, r.a[S], r.bm + (C2LO - 8));
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) m2[cb] = c0[cb] + c1[cb];
+        if constexpr (KB == 2) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                c0[cb] = r.qg[S % kPhase][cb][1];
+                c1[cb] = zero4();
+            }
+            mac<C3LO, C3HI, 4 * KB>(c0, c1, r.a[S] + NC2, r.bm + (C3LO - 8));
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) m3[cb] = c0[cb] + c1[cb];
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            result_to_operand(m2[cb], r.bm + 4 * KB * cb);
+            if constexpr (KB == 2) result_to_operand(m3[cb], r.bm + 4 * KB * cb + 4);
+        }
+        store_mu(r, t + 1);
     }
     template <int I0, int I = 0>
     __device__ void chain_phase(Chain& r, int t0) const {
@@ -281,9 +326,12 @@ struct Pipe {
     __device__ void chain_phase_body(Chain& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
-            const float* qs = qring + ((t0 + i) % kQRing) * kSlot + lane * 8;
-            r.qg[i][0] = ld4(qs);
-            if constexpr (KB == 2) r.qg[i][1] = ld4(qs + 4);
+            const float* qs = qring + ((t0 + i) % kQRing) * SLOT + lane * 8 * NCB;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                r.qg[i][cb][0] = ld4(qs + 8 * cb);
+                if constexpr (KB == 2) r.qg[i][cb][1] = ld4(qs + 8 * cb + 4);
+            }
         }
         chain_phase<I0>(r, t0);
         lds_barrier();
@@ -303,13 +351,13 @@ struct Pipe {
         // mu_0: zero forward; inverse (-1)^p times the completion slots 0..k-1 of tile 0
         const float sgn = p ? -1.0f : 1.0f;
 #pragma unroll
-        for (int j = 0; j < 4 * KB; ++j) {
-            const int row = 4 * j + q;
-            r.bm[j] = (INV && row < k) ? sgn * src[e0 + 2 * row] : 0.0f;
-        }
-        float* ms = mring + lane * 8;
-        st4(ms, f4{r.bm[0], r.bm[1], r.bm[2], r.bm[3]});
-        if constexpr (KB == 2) st4(ms + 4, f4{r.bm[4], r.bm[5], r.bm[6], r.bm[7]});
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int j = 0; j < 4 * KB; ++j) {
+                const int row = 4 * j + q;
+                r.bm[4 * KB * cb + j] = (INV && row < k) ? sgn * src[e0[cb] + 2 * row] : 0.0f;
+            }
+        store_mu(r, 0);
         lds_barrier();
         int ph = 0;
         for (; ph + kRep <= nact; ph += kRep) chain_iter(r, ph);
@@ -318,20 +366,22 @@ struct Pipe {
         }
         lds_barrier();
 #pragma unroll
-        for (int j = 0; j < 4 * KB; ++j) bm_out[j] = r.bm[j];
+        for (int j = 0; j < NCB * 4 * KB; ++j) bm_out[j] = r.bm[j];
     }
 
     // forward completion rows (-1)^p mu_NT into slots 0..k-1 of tile 0
-    // (moment row 4 j + l/16 is bm[j], operand layout)
+    // (operand layout: moment row 4 j + l/16 of block cb is bm[4 KB cb + j])
     __device__ void completion(const float* bm) const {
         const float sgn = p ? -1.0f : 1.0f;
 #pragma unroll
-        for (int j = 0; j < 4 * KB; ++j) {
-            const int row = 4 * j + q;
-            float x = sgn * bm[j];
-            if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
-            if (row < k) dst[e0 + 2 * row] = x;
-        }
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int j = 0; j < 4 * KB; ++j) {
+                const int row = 4 * j + q;
+                float x = sgn * bm[4 * KB * cb + j];
+                if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
+                if (row < k) dst[e0[cb] + 2 * row] = x;
+            }
     }
 
     // ---- result waves: rows 16 RB .. 16 RB + 15 of o_t ----
@@ -340,9 +390,9 @@ struct Pipe {
         static constexpr int LO = RB == 0 ? R0LO : R1LO, HI = RB == 0 ? R0HI : R1HI;
         static constexpr int ND = (HI - LO) / 4;
         f4 a[kSets][ND + KB];
-        f4 w[kSets];   // kinetic phases of the two stored slots (re, im, re, im)
-        float x[kPhase][8];
-        float mu[kPhase][4 * KB];
+        f4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
+        float x[kPhase][NCB * 8];     // block cb: data chunk kc in x[.][8 cb + kc]
+        float mu[kPhase][NCB * 4 * KB];
     };
     template <int RB, int S>
     __device__ void out_load(Out<RB>& r, int t) const {
@@ -359,31 +409,34 @@ struct Pipe {
         __builtin_amdgcn_sched_barrier(0);
         out_load<RB, (S + kPD) % kSets>(r, t + kPD);
         constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI;
-        const f4 z = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        f4 c0 = z, c1 = z;
-        mac<LO, HI>(c0, c1, r.a[S], r.x[S % kPhase] + LO);
-        mac<8, MHI>(c0, c1, r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
-        const f4 o = c0 + c1;
+        f4 c0[NCB], c1[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
+        mac<LO, HI, 8>(c0, c1, r.a[S], r.x[S % kPhase] + LO);
+        mac<8, MHI, 4 * KB>(c0, c1, r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
         if constexpr (TAIL) {
             if (t >= NT) return;
         }
-        // result layout -> (channel l/8, slots 2 (l%8), 2 (l%8) + 1)
-        float* y = yring + RB * kYWave;
-        st4(y + col * kYCol + 4 * q, o);
-        wave_lds_fence();
-        const int c = lane >> 3, s0 = 2 * (lane & 7);
-        const f2 re = *reinterpret_cast<const f2*>(y + 2 * c * kYCol + s0);
-        const f2 im = *reinterpret_cast<const f2*>(y + (2 * c + 1) * kYCol + s0);
-        wave_lds_fence();
-        f4 v = f4{re.x, im.x, re.y, im.y};
-        if constexpr (KPH) {
-            const f4 w = r.w[S];
-            const float s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
-            v = f4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
-        }
-        // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
         const int J = tile(t);
-        *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0 + 64 * (int64_t)J + 2 * (16 * RB + s0)) = v;
+        const int c = lane >> 3, s0 = 2 * (lane & 7);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            // result layout -> (channel 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1)
+            float* y = yring + (RB * NCB + cb) * 16 * kYCol;
+            st4(y + col * kYCol + 4 * q, c0[cb] + c1[cb]);
+            wave_lds_fence();
+            const f2 re = *reinterpret_cast<const f2*>(y + 2 * c * kYCol + s0);
+            const f2 im = *reinterpret_cast<const f2*>(y + (2 * c + 1) * kYCol + s0);
+            wave_lds_fence();
+            f4 v = f4{re.x, im.x, re.y, im.y};
+            if constexpr (KPH) {
+                const f4 w = r.w[S];
+                const float s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
+                v = f4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+            }
+            // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
+            *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) = v;
+        }
     }
     template <int RB, int I0, int I = 0>
     __device__ void out_phase(Out<RB>& r, int t0) const {
@@ -396,17 +449,20 @@ struct Pipe {
     __device__ void out_phase_body(Out<RB>& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
-            const float* xs = xring + ((t0 + i) % kXRing) * kXSlot + xop;
-            const float* ms = mring + ((t0 + i) % kMRing) * kSlot + lane * 8;
-            const f4 m0 = ld4(ms);
+            const float* xs = xring + ((t0 + i) % kXRing) * XSLOT;
+            const float* ms = mring + ((t0 + i) % kMRing) * SLOT + lane * 8 * NCB;
 #pragma unroll
-            for (int kc = 0; kc < 8; ++kc) r.x[i][kc] = xs[8 * kc];
+            for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r.mu[i][j] = m0[j];
-            if constexpr (KB == 2) {
-                const f4 m1 = ld4(ms + 4);
+                for (int kc = 0; kc < 8; ++kc) r.x[i][8 * cb + kc] = xs[xop[cb] + 8 * kc];
+                const f4 m0 = ld4(ms + 8 * cb);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) r.mu[i][4 + j] = m1[j];
+                for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + j] = m0[j];
+                if constexpr (KB == 2) {
+                    const f4 m1 = ld4(ms + 8 * cb + 4);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + 4 + j] = m1[j];
+                }
             }
         }
         out_phase<RB, I0>(r, t0);
@@ -440,7 +496,7 @@ struct Pipe {
         // a compute unit start their waves one SIMD further along the sequence
         // 0, 2, 1, 3, so this order pairs a heavy and a light role on each SIMD.
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        float bm[4 * KB];
+        float bm[NCB * 4 * KB];
         switch (wave) {
             case 0: run_pre(); break;
             case 1: run_chain(bm); break;
@@ -456,30 +512,37 @@ struct Pipe {
     }
 };
 
+template <bool INV, bool KPH, int NCB>
+__device__ void run_item(const MItem& it, const float2* src, float2* dst, const PhaseArgs& ph, float* lds) {
+    const bool tail = it.NT % kSets != 0;
+    if (it.k > 16) {
+        if (tail) Pipe<INV, KPH, 2, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<INV, KPH, 2, false, NCB>(it, src, dst, ph, lds).run();
+    } else {
+        if (tail) Pipe<INV, KPH, 1, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<INV, KPH, 1, false, NCB>(it, src, dst, ph, lds).run();
+    }
+}
+
 template <bool INV, bool KPH>
 __global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const float2* src, float2* dst,
                                                     PhaseArgs ph) {
     extern __shared__ __align__(16) float lds[];
     const MItem& it = items[blockIdx.x];
     if (it.nch == 0) return;   // idle slot of the per-XCD schedule
-    const bool tail = it.NT % kSets != 0;
-    if (it.k > 16) {
-        if (tail) Pipe<INV, KPH, 2, true>(it, src, dst, ph, lds).run();
-        else Pipe<INV, KPH, 2, false>(it, src, dst, ph, lds).run();
-    } else {
-        if (tail) Pipe<INV, KPH, 1, true>(it, src, dst, ph, lds).run();
-        else Pipe<INV, KPH, 1, false>(it, src, dst, ph, lds).run();
-    }
+    if (it.NCB == 2) run_item<INV, KPH, 2>(it, src, dst, ph, lds);
+    else run_item<INV, KPH, 1>(it, src, dst, ph, lds);
 }
 
 }  // namespace
 
-static constexpr size_t kChainLds = sizeof(float) * kLdsFloats;
+size_t chain_lds_bytes(int ncb) { return sizeof(float) * (size_t)chain_lds_floats(ncb > 1 ? 2 : 1); }
 
 hipError_t set_lds_limits_chain() {
     hipError_t e = hipSuccess;
     auto set = [&](const void* f) {
-        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chain_lds_bytes(2));
     };
     set((const void*)mstage_chain<true, false>);
     set((const void*)mstage_chain<false, true>);
@@ -487,18 +550,19 @@ hipError_t set_lds_limits_chain() {
     return e;
 }
 
-hipError_t launch_mstage_chain(const MItem* d_items, int nitems, const void* src, void* dst, bool inverse,
+hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (inverse && ph.use) return hipErrorInvalidValue;   // phases are applied on the forward output only
     const float2* a = (const float2*)src;
     float2* b = (float2*)dst;
+    const size_t lds = chain_lds_bytes(ncb);
     if (inverse)
-        hipLaunchKernelGGL((mstage_chain<true, false>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<true, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     else if (ph.use)
-        hipLaunchKernelGGL((mstage_chain<false, true>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<false, true>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     else
-        hipLaunchKernelGGL((mstage_chain<false, false>), dim3(nitems), dim3(256), kChainLds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<false, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     return hipGetLastError();
 }
 
