@@ -34,11 +34,13 @@ struct MItem {
     int64_t off[kMaxChanPerItem];
 };
 
-// MFMA operand layout of one direction's blocks: for tile J, row block rb and
-// lane l, the NK = 4 NB consecutive floats A'[16 rb + l%16][4 kc + l/16],
-// kc = 0..NK-1, where A' is the zero-padded R16 x R16 block mapping the input
-// vector (tile data, then moments) to the output vector (tile result, then
-// next moments).  size: NT * R16 * R16 floats.
+// MFMA operand layout of one direction's blocks: for tile J, row block rb,
+// float group g < NB (chunks kc = 4 g .. 4 g + 3) and lane l, the 4 consecutive
+// floats A'[16 rb + l%16][4 kc + l/16] at ((J NB + rb) NB + g) 256 + 4 l, where
+// A' is the zero-padded R16 x R16 block mapping the input vector (tile data,
+// then moments) to the output vector (tile result, then next moments).  A
+// 16-byte load of group g by the 64 lanes reads 1 KiB contiguous.  size:
+// NT * R16 * R16 floats.
 inline size_t mfma_table_floats(int NT, int NB) { return (size_t)NT * 256 * NB * NB; }
 
 // How a stage multiplies by the diagonal phases of the split step.

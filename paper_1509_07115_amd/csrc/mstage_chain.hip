@@ -30,8 +30,8 @@
 // v_mfma_f32_16x16x4_f32 layouts: lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16].  The
 // 16 columns of block cb are channels 8 cb .. 8 cb + 7 times (re, im).  Operands use the table layout
-// of MItem::mf_f / mf_i with NB = 4 (per row block and lane, the 16 floats
-// A'[16 rb + l%16][4 kc + l/16], kc = 0..15).  Zero blocks are skipped: the
+// of MItem::mf_f / mf_i with NB = 4 (per tile, row block rb and group g of 4
+// chunks, 64 lanes x the 4 floats A'[16 rb + l%16][4 kc + l/16]).  Zero blocks are skipped: the
 // in-tile band of T and the moment-to-moment block are triangular (lower
 // forward, upper inverse), and moment columns past k = ceil(l/2) are padding
 // (KB = ceil(k/16) chunks of 16).
@@ -149,13 +149,13 @@ struct Pipe {
         const int c = t < NT ? t : NT - 1;
         return INV ? NT - 1 - c : c;
     }
-    __device__ const float DSBT_GLOBAL* rows(int J, int rb) const {
-        return tab + ((size_t)(J * 4 + rb) * 64 + lane) * 16;
-    }
+    // this lane's operand floats of chunks 4 g .. 4 g + 3, g = G .. G + N - 1, of
+    // row block rb of tile J (each group: 64 lanes x 4 floats contiguous)
     template <int N>
-    static __device__ void seg(f4* o, const float DSBT_GLOBAL* s) {
+    __device__ void seg(f4* o, int J, int rb, int G) const {
+        const f4 DSBT_GLOBAL* s = reinterpret_cast<const f4 DSBT_GLOBAL*>(tab + (size_t)(J * 4 + rb) * 1024) + lane;
 #pragma unroll
-        for (int i = 0; i < N; ++i) o[i] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(s + 4 * i);
+        for (int i = 0; i < N; ++i) o[i] = s[64 * (G + i)];
     }
     // for every block cb: acc[cb] += A[:, chunks LO..HI) B_cb, alternating two
     // accumulators; A chunk kc is float kc - LO of av, B_cb chunk kc is
@@ -192,8 +192,8 @@ struct Pipe {
     __device__ void pre_load(Pre& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);   // loads are issued in tile order (prologue included)
         const int J = tile(t);
-        seg<2>(r.a[S], rows(J, 2));
-        if constexpr (KB == 2) seg<2>(r.a[S] + 2, rows(J, 3));
+        seg<2>(r.a[S], J, 2, 0);
+        if constexpr (KB == 2) seg<2>(r.a[S] + 2, J, 3, 0);
         const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)J);
 #pragma unroll
         for (int i = 0; i < 2 * NCB; ++i) r.x[S][i] = g[i];
@@ -270,8 +270,8 @@ struct Pipe {
     __device__ void chain_load(Chain& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);
         const int J = tile(t);
-        seg<NC2>(r.a[S], rows(J, 2) + C2LO);
-        if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, rows(J, 3) + C3LO);
+        seg<NC2>(r.a[S], J, 2, C2LO / 4);
+        if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, J, 3, C3LO / 4);
     }
     __device__ void store_mu(const Chain& r, int t) const {
         float* ms = mring + (t % kMRing) * SLOT + lane * 8 * NCB;
@@ -398,9 +398,8 @@ struct Pipe {
     __device__ void out_load(Out<RB>& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);
         const int J = tile(t);
-        const float DSBT_GLOBAL* b = rows(J, RB);
-        seg<Out<RB>::ND>(r.a[S], b + Out<RB>::LO);
-        seg<KB>(r.a[S] + Out<RB>::ND, b + 8);
+        seg<Out<RB>::ND>(r.a[S], J, RB, Out<RB>::LO / 4);
+        seg<KB>(r.a[S] + Out<RB>::ND, J, RB, 2);
         if constexpr (KPH)
             r.w[S] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
     }

@@ -13,8 +13,8 @@
 // D[4 (l/16) + v][l%16].
 //
 // Wave w owns row block rb = w % NB for the column blocks it takes; its
-// NK = 4 NB operand floats per tile come straight from global memory (laid out
-// per lane, 16-byte loads).  Operands and tile data are loaded two tiles ahead
+// NK = 4 NB operand floats per tile come straight from global memory (16-byte
+// loads, each reading 1 KiB contiguous over the wave).  Operands and tile data are loaded two tiles ahead
 // into three register sets; the tile loop is unrolled by three so that no set
 // is renamed while its loads are in flight, and the loop body has no branch
 // around a global access (every thread issues the same loads and stores each
@@ -100,9 +100,9 @@ struct MfmaTile {
     template <int S>
     __device__ void load(int step) {   // issue the loads of one tile (clamped to the last) into set S
         const int J = tile_of(step < NT ? step : NT - 1);
-        const f4 DSBT_GLOBAL* ap = reinterpret_cast<const f4 DSBT_GLOBAL*>(tab + (((size_t)J * NB + rb) * 64 + lane) * NK);
+        const f4 DSBT_GLOBAL* ap = reinterpret_cast<const f4 DSBT_GLOBAL*>(tab + ((size_t)J * NB + rb) * NK * 64) + lane;
 #pragma unroll
-        for (int i = 0; i < NK / 4; ++i) a[S][i] = ap[i];
+        for (int i = 0; i < NK / 4; ++i) a[S][i] = ap[64 * i];
 #pragma unroll
         for (int i = 0; i < GM; ++i) g[S][i] = src[gofs[i] + J * B];
     }

@@ -207,14 +207,15 @@ void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p,
         for (int rb = 0; rb < NB; ++rb) {
             for (int l = 0; l < 64; ++l) {
                 const int row = 16 * rb + (l % 16);
-                double* o = out.data() + (((size_t)J * NB + rb) * 64 + l) * NK;
+                // float group g = kc / 4 of lane l: 64 lanes x 4 floats contiguous
+                double* o = out.data() + ((size_t)J * NB + rb) * NK * 64 + 4 * l;
                 for (int kc = 0; kc < NK; ++kc) {
                     const int q = 4 * kc + l / 16;
                     if (row >= R || q >= R) continue;
                     double v = inverse ? M[(size_t)q * R + row] : M[(size_t)row * R + q];
                     // slot 0 of tile 0 is m = 0 for odd l, weighted by w_0
                     if (J == 0 && p == 0 && (inverse ? row == 0 : q == 0)) v *= w0;
-                    o[kc] = v;
+                    o[(kc / 4) * 256 + kc % 4] = v;
                 }
             }
         }
