@@ -51,11 +51,13 @@ constexpr int kPD = 3;                  // prefetch distance of the global opera
 constexpr int kSets = kPD + 1;          // register sets; set = tile mod kSets
 constexpr int kRep = kSets / kPhase;    // phases per loop iteration
 static_assert(kSets % kPhase == 0, "a loop iteration must cycle through the register sets exactly once");
-constexpr int kXRing = 3 * kPhase;      // tile data: written two phases before it is read
+// tile data: the pre wave writes tile t + 1 during step t, the result waves
+// read a tile two phases after its phase; 3 kPhase + 1 slots live
+constexpr int kXRing = 4 * kPhase;
 constexpr int kQRing = 2 * kPhase;      // Q x: read one phase after it is written
 constexpr int kMRing = 3 * kPhase;      // moments: 2 kPhase + 1 slots live
 static_assert(kMRing >= 2 * kPhase + 1, "moment ring too small");
-constexpr int kXCh = 72;                // floats per channel of a data slot (32 complex + padding)
+constexpr int kXCh = 68;                // floats per channel of a data slot (32 complex + padding)
 constexpr int kYCol = 20;               // result staging: floats per column (16 rows + padding)
 
 // LDS floats of an item of ncb column blocks: data ring (natural layout),
@@ -184,47 +186,67 @@ struct Pipe {
     static __device__ f4 zero4() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
 
     // ---- pre wave: q_t = Q x_t, x_t -> LDS ----
+    // Step t issues the loads (tables of t + kPD, data of t + kPD + 1), the
+    // matrix instructions of tile t from operands already in registers, the
+    // LDS round trip that turns tile t + 1 into the operand layout, and the
+    // read-out of tile t - 1 (in the same phase) while tile t's instructions run.
     struct Pre {
-        f4 a[kSets][2 * KB];
-        f4 x[kSets][2 * NCB];
+        f4 a[kSets][2 * KB];                // tables, tile t in set t % kSets
+        f4 x[kSets][2 * NCB];               // natural-layout data, tile t in set t % kSets
+        float xv[2][NCB * 8];               // operand layout of tile t in xv[t % 2]
+        f4 c0[kPhase][KB][NCB], c1[kPhase][KB][NCB];   // accumulators per step of a phase
     };
     template <int S>
-    __device__ void pre_load(Pre& r, int t) const {
-        __builtin_amdgcn_sched_barrier(0);   // loads are issued in tile order (prologue included)
+    __device__ void pre_load_tab(Pre& r, int t) const {
         const int J = tile(t);
         seg<2>(r.a[S], J, 2, 0);
         if constexpr (KB == 2) seg<2>(r.a[S] + 2, J, 3, 0);
-        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)J);
+    }
+    template <int S>
+    __device__ void pre_load_dat(Pre& r, int t) const {
+        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)tile(t));
 #pragma unroll
         for (int i = 0; i < 2 * NCB; ++i) r.x[S][i] = g[i];
     }
+    // tile t (data set S) -> LDS data slot, read back in the operand layout
     template <int S>
-    __device__ void pre_step(Pre& r, int t) const {
-        __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
-        pre_load<(S + kPD) % kSets>(r, t + kPD);
-        float* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
+    __device__ void pre_stage(Pre& r, int t) const {
         float* xs = xring + (t % kXRing) * XSLOT;
 #pragma unroll
         for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, r.x[S][i]);
         wave_lds_fence();
-        float xv[NCB * 8];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int kc = 0; kc < 8; ++kc) xv[8 * cb + kc] = xs[xop[cb] + 8 * kc];
-        f4 c0[NCB], c1[NCB];
+            for (int kc = 0; kc < 8; ++kc) r.xv[S & 1][8 * cb + kc] = xs[xop[cb] + 8 * kc];
+        wave_lds_fence();
+    }
+    template <int S>
+    __device__ void pre_mfma(Pre& r) const {
+        constexpr int I = S % kPhase;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
-        mac<0, 8, 8>(c0, c1, r.a[S], xv);
+        for (int h = 0; h < KB; ++h) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb, c0[cb] + c1[cb]);
-        if constexpr (KB == 2) {
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
-            mac<0, 8, 8>(c0, c1, r.a[S] + 2, xv);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb + 4, c0[cb] + c1[cb]);
+            for (int cb = 0; cb < NCB; ++cb) r.c0[I][h][cb] = r.c1[I][h][cb] = zero4();
+            mac<0, 8, 8>(r.c0[I][h], r.c1[I][h], r.a[S] + 2 * h, r.xv[S & 1]);
         }
+    }
+    template <int I>
+    __device__ void pre_readout(const Pre& r, int t) const {
+        float* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
+#pragma unroll
+        for (int h = 0; h < KB; ++h)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb + 4 * h, r.c0[I][h][cb] + r.c1[I][h][cb]);
+    }
+    template <int S>
+    __device__ void pre_step(Pre& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
+        pre_load_tab<(S + kPD) % kSets>(r, t + kPD);
+        pre_load_dat<(S + kPD + 1) % kSets>(r, t + kPD + 1);
+        if constexpr (S % kPhase > 0) pre_readout<S % kPhase - 1>(r, t - 1);
+        pre_mfma<S>(r);
+        pre_stage<(S + 1) % kSets>(r, t + 1);
     }
     // steps of one phase (tiles t0 .. t0 + kPhase - 1, register sets I0 ..)
     template <int I0, int I = 0>
@@ -232,6 +254,8 @@ struct Pipe {
         if constexpr (I < kPhase) {
             pre_step<I0 + I>(r, t0 + I);
             pre_phase<I0, I + 1>(r, t0);
+        } else {
+            pre_readout<kPhase - 1>(r, t0 + kPhase - 1);
         }
     }
     // phases ph .. ph + kRep - 1
@@ -245,9 +269,17 @@ struct Pipe {
     }
     __device__ void run_pre() const {
         Pre r;
-        pre_load<0>(r, 0);
-        pre_load<1>(r, 1);
-        pre_load<2>(r, 2);
+        __builtin_amdgcn_sched_barrier(0);   // prologue loads in the order of the steps
+        pre_load_tab<0>(r, 0);
+        pre_load_tab<1>(r, 1);
+        pre_load_tab<2>(r, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        pre_load_dat<0>(r, 0);
+        pre_load_dat<1>(r, 1);
+        pre_load_dat<2>(r, 2);
+        pre_load_dat<3>(r, 3);
+        __builtin_amdgcn_sched_barrier(0);
+        pre_stage<0>(r, 0);
         int ph = 0;
         for (; ph + kRep <= nact; ph += kRep) pre_iter(r, ph);
         if constexpr (TAIL) {
@@ -385,6 +417,10 @@ struct Pipe {
     }
 
     // ---- result waves: rows 16 RB .. 16 RB + 15 of o_t ----
+    // Step t issues the loads of tile t + kPD, the read-out and stores of tile
+    // t - 1 and the matrix instructions of tile t, so that the read-out runs
+    // while the matrix core works.  The first loop iteration is peeled (no tile
+    // -1), which keeps every loop body free of branches around memory operations.
     template <int RB>
     struct Out {
         static constexpr int LO = RB == 0 ? R0LO : R1LO, HI = RB == 0 ? R0HI : R1HI;
@@ -393,6 +429,8 @@ struct Pipe {
         f4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
         float x[kPhase][NCB * 8];     // block cb: data chunk kc in x[.][8 cb + kc]
         float mu[kPhase][NCB * 4 * KB];
+        f4 c0[2][NCB], c1[2][NCB];    // accumulators of tile t in [t % 2]
+        f4 wq[2];                     // kinetic phases of tile t in [t % 2]
     };
     template <int RB, int S>
     __device__ void out_load(Out<RB>& r, int t) const {
@@ -403,33 +441,23 @@ struct Pipe {
         if constexpr (KPH)
             r.w[S] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
     }
-    template <int RB, int S>
-    __device__ void out_step(Out<RB>& r, int t) const {
-        __builtin_amdgcn_sched_barrier(0);
-        out_load<RB, (S + kPD) % kSets>(r, t + kPD);
-        constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI;
-        f4 c0[NCB], c1[NCB];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) c0[cb] = c1[cb] = zero4();
-        mac<LO, HI, 8>(c0, c1, r.a[S], r.x[S % kPhase] + LO);
-        mac<8, MHI, 4 * KB>(c0, c1, r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
-        if constexpr (TAIL) {
-            if (t >= NT) return;
-        }
+    // read-out of tile t from accumulators [P]: result layout -> (channel
+    // 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through LDS, phase, 16-byte store
+    template <int RB, int P>
+    __device__ void out_epilogue(Out<RB>& r, int t) const {
         const int J = tile(t);
         const int c = lane >> 3, s0 = 2 * (lane & 7);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-            // result layout -> (channel 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1)
             float* y = yring + (RB * NCB + cb) * 16 * kYCol;
-            st4(y + col * kYCol + 4 * q, c0[cb] + c1[cb]);
+            st4(y + col * kYCol + 4 * q, r.c0[P][cb] + r.c1[P][cb]);
             wave_lds_fence();
             const f2 re = *reinterpret_cast<const f2*>(y + 2 * c * kYCol + s0);
             const f2 im = *reinterpret_cast<const f2*>(y + (2 * c + 1) * kYCol + s0);
             wave_lds_fence();
             f4 v = f4{re.x, im.x, re.y, im.y};
             if constexpr (KPH) {
-                const f4 w = r.w[S];
+                const f4 w = r.wq[P];
                 const float s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
                 v = f4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
             }
@@ -437,14 +465,32 @@ struct Pipe {
             *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) = v;
         }
     }
-    template <int RB, int I0, int I = 0>
+    template <int RB, int S, bool FIRST>
+    __device__ void out_step(Out<RB>& r, int t) const {
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!FIRST) {
+            if constexpr (TAIL) {
+                if (t - 1 < NT) out_epilogue<RB, (S + 1) & 1>(r, t - 1);
+            } else {
+                out_epilogue<RB, (S + 1) & 1>(r, t - 1);
+            }
+        }
+        out_load<RB, (S + kPD) % kSets>(r, t + kPD);
+        constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI, P = S & 1;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) r.c0[P][cb] = r.c1[P][cb] = zero4();
+        mac<LO, HI, 8>(r.c0[P], r.c1[P], r.a[S], r.x[S % kPhase] + LO);
+        mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
+        if constexpr (KPH) r.wq[P] = r.w[S];
+    }
+    template <int RB, int I0, bool FIRST, int I = 0>
     __device__ void out_phase(Out<RB>& r, int t0) const {
         if constexpr (I < kPhase) {
-            out_step<RB, I0 + I>(r, t0 + I);
-            out_phase<RB, I0, I + 1>(r, t0);
+            out_step<RB, I0 + I, FIRST && I0 + I == 0>(r, t0 + I);
+            out_phase<RB, I0, FIRST, I + 1>(r, t0);
         }
     }
-    template <int RB, int I0>
+    template <int RB, int I0, bool FIRST>
     __device__ void out_phase_body(Out<RB>& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
@@ -464,14 +510,14 @@ struct Pipe {
                 }
             }
         }
-        out_phase<RB, I0>(r, t0);
+        out_phase<RB, I0, FIRST>(r, t0);
         lds_barrier();
     }
-    template <int RB, int P = 0>
+    template <int RB, bool FIRST, int P = 0>
     __device__ void out_iter(Out<RB>& r, int ph) const {
         if constexpr (P < kRep) {
-            out_phase_body<RB, P * kPhase>(r, (ph + P) * kPhase);
-            out_iter<RB, P + 1>(r, ph);
+            out_phase_body<RB, P * kPhase, FIRST>(r, (ph + P) * kPhase);
+            out_iter<RB, FIRST, P + 1>(r, ph);
         }
     }
     template <int RB>
@@ -482,10 +528,15 @@ struct Pipe {
         out_load<RB, 2>(r, 2);
         lds_barrier();
         lds_barrier();
-        int ph = 0;
-        for (; ph + kRep <= nact; ph += kRep) out_iter<RB>(r, ph);
+        const int tl = nact * kPhase - 1;   // last step
         if constexpr (TAIL) {
-            if (ph < nact) out_phase_body<RB, 0>(r, ph * kPhase);
+            // nact == 1 < kRep: one phase
+            out_phase_body<RB, 0, true>(r, 0);
+            if (tl < NT) out_epilogue<RB, (kPhase - 1) & 1>(r, tl);
+        } else {
+            out_iter<RB, true>(r, 0);
+            for (int ph = kRep; ph + kRep <= nact; ph += kRep) out_iter<RB, false>(r, ph);
+            out_epilogue<RB, (kSets - 1) & 1>(r, tl);   // nact is a multiple of kRep
         }
     }
 
