@@ -3,7 +3,8 @@
     python -m paper_1509_07115_amd.build      (or  python paper_1509_07115_amd/build.py)
 
 Every HIP translation unit is compiled with packed FP32 instructions disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``) and with matrix-core
+accumulators kept in VGPRs (``-mllvm -amdgpu-mfma-vgpr-form``).
 """
 from __future__ import annotations
 
@@ -29,8 +30,10 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     cc = hipcc()
+    # -amdgpu-mfma-vgpr-form: matrix-instruction accumulators in ordinary VGPRs
+    # (no v_accvgpr_read per result register)
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(HERE, "..", "include"), "-Wall", "-Wno-unused-result"]
     tmp = tempfile.mkdtemp(prefix="dsbt_build_")
     try:
