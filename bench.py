@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBps": 8000.0, "mfma_fp32_TFLOPs": 157.3}
+PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP events
 
 # HBM traffic of one moment-stage launch (forward and inverse averaged) on this
 # workload, from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs of this
@@ -243,19 +244,26 @@ def main():
     torch.cuda.synchronize()
 
     progress("warmup done; timing")
-    # timed region: K steps, per-stage HIP events on the launch stream
+    # timed region: K steps.  Per-stage HIP events on the launch stream bracket
+    # the launches of every PROFILE_EVERY-th step (events on every launch would
+    # add their own gaps to the step time).
     plan.profile(True)
+    plan.profile(False)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        sample = i % PROFILE_EVERY == 0
+        if sample:
+            plan.profile(True, clear=False)
         plan.forward(x, b)
         plan.inverse(b, y)
+        if sample:
+            plan.profile(False)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     stages = plan.profile_read()
-    plan.profile(False)
     ms_step = total_ms / args.steps
     alg = algorithmic_counts(w.channels)
     pts = alg["points"]
@@ -272,6 +280,7 @@ def main():
     else:
         roof = roofline("sine/cosine stage (dsbt::fstage_n)", alg["flops_sincos"], alg["bytes_sincos"], avg_f, None)
     roof["stages_ms_per_launch"] = {"sincos": avg_f, "moment": avg_m}
+    roof["stage_launches_timed"] = {"sincos": n_f, "moment": n_m, "every_nth_step": PROFILE_EVERY}
 
     progress(f"timed {args.steps} steps: {ms_step:.4f} ms per step; checking l = 1, 32, 63 against the oracle")
     # accuracy on sampled l groups against the FP64 oracle

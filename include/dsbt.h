@@ -164,9 +164,10 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
 
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is
- * bracketed by HIP events recorded on the launch stream.  enable != 0 clears
- * the accumulators; enable == 0 stops recording.  Adds two event records per
- * launch. */
+ * bracketed by HIP events recorded on the launch stream.  enable == 1 clears
+ * the accumulators and starts recording; enable == 2 resumes recording and
+ * keeps them (to sample some launches of a longer run); enable == 0 stops
+ * recording.  Adds two event records per recorded launch. */
 dsbt_status dsbt_profile_enable(dsbt_plan p, int32_t enable);
 enum { DSBT_STAGE_SINCOS = 0, DSBT_STAGE_MOMENT = 1, DSBT_NUM_STAGES = 2 };
 /* Synchronises on the recorded events and returns, per stage (index as above,

@@ -161,9 +161,11 @@ class Plan:
                                               _stream_handle(stream)), "dsbt_step_grad_s")
         return out
 
-    def profile(self, enable: bool = True):
-        """Start (clearing) or stop per-stage HIP-event timing (``dsbt_profile_enable``)."""
-        _lib.check(self._lib.dsbt_profile_enable(self._h, 1 if enable else 0), "dsbt_profile_enable")
+    def profile(self, enable: bool = True, clear: bool = True):
+        """Start or stop per-stage HIP-event timing (``dsbt_profile_enable``);
+        ``clear=False`` resumes without clearing what was recorded."""
+        mode = (1 if clear else 2) if enable else 0
+        _lib.check(self._lib.dsbt_profile_enable(self._h, mode), "dsbt_profile_enable")
 
     def profile_read(self) -> dict:
         """{stage: (milliseconds summed, launches)} for "sincos" and "moment" (``dsbt_profile_read``)."""

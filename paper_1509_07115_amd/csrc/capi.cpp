@@ -413,6 +413,24 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     for (auto& g : P->groups)
         if (tabs[g.ell].NB == 8) any_nb8 = true;
     P->mf_waves = any_nb8 ? 8 : 4;
+    int ncu = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t pr;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
+            pr.multiProcessorCount >= 8)
+            ncu = pr.multiProcessorCount;
+    }
+    // four-wave pipeline: 16 channels (two column blocks) per item halve the
+    // table reads per channel, but only while that still gives every compute
+    // unit an item (each item is a serial chain of tile steps)
+    int wide = 1;
+    if (P->mf_waves == 4 && (cpb <= 0 || cpb > 8)) {
+        size_t n16 = 0;
+        for (auto& g : P->groups)
+            if (tabs[g.ell].mf) n16 += (g.chans.size() + 15) / 16;
+        wide = n16 >= (size_t)ncu ? 2 : 1;
+    }
     std::vector<dsbt::MItem> items_mf, items_v1;
     std::vector<int> items_mf_ell;
     P->h_items1.assign(nch, dsbt::MItem{});
@@ -439,9 +457,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         const bool mf = t.mf != nullptr;
         int per = dsbt::kMaxChanPerItem;
         if (mf) {
-            // the four-wave pipeline takes 16 channels (two column blocks) per
-            // item unless the caller caps the item at 8
-            base.NCB = P->mf_waves == 4 ? (cpb > 0 && cpb <= 8 ? 1 : 2) : dsbt::mfma_ncb(P->mf_waves, base.NB);
+            base.NCB = P->mf_waves == 4 ? wide : dsbt::mfma_ncb(P->mf_waves, base.NB);
             per = 8 * base.NCB;
         }
         if (cpb > 0) per = std::min(per, cpb);
@@ -483,14 +499,6 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     // holds the r-th heaviest item of every compute unit.
     {
         const int nx = 8, chunk = 4;
-        int ncu = 256;
-        {
-            int dev = 0;
-            hipDeviceProp_t pr;
-            if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
-                pr.multiProcessorCount >= nx)
-                ncu = pr.multiProcessorCount;
-        }
         const int cpx = ncu / nx;
         // matrix instructions per tile: the four-wave pipeline skips zero blocks
         auto cost_of = [&](const dsbt::MItem& it) {
@@ -955,7 +963,7 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
 dsbt_status dsbt_profile_enable(dsbt_plan p, int32_t enable) {
     if (!p) return fail(DSBT_ERR_INVALID_ARG, "plan is NULL");
     return guarded([&]() -> dsbt_status {
-        if (enable) {
+        if (enable == 1) {
             for (auto& t : p->prof_events) {
                 p->event_pool.push_back(std::get<1>(t));
                 p->event_pool.push_back(std::get<2>(t));
