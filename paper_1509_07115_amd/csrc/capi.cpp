@@ -327,9 +327,10 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         tileB[ell] = B;
     }
     // moment tables per l
-    struct Tab { const void* f; const void* i; const float* mf; const float* mi; int NB; };
+    struct Tab { const void* f; const void* i; const void* mf; const void* mi; int NB; };
     std::map<int, Tab> tabs;
     const bool fp32 = std::is_same<T, float>::value;
+    const bool c64x = P->precision == DSBT_C64_FP64;   // complex64 data, FP64 arithmetic
     // FP64 blocks generated on the device (default) or by host threads
     DeviceScratch scratch;
     if (P->opts.plan_where == DSBT_PLAN_ON_DEVICE) {
@@ -353,9 +354,17 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             t.NB = R16 / 16;
             std::vector<double> arr;
             dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, false, arr);
-            t.mf = (const float*)upload_converted<float>(P, arr, s);
+            t.mf = upload_converted<float>(P, arr, s);
             dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, true, arr);
-            t.mi = (const float*)upload_converted<float>(P, arr, s);
+            t.mi = upload_converted<float>(P, arr, s);
+        } else if (c64x && B == 32 && R <= R16) {
+            // FP64 tables in the same operand layout for the FP64 four-wave pipeline
+            t.NB = 4;
+            std::vector<double> arr;
+            dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, false, arr);
+            t.mf = upload_converted<double>(P, arr, s);
+            dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, true, arr);
+            t.mi = upload_converted<double>(P, arr, s);
         } else {
             std::vector<double> tr(blk.size());
             for (int J = 0; J < NT; ++J) {
@@ -425,7 +434,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     // table reads per channel, but only while that still gives every compute
     // unit an item (each item is a serial chain of tile steps)
     int wide = 1;
-    if (P->mf_waves == 4 && (cpb <= 0 || cpb > 8)) {
+    if (fp32 && P->mf_waves == 4 && (cpb <= 0 || cpb > 8)) {
         size_t n16 = 0;
         for (auto& g : P->groups)
             if (tabs[g.ell].mf) n16 += (g.chans.size() + 15) / 16;
@@ -566,7 +575,8 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     const size_t m_lds = P->cmp_bytes * (size_t)dsbt::kMaxChanPerItem * P->maxR;
     hip_check(dsbt::set_lds_limits<T>(m_lds), "set LDS limits");
     hip_check(dsbt::set_lds_limits_mfma(), "set LDS limits");
-    hip_check(dsbt::set_lds_limits_chain(), "set LDS limits");
+    hip_check(dsbt::set_lds_limits_chain<float>(), "set LDS limits");
+    hip_check(dsbt::set_lds_limits_chain<double>(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
 }
 
@@ -588,9 +598,12 @@ void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
 // Matrix-core moment stage: the four-wave pipeline when every item has B = 32,
 // else the row-block kernel (B = 64 items need 8 waves).  ncb: the largest
 // column-block count of the launched items.
+// T: arithmetic precision (FP64 only for complex64 data with FP64 arithmetic,
+// whose tables are all B = 32).
+template <typename T>
 hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, int ncb, const void* src, void* dst,
                      bool inverse, dsbt::PhaseArgs ph, hipStream_t s) {
-    if (P->mf_waves == 4) return dsbt::launch_mstage_chain(items, n, ncb, src, dst, inverse, ph, s);
+    if (P->mf_waves == 4) return dsbt::launch_mstage_chain<T>(items, n, ncb, src, dst, inverse, ph, s);
     return dsbt::launch_mstage_mfma(items, n, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s);
 }
 
@@ -598,7 +611,7 @@ template <typename T, typename S>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(launch_mf(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -612,7 +625,7 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
                         dsbt::PhaseArgs ph) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
         if (P->items1_mf[c])
-            hip_check(launch_mf(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T>(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
         else
             hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
     });

@@ -25,8 +25,9 @@ struct FChan {
 struct MItem {
     const void* tab_f;     // NT blocks, A[q][r] = M_J[r][q]
     const void* tab_i;     // NT blocks, A[q][r] = M_J[q][r]
-    const float* mf_f;     // MFMA operand layout of the forward blocks (FP32 plans), or nullptr
-    const float* mf_i;     // MFMA operand layout of the inverse blocks
+    const void* mf_f;      // MFMA operand layout of the forward blocks (FP32, or FP64 for FP64
+                           // arithmetic on complex64 data), or nullptr
+    const void* mf_i;      // MFMA operand layout of the inverse blocks
     const void* kphase;    // unit-modulus exp(-i K_n tau) per slot (complex of the data precision), or nullptr
     int B, k, R, NT, p, nch;
     int NB;                // 16-row blocks of the padded block size R16 = 16 NB (1, 2, 4 or 8)
@@ -112,13 +113,18 @@ inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
 }
 hipError_t set_lds_limits_mfma();
 // Moment stage for items with NB = 4 (B = 32, k <= 32) as a four-wave pipeline
-// per item (Q x, moment chain, two result row blocks); 256 threads.  An item
-// has NCB = 1 or 2 blocks of 8 channels (off[]: slots past nch repeat a real
-// channel); ncb is the largest NCB of the launched items and sizes the LDS.
-// Runs in place.  Phases (ph.use) are supported on the forward direction only.
+// per item (Q x, moment chain, two result row blocks); 256 threads.  Complex64
+// data; T = float (FP32 tables and arithmetic) or double (FP64 tables and
+// arithmetic, items of one column block).  An item has NCB = 1 or 2 blocks of
+// 8 channels (off[]: slots past nch repeat a real channel); ncb is the largest
+// NCB of the launched items and sizes the LDS.  Runs in place.  Phases
+// (ph.use, complex of T per slot) are supported on the forward direction only.
+template <typename T>
 hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s);
+template <typename T>
 hipError_t set_lds_limits_chain();
+template <typename T>
 size_t chain_lds_bytes(int ncb);
 
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into

@@ -28,7 +28,8 @@
 // the LDS rings small enough for three items per compute unit.
 //
 // v_mfma_f32_16x16x4_f32 layouts: lane l holds A[l%16][l/16] and
-// B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16].  The
+// B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16]
+// (v_mfma_f64_16x16x4_f64: the same operands, result row 4 v + l/16).  The
 // 16 columns of block cb are channels 8 cb .. 8 cb + 7 times (re, im).  Operands use the table layout
 // of MItem::mf_f / mf_i with NB = 4 (per tile, row block rb and group g of 4
 // chunks, 64 lanes x the 4 floats A'[16 rb + l%16][4 kc + l/16]).  Zero blocks are skipped: the
@@ -46,6 +47,24 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 // 16-byte global access of two complex64 values, which are 8-byte aligned
 typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
 
+// Arithmetic precision of the pipeline: float (complex64 plans) or double
+// (complex64 data with FP64 arithmetic and tables).  Data in memory are
+// complex64 either way.
+template <typename T>
+struct Arith;
+template <>
+struct Arith<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    static __device__ v4 mfma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Arith<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    static __device__ v4 mfma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+
 constexpr int kPhase = 2;               // tiles per phase
 constexpr int kPD = 3;                  // prefetch distance of the global operands, in tiles
 constexpr int kSets = kPD + 1;          // register sets; set = tile mod kSets
@@ -57,13 +76,13 @@ constexpr int kXRing = 4 * kPhase;
 constexpr int kQRing = 2 * kPhase;      // Q x: read one phase after it is written
 constexpr int kMRing = 3 * kPhase;      // moments: 2 kPhase + 1 slots live
 static_assert(kMRing >= 2 * kPhase + 1, "moment ring too small");
-constexpr int kXCh = 68;                // floats per channel of a data slot (32 complex + padding)
-constexpr int kYCol = 20;               // result staging: floats per column (16 rows + padding)
+constexpr int kXCh = 68;                // values per channel of a data slot (32 complex + padding)
+constexpr int kYCol = 20;               // result staging: values per column (16 rows + padding)
 
-// LDS floats of an item of ncb column blocks: data ring (natural layout),
-// Q x and moment rings (8 floats per lane and block), result staging of the
-// two result waves
-__host__ __device__ constexpr int chain_lds_floats(int ncb) {
+// LDS values (of the arithmetic type) of an item of ncb column blocks: data
+// ring (natural layout), Q x and moment rings (8 values per lane and block),
+// result staging of the two result waves
+__host__ __device__ constexpr int chain_lds_values(int ncb) {
     return kXRing * 8 * ncb * kXCh + (kQRing + kMRing) * 64 * 8 * ncb + 2 * ncb * 16 * kYCol;
 }
 
@@ -75,21 +94,37 @@ __device__ __forceinline__ void wave_lds_fence() {
 }
 
 // (row 4 (l/16) + v, column l%16) in register v  ->  (row 4 j + l/16) in out[j]:
-// a transpose of the 4 x 4 grid (lane quarter, register).  The 32-lane swap
-// exchanges the high bits of the two indices, the 16-lane swap the low bits.
-__device__ __forceinline__ void result_to_operand(f4 m, float* out) {
-    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[0]), __float_as_uint(m[2]), false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(m[1]), __float_as_uint(m[3]), false, false);
+// a transpose of the 4 x 4 grid (lane quarter, register) of 32-bit words.  The
+// 32-lane swap exchanges the high bits of the two indices, the 16-lane swap
+// the low bits.
+__device__ __forceinline__ void transpose_words(const unsigned* m, unsigned* out) {
+    const auto a = __builtin_amdgcn_permlane32_swap(m[0], m[2], false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(m[1], m[3], false, false);
     const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
     const auto d = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
-    out[0] = __uint_as_float(c[0]);
-    out[1] = __uint_as_float(c[1]);
-    out[2] = __uint_as_float(d[0]);
-    out[3] = __uint_as_float(d[1]);
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = d[0];
+    out[3] = d[1];
+}
+__device__ __forceinline__ void result_to_operand(Arith<float>::v4 m, float* out) {
+    const unsigned w[4] = {__float_as_uint(m[0]), __float_as_uint(m[1]), __float_as_uint(m[2]), __float_as_uint(m[3])};
+    unsigned o[4];
+    transpose_words(w, o);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = __uint_as_float(o[j]);
+}
+// v_mfma_f64_16x16x4_f64 returns row 4 v + l/16 in register v (measured on
+// gfx950): its result is already in the operand layout
+__device__ __forceinline__ void result_to_operand(Arith<double>::v4 m, double* out) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = m[j];
 }
 
-template <bool INV, bool KPH, int KB, bool TAIL, int NCB>
+template <typename T, bool INV, bool KPH, int KB, bool TAIL, int NCB>
 struct Pipe {
+    using V4 = typename Arith<T>::v4;
+    using V2 = typename Arith<T>::v2;
     // chunk kc = A' columns 4 kc .. 4 kc + 3 (0..7 tile data, 8.. moments)
     static constexpr int MHI = 8 + 4 * KB;
     static constexpr int R0LO = 0, R0HI = INV ? 8 : 4;      // result rows 0..15, data chunks
@@ -97,19 +132,19 @@ struct Pipe {
     static constexpr int C2LO = 8, C2HI = INV ? MHI : 12;   // moment rows 0..15, moment chunks
     static constexpr int C3LO = INV ? 12 : 8, C3HI = MHI;   // moment rows 16..31 (KB = 2)
     static constexpr int NC2 = (C2HI - C2LO) / 4, NC3 = KB == 2 ? (C3HI - C3LO) / 4 : 0;
-    static constexpr int SLOT = 64 * 8 * NCB;               // floats per Q x / moment slot
-    static constexpr int XSLOT = 8 * NCB * kXCh;            // floats per data slot
+    static constexpr int SLOT = 64 * 8 * NCB;               // values per Q x / moment slot
+    static constexpr int XSLOT = 8 * NCB * kXCh;            // values per data slot
     static constexpr int YWAVE = NCB * 16 * kYCol;          // result staging per result wave
     static constexpr int LPC = 8 / NCB, FPL = 8 * NCB;      // pre-wave loads: lanes per channel, floats per lane
 
     const float DSBT_GLOBAL* src;
     float DSBT_GLOBAL* dst;
-    const float DSBT_GLOBAL* tab;
-    const f2 DSBT_GLOBAL* kphase;
-    float* xring;
-    float* qring;
-    float* mring;
-    float* yring;
+    const T DSBT_GLOBAL* tab;
+    const V2 DSBT_GLOBAL* kphase;   // complex of the arithmetic precision
+    T* xring;
+    T* qring;
+    T* mring;
+    T* yring;
     int NT, k, p, lane, q, col, nact;
     int64_t e0[NCB];   // float index of (channel 8 cb + col/2, slot 0, re/im col%2)
     // natural layout: the pre wave's lane l loads channel l/LPC, FPL floats
@@ -117,11 +152,11 @@ struct Pipe {
     // 2 (l%8), 2 (l%8) + 1 of channel 8 cb + l/8 in a 16-row block
     int64_t gpre;      // float index of the pre wave's first float in tile 0
     int64_t g0[NCB];   // float index of (channel 8 cb + l/8, slot 0)
-    int xnat;          // float offset of the pre wave's loaded floats in a data slot
-    int xop[NCB];      // float offset of operand (slot l/16, column l%16 of block cb) in a data slot
+    int xnat;          // offset of the pre wave's loaded values in a data slot
+    int xop[NCB];      // offset of operand (slot l/16, column l%16 of block cb) in a data slot
     bool conj;
 
-    __device__ Pipe(const MItem& it, const float2* s_, float2* d_, const PhaseArgs& ph, float* lds)
+    __device__ Pipe(const MItem& it, const float2* s_, float2* d_, const PhaseArgs& ph, T* lds)
         : src(as_global(reinterpret_cast<const float*>(s_))), dst(as_global_rw(reinterpret_cast<float*>(d_))) {
         NT = it.NT;
         k = it.k;
@@ -130,8 +165,8 @@ struct Pipe {
         q = lane >> 4;
         col = lane & 15;
         conj = ph.conj != 0;
-        tab = as_global(INV ? it.mf_i : it.mf_f);
-        kphase = as_global(reinterpret_cast<const f2*>(it.kphase));
+        tab = as_global(static_cast<const T*>(INV ? it.mf_i : it.mf_f));
+        kphase = as_global(reinterpret_cast<const V2*>(it.kphase));
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             e0[cb] = 2 * it.off[8 * cb + (col >> 1)] + (col & 1);
@@ -154,36 +189,36 @@ struct Pipe {
     // this lane's operand floats of chunks 4 g .. 4 g + 3, g = G .. G + N - 1, of
     // row block rb of tile J (each group: 64 lanes x 4 floats contiguous)
     template <int N>
-    __device__ void seg(f4* o, int J, int rb, int G) const {
-        const f4 DSBT_GLOBAL* s = reinterpret_cast<const f4 DSBT_GLOBAL*>(tab + (size_t)(J * 4 + rb) * 1024) + lane;
+    __device__ void seg(V4* o, int J, int rb, int G) const {
+        const V4 DSBT_GLOBAL* s = reinterpret_cast<const V4 DSBT_GLOBAL*>(tab + (size_t)(J * 4 + rb) * 1024) + lane;
 #pragma unroll
         for (int i = 0; i < N; ++i) o[i] = s[64 * (G + i)];
     }
     // for every block cb: acc[cb] += A[:, chunks LO..HI) B_cb, alternating two
-    // accumulators; A chunk kc is float kc - LO of av, B_cb chunk kc is
+    // accumulators; A chunk kc is value kc - LO of av, B_cb chunk kc is
     // bv[BS cb + kc - LO]
     template <int LO, int HI, int BS>
-    static __device__ void mac(f4* c0, f4* c1, const f4* av, const float* bv) {
+    static __device__ void mac(V4* c0, V4* c1, const V4* av, const T* bv) {
 #pragma unroll
         for (int kc = LO; kc < HI; ++kc) {
             const int j = kc - LO;
-            const float x = av[j >> 2][j & 3];
+            const T x = av[j >> 2][j & 3];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                if (j & 1) c1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[BS * cb + j], c1[cb], 0, 0, 0);
-                else c0[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, bv[BS * cb + j], c0[cb], 0, 0, 0);
+                if (j & 1) c1[cb] = Arith<T>::mfma(x, bv[BS * cb + j], c1[cb]);
+                else c0[cb] = Arith<T>::mfma(x, bv[BS * cb + j], c0[cb]);
             }
         }
     }
     // x (w.x + i w.y) on the lane pair (re, im) of one complex value
-    static __device__ float phase(float x, f2 w, bool im, bool cj) {
-        const float y = __shfl_xor(x, 1, 64);
-        const float s = cj ? -w.y : w.y;
+    static __device__ T phase(T x, V2 w, bool im, bool cj) {
+        const T y = __shfl_xor(x, 1, 64);
+        const T s = cj ? -w.y : w.y;
         return im ? x * w.x + y * s : x * w.x - y * s;
     }
-    static __device__ f4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
-    static __device__ void st4(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
-    static __device__ f4 zero4() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+    static __device__ V4 ld4(const T* p) { return *reinterpret_cast<const V4*>(p); }
+    static __device__ void st4(T* p, V4 v) { *reinterpret_cast<V4*>(p) = v; }
+    static __device__ V4 zero4() { return V4{0, 0, 0, 0}; }
 
     // ---- pre wave: q_t = Q x_t, x_t -> LDS ----
     // Step t issues the loads (tables of t + kPD, data of t + kPD + 1), the
@@ -191,10 +226,10 @@ struct Pipe {
     // LDS round trip that turns tile t + 1 into the operand layout, and the
     // read-out of tile t - 1 (in the same phase) while tile t's instructions run.
     struct Pre {
-        f4 a[kSets][2 * KB];                // tables, tile t in set t % kSets
-        f4 x[kSets][2 * NCB];               // natural-layout data, tile t in set t % kSets
-        float xv[2][NCB * 8];               // operand layout of tile t in xv[t % 2]
-        f4 c0[kPhase][KB][NCB], c1[kPhase][KB][NCB];   // accumulators per step of a phase
+        V4 a[kSets][2 * KB];                // tables, tile t in set t % kSets
+        f4 x[kSets][2 * NCB];               // natural-layout data (complex64), tile t in set t % kSets
+        T xv[2][NCB * 8];                   // operand layout of tile t in xv[t % 2]
+        V4 c0[kPhase][KB][NCB], c1[kPhase][KB][NCB];   // accumulators per step of a phase
     };
     template <int S>
     __device__ void pre_load_tab(Pre& r, int t) const {
@@ -211,9 +246,9 @@ struct Pipe {
     // tile t (data set S) -> LDS data slot, read back in the operand layout
     template <int S>
     __device__ void pre_stage(Pre& r, int t) const {
-        float* xs = xring + (t % kXRing) * XSLOT;
+        T* xs = xring + (t % kXRing) * XSLOT;
 #pragma unroll
-        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, r.x[S][i]);
+        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, __builtin_convertvector(r.x[S][i], V4));
         wave_lds_fence();
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
@@ -233,7 +268,7 @@ struct Pipe {
     }
     template <int I>
     __device__ void pre_readout(const Pre& r, int t) const {
-        float* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
+        T* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
 #pragma unroll
         for (int h = 0; h < KB; ++h)
 #pragma unroll
@@ -294,9 +329,9 @@ struct Pipe {
 
     // ---- chain wave: mu_t+1 = q_t + D mu_t ----
     struct Chain {
-        f4 a[kSets][NC2 + NC3];
-        f4 qg[kPhase][NCB][KB];
-        float bm[NCB * 4 * KB];   // block cb: moment row 4 j + l/16 in bm[4 KB cb + j]
+        V4 a[kSets][NC2 + NC3];
+        V4 qg[kPhase][NCB][KB];
+        T bm[NCB * 4 * KB];   // block cb: moment row 4 j + l/16 in bm[4 KB cb + j]
     };
     template <int S>
     __device__ void chain_load(Chain& r, int t) const {
@@ -306,12 +341,12 @@ struct Pipe {
         if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, J, 3, C3LO / 4);
     }
     __device__ void store_mu(const Chain& r, int t) const {
-        float* ms = mring + (t % kMRing) * SLOT + lane * 8 * NCB;
+        T* ms = mring + (t % kMRing) * SLOT + lane * 8 * NCB;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-            const float* b = r.bm + 4 * KB * cb;
-            st4(ms + 8 * cb, f4{b[0], b[1], b[2], b[3]});
-            if constexpr (KB == 2) st4(ms + 8 * cb + 4, f4{b[4], b[5], b[6], b[7]});
+            const T* b = r.bm + 4 * KB * cb;
+            st4(ms + 8 * cb, V4{b[0], b[1], b[2], b[3]});
+            if constexpr (KB == 2) st4(ms + 8 * cb + 4, V4{b[4], b[5], b[6], b[7]});
         }
     }
     template <int S>
@@ -321,7 +356,7 @@ struct Pipe {
         }
         __builtin_amdgcn_sched_barrier(0);
         chain_load<(S + kPD) % kSets>(r, t + kPD);
-        f4 c0[NCB], c1[NCB], m2[NCB], m3[NCB];
+        V4 c0[NCB], c1[NCB], m2[NCB], m3[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             c0[cb] = r.qg[S % kPhase][cb][0];
@@ -358,7 +393,7 @@ struct Pipe {
     __device__ void chain_phase_body(Chain& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
-            const float* qs = qring + ((t0 + i) % kQRing) * SLOT + lane * 8 * NCB;
+            const T* qs = qring + ((t0 + i) % kQRing) * SLOT + lane * 8 * NCB;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
                 r.qg[i][cb][0] = ld4(qs + 8 * cb);
@@ -375,19 +410,19 @@ struct Pipe {
             chain_iter<P + 1>(r, ph);
         }
     }
-    __device__ void run_chain(float* bm_out) const {
+    __device__ void run_chain(T* bm_out) const {
         Chain r;
         chain_load<0>(r, 0);
         chain_load<1>(r, 1);
         chain_load<2>(r, 2);
         // mu_0: zero forward; inverse (-1)^p times the completion slots 0..k-1 of tile 0
-        const float sgn = p ? -1.0f : 1.0f;
+        const T sgn = p ? -1 : 1;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int j = 0; j < 4 * KB; ++j) {
                 const int row = 4 * j + q;
-                r.bm[4 * KB * cb + j] = (INV && row < k) ? sgn * src[e0[cb] + 2 * row] : 0.0f;
+                r.bm[4 * KB * cb + j] = (INV && row < k) ? sgn * (T)src[e0[cb] + 2 * row] : T(0);
             }
         store_mu(r, 0);
         lds_barrier();
@@ -403,16 +438,16 @@ struct Pipe {
 
     // forward completion rows (-1)^p mu_NT into slots 0..k-1 of tile 0
     // (operand layout: moment row 4 j + l/16 of block cb is bm[4 KB cb + j])
-    __device__ void completion(const float* bm) const {
-        const float sgn = p ? -1.0f : 1.0f;
+    __device__ void completion(const T* bm) const {
+        const T sgn = p ? -1 : 1;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int j = 0; j < 4 * KB; ++j) {
                 const int row = 4 * j + q;
-                float x = sgn * bm[4 * KB * cb + j];
+                T x = sgn * bm[4 * KB * cb + j];
                 if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
-                if (row < k) dst[e0[cb] + 2 * row] = x;
+                if (row < k) dst[e0[cb] + 2 * row] = (float)x;
             }
     }
 
@@ -425,12 +460,12 @@ struct Pipe {
     struct Out {
         static constexpr int LO = RB == 0 ? R0LO : R1LO, HI = RB == 0 ? R0HI : R1HI;
         static constexpr int ND = (HI - LO) / 4;
-        f4 a[kSets][ND + KB];
-        f4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
-        float x[kPhase][NCB * 8];     // block cb: data chunk kc in x[.][8 cb + kc]
-        float mu[kPhase][NCB * 4 * KB];
-        f4 c0[2][NCB], c1[2][NCB];    // accumulators of tile t in [t % 2]
-        f4 wq[2];                     // kinetic phases of tile t in [t % 2]
+        V4 a[kSets][ND + KB];
+        V4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
+        T x[kPhase][NCB * 8];         // block cb: data chunk kc in x[.][8 cb + kc]
+        T mu[kPhase][NCB * 4 * KB];
+        V4 c0[2][NCB], c1[2][NCB];    // accumulators of tile t in [t % 2]
+        V4 wq[2];                     // kinetic phases of tile t in [t % 2]
     };
     template <int RB, int S>
     __device__ void out_load(Out<RB>& r, int t) const {
@@ -439,7 +474,7 @@ struct Pipe {
         seg<Out<RB>::ND>(r.a[S], J, RB, Out<RB>::LO / 4);
         seg<KB>(r.a[S] + Out<RB>::ND, J, RB, 2);
         if constexpr (KPH)
-            r.w[S] = *reinterpret_cast<const f4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
+            r.w[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
     }
     // read-out of tile t from accumulators [P]: result layout -> (channel
     // 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through LDS, phase, 16-byte store
@@ -449,20 +484,27 @@ struct Pipe {
         const int c = lane >> 3, s0 = 2 * (lane & 7);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-            float* y = yring + (RB * NCB + cb) * 16 * kYCol;
-            st4(y + col * kYCol + 4 * q, r.c0[P][cb] + r.c1[P][cb]);
+            T* y = yring + (RB * NCB + cb) * 16 * kYCol;
+            const V4 o = r.c0[P][cb] + r.c1[P][cb];
+            if constexpr (sizeof(T) == sizeof(float)) {
+                st4(y + col * kYCol + 4 * q, o);   // rows 4 (l/16) + v
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[col * kYCol + 4 * v + q] = o[v];   // rows 4 v + l/16
+            }
             wave_lds_fence();
-            const f2 re = *reinterpret_cast<const f2*>(y + 2 * c * kYCol + s0);
-            const f2 im = *reinterpret_cast<const f2*>(y + (2 * c + 1) * kYCol + s0);
+            const V2 re = *reinterpret_cast<const V2*>(y + 2 * c * kYCol + s0);
+            const V2 im = *reinterpret_cast<const V2*>(y + (2 * c + 1) * kYCol + s0);
             wave_lds_fence();
-            f4 v = f4{re.x, im.x, re.y, im.y};
+            V4 v = V4{re.x, im.x, re.y, im.y};
             if constexpr (KPH) {
-                const f4 w = r.wq[P];
-                const float s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
-                v = f4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+                const V4 w = r.wq[P];
+                const T s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
+                v = V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
             }
             // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
-            *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) = v;
+            *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) =
+                __builtin_convertvector(v, f4u);
         }
     }
     template <int RB, int S, bool FIRST>
@@ -494,17 +536,17 @@ struct Pipe {
     __device__ void out_phase_body(Out<RB>& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
-            const float* xs = xring + ((t0 + i) % kXRing) * XSLOT;
-            const float* ms = mring + ((t0 + i) % kMRing) * SLOT + lane * 8 * NCB;
+            const T* xs = xring + ((t0 + i) % kXRing) * XSLOT;
+            const T* ms = mring + ((t0 + i) % kMRing) * SLOT + lane * 8 * NCB;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
                 for (int kc = 0; kc < 8; ++kc) r.x[i][8 * cb + kc] = xs[xop[cb] + 8 * kc];
-                const f4 m0 = ld4(ms + 8 * cb);
+                const V4 m0 = ld4(ms + 8 * cb);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + j] = m0[j];
                 if constexpr (KB == 2) {
-                    const f4 m1 = ld4(ms + 8 * cb + 4);
+                    const V4 m1 = ld4(ms + 8 * cb + 4);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + 4 + j] = m1[j];
                 }
@@ -546,7 +588,7 @@ struct Pipe {
         // a compute unit start their waves one SIMD further along the sequence
         // 0, 2, 1, 3, so this order pairs a heavy and a light role on each SIMD.
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        float bm[NCB * 4 * KB];
+        T bm[NCB * 4 * KB];
         switch (wave) {
             case 0: run_pre(); break;
             case 1: run_chain(bm); break;
@@ -562,58 +604,78 @@ struct Pipe {
     }
 };
 
-template <bool INV, bool KPH, int NCB>
-__device__ void run_item(const MItem& it, const float2* src, float2* dst, const PhaseArgs& ph, float* lds) {
+template <typename T, bool INV, bool KPH, int NCB>
+__device__ void run_item(const MItem& it, const float2* src, float2* dst, const PhaseArgs& ph, T* lds) {
     const bool tail = it.NT % kSets != 0;
     if (it.k > 16) {
-        if (tail) Pipe<INV, KPH, 2, true, NCB>(it, src, dst, ph, lds).run();
-        else Pipe<INV, KPH, 2, false, NCB>(it, src, dst, ph, lds).run();
+        if (tail) Pipe<T, INV, KPH, 2, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<T, INV, KPH, 2, false, NCB>(it, src, dst, ph, lds).run();
     } else {
-        if (tail) Pipe<INV, KPH, 1, true, NCB>(it, src, dst, ph, lds).run();
-        else Pipe<INV, KPH, 1, false, NCB>(it, src, dst, ph, lds).run();
+        if (tail) Pipe<T, INV, KPH, 1, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<T, INV, KPH, 1, false, NCB>(it, src, dst, ph, lds).run();
     }
 }
 
-template <bool INV, bool KPH>
+template <typename T, bool INV, bool KPH>
 __global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const float2* src, float2* dst,
                                                     PhaseArgs ph) {
-    extern __shared__ __align__(16) float lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
     const MItem& it = items[blockIdx.x];
     if (it.nch == 0) return;   // idle slot of the per-XCD schedule
-    if (it.NCB == 2) run_item<INV, KPH, 2>(it, src, dst, ph, lds);
-    else run_item<INV, KPH, 1>(it, src, dst, ph, lds);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        if (it.NCB == 2) {
+            run_item<T, INV, KPH, 2>(it, src, dst, ph, lds);
+            return;
+        }
+    }
+    run_item<T, INV, KPH, 1>(it, src, dst, ph, lds);   // FP64 items have one column block
 }
 
 }  // namespace
 
-size_t chain_lds_bytes(int ncb) { return sizeof(float) * (size_t)chain_lds_floats(ncb > 1 ? 2 : 1); }
+template <typename T>
+size_t chain_lds_bytes(int ncb) {
+    return sizeof(T) * (size_t)chain_lds_values(ncb > 1 ? 2 : 1);
+}
 
+template <typename T>
 hipError_t set_lds_limits_chain() {
     hipError_t e = hipSuccess;
+    const int bytes = (int)chain_lds_bytes<T>(sizeof(T) == sizeof(float) ? 2 : 1);
     auto set = [&](const void* f) {
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chain_lds_bytes(2));
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     };
-    set((const void*)mstage_chain<true, false>);
-    set((const void*)mstage_chain<false, true>);
-    set((const void*)mstage_chain<false, false>);
+    set((const void*)mstage_chain<T, true, false>);
+    set((const void*)mstage_chain<T, false, true>);
+    set((const void*)mstage_chain<T, false, false>);
     return e;
 }
 
+template <typename T>
 hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (inverse && ph.use) return hipErrorInvalidValue;   // phases are applied on the forward output only
+    if (sizeof(T) != sizeof(float) && ncb != 1) return hipErrorInvalidValue;
     const float2* a = (const float2*)src;
     float2* b = (float2*)dst;
-    const size_t lds = chain_lds_bytes(ncb);
+    const size_t lds = chain_lds_bytes<T>(ncb);
     if (inverse)
-        hipLaunchKernelGGL((mstage_chain<true, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, true, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     else if (ph.use)
-        hipLaunchKernelGGL((mstage_chain<false, true>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, false, true>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     else
-        hipLaunchKernelGGL((mstage_chain<false, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, false, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
     return hipGetLastError();
 }
+
+template size_t chain_lds_bytes<float>(int);
+template size_t chain_lds_bytes<double>(int);
+template hipError_t set_lds_limits_chain<float>();
+template hipError_t set_lds_limits_chain<double>();
+template hipError_t launch_mstage_chain<float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs, hipStream_t);
+template hipError_t launch_mstage_chain<double>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                hipStream_t);
 
 }  // namespace dsbt

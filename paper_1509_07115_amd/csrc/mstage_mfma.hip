@@ -75,7 +75,7 @@ struct MfmaTile {
         for (int i = 0; i < UMAX; ++i) cbs[i] = ((wave + WAVES * i) % (NB * NCB)) / NB;
         Xt = lds;
         Yt = lds + 2 * NCB * R16 * 16;
-        tab = as_global(INV ? it.mf_i : it.mf_f);
+        tab = as_global(static_cast<const float*>(INV ? it.mf_i : it.mf_f));
         kphase = as_global(reinterpret_cast<const f2*>(it.kphase));
         conj = ph.conj != 0;
         // element e = (channel, slot): 4 consecutive slots of one channel per
