@@ -30,8 +30,8 @@ PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP 
 # sources at the time of the measurement; after any change to them the figure
 # no longer applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h"],
-                  "sha256": "d6e84680ecad6f3be5892410552fd9fb5e7f8a52c723f89df4979eb675b8432a",
-                  "fetch_bytes": 143476636, "write_bytes": 67482512}
+                  "sha256": "3e7a7e9b8860d19f9eb05a08d05cd9b72d1bc0d22e8ca7d1316e8fb716826213",
+                  "fetch_bytes": 143461592, "write_bytes": 67482528}
 
 
 def sources_sha256(paths):
