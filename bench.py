@@ -210,6 +210,9 @@ def main():
                     help="skip the other workloads (uneven batch, 1000-step TDSE, adjoint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run device copies of 256 MiB (for scaling memory counters)")
+    ap.add_argument("--split-step-profile", action="store_true",
+                    help="only run --steps split steps of the 1000-step TDSE workload per precision "
+                         "(c64, c64x), launched one by one, for a kernel trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -226,6 +229,25 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 4}))
+        return
+
+    if args.split_step_profile:
+        w = workloads.tdse()
+        out = {}
+        for prec in ("c64", "c64x"):
+            plan = Plan(w.channels, precision=prec)
+            plan.set_potential(w.extra["V"], w.extra["dt"])
+            x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+            plan.kinetic_step(x, args.warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.kinetic_step(x, args.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            out[prec] = {"workload": w.name, "ms_per_step": e0.elapsed_time(e1) / args.steps, "steps": args.steps}
+            del plan
+        print(json.dumps(out))
         return
 
     if not os.path.exists(_lib.LIB_PATH):
