@@ -27,7 +27,8 @@ import numpy as np
 from . import dsbt
 from .sbf import corrected_momenta
 
-__all__ = ["kinetic_energies", "hamiltonian", "step", "propagate", "loss_and_grad", "loss_and_grad_blocks"]
+__all__ = ["kinetic_energies", "hamiltonian", "step", "propagate", "loss_and_grad", "loss_and_grad_blocks",
+           "imag_step", "orthonormalize", "energy_terms", "imag_time"]
 
 
 def kinetic_energies(N: int, rmax: float, ell: int, corrected: bool = False) -> np.ndarray:
@@ -118,3 +119,59 @@ def loss_and_grad_blocks(blocks, dt: float, s: np.ndarray):
             gs[t] += 0.5 * dt * float(np.sum(Vb * acc.imag))
         grads.append(lam)
     return L, grads, gs
+
+
+# --- Imaginary-time method (Sec. 4.3) -------------------------------------
+#
+# Bound states are found by propagating in imaginary time: t -> -i t turns
+# every unitary factor exp(-i X tau) of the step into the real decay
+# exp(-X tau), so the component along an eigenvector of energy E shrinks like
+# exp(-E tau) per step and the lowest state dominates.  Excited states of one
+# l are obtained by orthogonalising each state to the lower ones after every
+# step (Sec. 4.3), and the energy is the expectation of the dense
+# Hamiltonian of eq. H_DVR: <psi|B^T diag(E) B + diag(V)|psi> / <psi|psi>.
+
+
+def imag_step(psi: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray, dt: float) -> np.ndarray:
+    """One imaginary-time step exp(-V tau/2) F^T T^T exp(-E tau) T F exp(-V tau/2) on
+    psi of shape (N,) or (N, C)."""
+    pv = np.exp(-V * dt / 2.0)
+    pk = np.exp(-E * dt)
+    if psi.ndim == 2:
+        pv = pv[:, None]
+        pk = pk[:, None]
+    x = pv * psi
+    b = dsbt.forward(x, ell)
+    x = dsbt.inverse(pk * b, ell)
+    return pv * x
+
+
+def orthonormalize(X: np.ndarray) -> np.ndarray:
+    """Gram-Schmidt over the columns of X (N, m) in column order: column j loses
+    its components along the already orthonormalised columns 0..j-1 one at a
+    time (modified form), then is scaled to unit norm."""
+    Y = np.array(X, dtype=np.complex128)
+    for j in range(Y.shape[1]):
+        for i in range(j):
+            Y[:, j] -= np.vdot(Y[:, i], Y[:, j]) * Y[:, i]
+        Y[:, j] /= np.linalg.norm(Y[:, j])
+    return Y
+
+
+def energy_terms(psi: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Per column of psi (N,) or (N, C): [<psi|psi>, <psi|V|psi>, <psi|B^T E B|psi>]
+    (the kinetic term from b = T F psi, eq. H_DVR)."""
+    P = psi[:, None] if psi.ndim == 1 else psi
+    b = dsbt.forward(P, ell)
+    a2 = np.abs(P) ** 2
+    out = np.stack([a2.sum(0), (V[:, None] * a2).sum(0), (E[:, None] * np.abs(b) ** 2).sum(0)], 1)
+    return out[0] if psi.ndim == 1 else out
+
+
+def imag_time(X0: np.ndarray, ell: int, V: np.ndarray, E: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+    """nsteps imaginary-time steps of the states X0 (N, m) of one l, each followed by
+    orthonormalisation in column order (state j is kept orthogonal to states < j)."""
+    X = orthonormalize(X0)
+    for _ in range(nsteps):
+        X = orthonormalize(imag_step(X, ell, V, E, dt))
+    return X
