@@ -140,6 +140,22 @@ dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream);
  * exp(-i K_n tau) are formed from FP64 angles reduced mod 2 pi.  Synchronises. */
 dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt);
 
+/* Imaginary-time method (Sec. 4.3, t -> -i t): the step factors become the
+ * real decays exp(-V tau/2) and exp(-K_n tau), formed in FP64 and stored in
+ * the plan's step tables (as complex values with zero imaginary part).
+ * dsbt_kinetic_step then applies
+ *     psi <- exp(-V tau/2) F^T T^T exp(-K tau) T F exp(-V tau/2) psi,
+ * which damps every eigencomponent of energy E by exp(-E tau) per step (up to
+ * the splitting error), so repeated steps followed by dsbt_orthonormalize
+ * converge to the lowest bound states.  With this flag, dsbt_kinetic_step
+ * takes no strengths (s must be NULL) and dsbt_step_grad_s returns
+ * DSBT_ERR_PLAN_MISMATCH until the potential is set again without it. */
+enum { DSBT_TIME_IMAGINARY = 1 };
+
+/* dsbt_set_potential with flags: 0 (real time, the same as dsbt_set_potential)
+ * or DSBT_TIME_IMAGINARY.  Other bits: DSBT_ERR_INVALID_ARG.  Synchronises. */
+dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32_t flags);
+
 enum {
     DSBT_STEP_ADJOINT = 1,   /* apply U^H (conjugated phases), steps in reverse order */
     DSBT_STEP_GRAPH = 2,     /* capture the nsteps launches once in a hipGraph and replay it; the
@@ -161,6 +177,31 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
  * out is a device FP64 scalar; written, not accumulated. */
 dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
                              const void* lam_t, const void* lam_t1, double* out, void* stream);
+
+/* Energy terms of eq. H_DVR per channel (Sec. 4.1, used for the bound-state
+ * energies of Sec. 4.3): with b = T F psi,
+ *     out[3c + 0] = sum_i |psi_i|^2,
+ *     out[3c + 1] = sum_i V_i |psi_i|^2,
+ *     out[3c + 2] = sum_n K_n |b_n|^2,   K_n = k_n^2/2 as in dsbt_kinetic_momenta,
+ * so the energy of channel c is (out[3c+1] + out[3c+2]) / out[3c+0].  V is the
+ * potential of the last dsbt_set_potential(_ex) (DSBT_ERR_PLAN_MISMATCH if none).
+ * psi: device data buffer; work: device data buffer of the plan's size that
+ * receives b (must not alias psi); out: device FP64 array of 3 * nch values,
+ * written (not accumulated) in FP64 sums.  Enqueued on `stream`. */
+dsbt_status dsbt_energy(dsbt_plan p, const void* psi, void* work, double* out, void* stream);
+
+/* Gram-Schmidt orthonormalisation within sets of channels, in place on the
+ * device buffer psi (the orthogonalisation to lower states of Sec. 4.3).  sets
+ * is a HOST array of nsets + 1 channel indices, strictly increasing within
+ * [0, nch]; set k is the channels sets[k] .. sets[k+1]-1, which must share N
+ * (else DSBT_ERR_INVALID_ARG).  In channel order, each channel of a set loses
+ * its components <psi_i|psi_j> psi_i along the already orthonormalised
+ * channels i of its set (one at a time, FP64 sums), then is scaled to unit
+ * norm; a channel whose norm is zero is left zero.  Channels outside every set
+ * are not touched.  The set table is kept in the plan: a call with a table that
+ * differs from the previous call's synchronises `stream` and uploads it, other
+ * calls only enqueue one launch on `stream`. */
+dsbt_status dsbt_orthonormalize(dsbt_plan p, void* psi, const int32_t* sets, int32_t nsets, void* stream);
 
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is

@@ -126,13 +126,36 @@ class Plan:
                                           _stream_handle(stream)), "dsbt_inverse")
         return out
 
-    def set_potential(self, V: np.ndarray, dt: float):
-        """Radial potential in data layout (FP64 host array) and time step (``dsbt_set_potential``)."""
+    def set_potential(self, V: np.ndarray, dt: float, imaginary: bool = False):
+        """Radial potential in data layout (FP64 host array) and time step (``dsbt_set_potential_ex``);
+        ``imaginary``: real decay factors exp(-V tau/2), exp(-K tau) (imaginary-time method)."""
         V = np.ascontiguousarray(V, dtype=np.float64)
         if V.size < self.elems:
             raise ValueError("potential shorter than the data layout")
-        _lib.check(self._lib.dsbt_set_potential(self._h, V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                                float(dt)), "dsbt_set_potential")
+        flags = _lib.DSBT_TIME_IMAGINARY if imaginary else 0
+        _lib.check(self._lib.dsbt_set_potential_ex(self._h, V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                   float(dt), flags), "dsbt_set_potential_ex")
+
+    def energy(self, psi, work=None, out=None, stream=None):
+        """Per-channel energy terms (``dsbt_energy``): cuda float64 tensor (nch, 3) holding
+        <psi|psi>, <psi|V|psi>, <psi|K|psi>; work receives b = T F psi."""
+        import torch
+        work = self.empty() if work is None else work
+        if out is None:
+            out = torch.empty((len(self.channels), 3), dtype=torch.float64, device="cuda")
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and out.numel() >= 3 * len(self.channels)):
+            raise TypeError("out must be a contiguous cuda float64 tensor with 3 values per channel")
+        _lib.check(self._lib.dsbt_energy(self._h, self._check_buf(psi, "psi"), self._check_buf(work, "work"),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "dsbt_energy")
+        return out
+
+    def orthonormalize(self, psi, sets: Sequence[int], stream=None):
+        """Gram-Schmidt within channel sets [sets[k], sets[k+1]) in place (``dsbt_orthonormalize``)."""
+        arr = (ctypes.c_int32 * len(sets))(*[int(x) for x in sets])
+        _lib.check(self._lib.dsbt_orthonormalize(self._h, self._check_buf(psi, "psi"), arr, len(sets) - 1,
+                                                 _stream_handle(stream)), "dsbt_orthonormalize")
+        return psi
 
     def kinetic_step(self, psi, nsteps: int = 1, s=None, adjoint: bool = False, graph: bool = False,
                      resident: bool = False, stream=None):

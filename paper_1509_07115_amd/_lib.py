@@ -14,6 +14,7 @@ DSBT_SIGN_C, DSBT_SIGN_PRINTED_F = 0, 1
 DSBT_MODE_BATCHED, DSBT_MODE_PLAIN = 0, 1
 DSBT_PLAN_ON_DEVICE, DSBT_PLAN_ON_HOST = 0, 1
 DSBT_STEP_ADJOINT, DSBT_STEP_GRAPH, DSBT_STEP_RESIDENT = 1, 2, 4
+DSBT_TIME_IMAGINARY = 1
 
 STATUS_NAMES = {
     0: "DSBT_OK", -1: "DSBT_ERR_INVALID_ARG", -2: "DSBT_ERR_UNSUPPORTED", -3: "DSBT_ERR_OOM",
@@ -23,9 +24,9 @@ STATUS_NAMES = {
 # every symbol include/dsbt.h declares
 EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
-    "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_kinetic_step",
-    "dsbt_step_grad_s", "dsbt_profile_enable", "dsbt_profile_read", "dsbt_host_ftb_tables",
-    "dsbt_device_ftb_tables", "dsbt_kinetic_momenta",
+    "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_set_potential_ex",
+    "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
+    "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_device_ftb_tables", "dsbt_kinetic_momenta",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -71,6 +72,9 @@ def load() -> ctypes.CDLL:
         "dsbt_forward": (i32, [P, P, P, P]),
         "dsbt_inverse": (i32, [P, P, P, P]),
         "dsbt_set_potential": (i32, [P, ctypes.POINTER(dbl), dbl]),
+        "dsbt_set_potential_ex": (i32, [P, ctypes.POINTER(dbl), dbl, i32]),
+        "dsbt_energy": (i32, [P, P, P, P, P]),
+        "dsbt_orthonormalize": (i32, [P, P, ctypes.POINTER(i32), i32, P]),
         "dsbt_kinetic_step": (i32, [P, P, i32, P, i32, P]),
         "dsbt_step_grad_s": (i32, [P, P, P, P, P, P, P]),
         "dsbt_profile_enable": (i32, [P, i32]),

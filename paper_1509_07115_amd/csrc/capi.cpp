@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "plan_device.h"
 #include "plan_host.h"
+#include "state.h"
 
 namespace {
 
@@ -105,6 +106,22 @@ std::vector<unsigned char> phase_table(const std::vector<double>& ang, bool fp64
     return out;
 }
 
+// exp(-a) for every exponent a (imaginary time, t -> -i t): real factors stored
+// as complex values with zero imaginary part, in the layout of phase_table.
+std::vector<unsigned char> decay_table(const std::vector<double>& ex, bool fp64) {
+    std::vector<unsigned char> out(ex.size() * (fp64 ? sizeof(double2) : sizeof(float2)));
+    for (size_t i = 0; i < ex.size(); ++i) {
+        if (fp64) {
+            const double2 z = make_double2(std::exp(-ex[i]), 0.0);
+            std::memcpy(out.data() + i * sizeof(double2), &z, sizeof(z));
+        } else {
+            const float2 z = make_float2((float)std::exp(-ex[i]), 0.0f);
+            std::memcpy(out.data() + i * sizeof(float2), &z, sizeof(z));
+        }
+    }
+    return out;
+}
+
 }  // namespace
 
 struct dsbt_plan_s {
@@ -123,6 +140,7 @@ struct dsbt_plan_s {
         double rmax;
         std::vector<int> chans;
         void* d_kphase = nullptr;    // per slot (complex of the data precision), after set_potential
+        double* d_kin = nullptr;     // K_n = k_n^2/2 per slot (FP64), after set_potential
     };
     std::vector<Group> groups;
 
@@ -151,6 +169,15 @@ struct dsbt_plan_s {
     double dt = 0.0;
     void* d_vphase = nullptr;     // complex of the data precision
     double* d_vangle = nullptr;
+    bool imaginary = false;       // tables hold exp(-V tau/2), exp(-K tau) (DSBT_TIME_IMAGINARY)
+    dsbt::EChan* d_echans = nullptr;   // per channel, for dsbt_energy
+
+    // dsbt_orthonormalize: channel offsets and sizes, and the last set table
+    int64_t* d_off = nullptr;
+    int* d_nch = nullptr;
+    int* d_sets = nullptr;
+    int sets_cap = 0;
+    std::vector<int> h_sets;
     double* d_scratch = nullptr;
 
     // stage timing (dsbt_profile_enable)
@@ -820,8 +847,14 @@ dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream) {
 }
 
 dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
+    return dsbt_set_potential_ex(p, V, dt, 0);
+}
+
+dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32_t flags) {
     if (!p || !V) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DSBT_ERR_INVALID_ARG, "dt must be positive");
+    if (flags & ~DSBT_TIME_IMAGINARY) return fail(DSBT_ERR_INVALID_ARG, "unknown potential flag");
+    const bool imag = (flags & DSBT_TIME_IMAGINARY) != 0;
     return guarded([&]() -> dsbt_status {
         const int64_t n = p->elems;
         const bool fp64 = p->precision != DSBT_C64;   // phases in the arithmetic precision
@@ -833,7 +866,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
                 ang[x.offset + i] = v * dt / 2.0;
             }
         }
-        const std::vector<unsigned char> ph = phase_table(ang, fp64);
+        const std::vector<unsigned char> ph = imag ? decay_table(ang, fp64) : phase_table(ang, fp64);
         if (!p->d_vphase) {
             p->d_vphase = p->dalloc(ph.size());
             p->d_vangle = (double*)p->dalloc(sizeof(double) * n);
@@ -844,7 +877,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
         const double pi = 3.14159265358979323846;
         for (auto& g : p->groups) {
             const double dk = pi / g.rmax;
-            std::vector<double> ka(g.N), kc;
+            std::vector<double> ka(g.N), kin(g.N), kc;
             if (p->opts.kinetic == DSBT_K_CORRECTED) {
                 kc.resize(g.N);
                 dsbt::corrected_momenta(g.N, g.ell, g.rmax, kc.data());
@@ -852,11 +885,24 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
             for (int j = 0; j < g.N; ++j) {
                 const int nidx = j + g.p;
                 const double kn = !kc.empty() ? kc[j] : ((j < g.k) ? g.N * dk : nidx * dk);
-                ka[j] = 0.5 * kn * kn * dt;
+                kin[j] = 0.5 * kn * kn;
+                ka[j] = kin[j] * dt;
             }
-            const std::vector<unsigned char> kp = phase_table(ka, fp64);
+            const std::vector<unsigned char> kp = imag ? decay_table(ka, fp64) : phase_table(ka, fp64);
             if (!g.d_kphase) g.d_kphase = p->dalloc(kp.size());
             hip_check(hipMemcpy(g.d_kphase, kp.data(), kp.size(), hipMemcpyHostToDevice), "kphase");
+            if (!g.d_kin) g.d_kin = (double*)p->dalloc(sizeof(double) * g.N);
+            hip_check(hipMemcpy(g.d_kin, kin.data(), sizeof(double) * g.N, hipMemcpyHostToDevice), "kin");
+        }
+        // energy descriptors
+        {
+            std::vector<dsbt::EChan> ec(p->ch.size());
+            for (auto& g : p->groups)
+                for (int c : g.chans)
+                    ec[c] = dsbt::EChan{p->ch[c].offset, p->ch[c].N, 0, p->d_vangle + p->ch[c].offset, g.d_kin};
+            if (!p->d_echans) p->d_echans = (dsbt::EChan*)p->dalloc(sizeof(dsbt::EChan) * ec.size());
+            hip_check(hipMemcpy(p->d_echans, ec.data(), sizeof(dsbt::EChan) * ec.size(), hipMemcpyHostToDevice),
+                      "echans");
         }
         // refresh descriptors with the phase pointers
         for (size_t c = 0; c < p->ch.size(); ++c) {
@@ -878,6 +924,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
         refresh(p->h_items_v1, p->d_items_v1);
         refresh(p->h_items1, p->d_items1);
         p->has_potential = true;
+        p->imaginary = imag;
         p->dt = dt;
         if (p->graph_exec) {
             (void)hipGraphExecDestroy(p->graph_exec);
@@ -896,6 +943,7 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
     if (flags & ~(DSBT_STEP_ADJOINT | DSBT_STEP_GRAPH | DSBT_STEP_RESIDENT))
         return fail(DSBT_ERR_INVALID_ARG, "unknown step flag");
     if (flags & DSBT_STEP_RESIDENT) return fail(DSBT_ERR_UNSUPPORTED, "resident step kernel not built in");
+    if (p->imaginary && s) return fail(DSBT_ERR_INVALID_ARG, "strengths are not supported in imaginary time");
     if (nsteps == 0) return DSBT_OK;
     return guarded([&]() -> dsbt_status {
         hipStream_t st = (hipStream_t)stream;
@@ -960,6 +1008,7 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
                              const void* lam_t1, double* out, void* stream) {
     if (!p || !psi_t || !psi_t1 || !lam_t || !lam_t1 || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    if (p->imaginary) return fail(DSBT_ERR_PLAN_MISMATCH, "the potential was set for imaginary time");
     return guarded([&]() -> dsbt_status {
         const int nch = (int)p->ch.size();
         hipStream_t st = (hipStream_t)stream;
@@ -969,6 +1018,73 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
         else
             hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
                                                  st), "grad_s");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_energy(dsbt_plan p, const void* psi, void* work, double* out, void* stream) {
+    if (!p || !psi || !work || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (psi == work) return fail(DSBT_ERR_INVALID_ARG, "work must not alias psi");
+    if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    return guarded([&]() -> dsbt_status {
+        hipStream_t st = (hipStream_t)stream;
+        dsbt::PhaseArgs none{};
+        const int nch = (int)p->ch.size();
+        const double vscale = 2.0 / p->dt;   // d_vangle holds V tau/2
+        if (p->precision == DSBT_C128) {
+            enqueue_forward<double, double>(p, psi, work, st, none, none);
+            hip_check(dsbt::launch_energy_terms<double>(p->d_echans, nch, psi, work, vscale, out, st), "energy");
+        } else {
+            if (p->precision == DSBT_C64_FP64)
+                enqueue_forward<double, float>(p, psi, work, st, none, none);
+            else
+                enqueue_forward<float, float>(p, psi, work, st, none, none);
+            hip_check(dsbt::launch_energy_terms<float>(p->d_echans, nch, psi, work, vscale, out, st), "energy");
+        }
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_orthonormalize(dsbt_plan p, void* psi, const int32_t* sets, int32_t nsets, void* stream) {
+    if (!p || !psi || (!sets && nsets > 0)) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (nsets < 0) return fail(DSBT_ERR_INVALID_ARG, "negative set count");
+    if (nsets == 0) return DSBT_OK;
+    const int nch = (int)p->ch.size();
+    for (int k = 0; k < nsets; ++k) {
+        if (sets[k] < 0 || sets[k + 1] <= sets[k] || sets[k + 1] > nch)
+            return fail(DSBT_ERR_INVALID_ARG, "set boundaries must increase strictly within [0, nch]");
+        for (int c = sets[k] + 1; c < sets[k + 1]; ++c)
+            if (p->ch[c].N != p->ch[sets[k]].N) return fail(DSBT_ERR_INVALID_ARG, "channels of a set differ in N");
+    }
+    return guarded([&]() -> dsbt_status {
+        hipStream_t st = (hipStream_t)stream;
+        if (!p->d_off) {
+            std::vector<int64_t> off(nch);
+            std::vector<int> n(nch);
+            for (int c = 0; c < nch; ++c) {
+                off[c] = p->ch[c].offset;
+                n[c] = p->ch[c].N;
+            }
+            p->d_off = (int64_t*)p->dalloc(sizeof(int64_t) * nch);
+            p->d_nch = (int*)p->dalloc(sizeof(int) * nch);
+            hip_check(hipMemcpy(p->d_off, off.data(), sizeof(int64_t) * nch, hipMemcpyHostToDevice), "offsets");
+            hip_check(hipMemcpy(p->d_nch, n.data(), sizeof(int) * nch, hipMemcpyHostToDevice), "sizes");
+        }
+        const std::vector<int> want(sets, sets + nsets + 1);
+        if (want != p->h_sets) {
+            // a new set table: wait until no queued launch can still read the old one
+            hip_check(hipStreamSynchronize(st), "stream synchronize");
+            if (p->sets_cap < nsets + 1) {
+                p->d_sets = (int*)p->dalloc(sizeof(int) * (nsets + 1));
+                p->sets_cap = nsets + 1;
+            }
+            hip_check(hipMemcpy(p->d_sets, want.data(), sizeof(int) * (nsets + 1), hipMemcpyHostToDevice), "sets");
+            p->h_sets = want;
+        }
+        if (p->precision == DSBT_C128)
+            hip_check(dsbt::launch_orthonormalize<double>(p->d_off, p->d_nch, p->d_sets, nsets, psi, st), "orthonormalize");
+        else
+            hip_check(dsbt::launch_orthonormalize<float>(p->d_off, p->d_nch, p->d_sets, nsets, psi, st), "orthonormalize");
         return DSBT_OK;
     });
 }

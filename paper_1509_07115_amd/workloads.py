@@ -21,6 +21,12 @@ Workloads (all inputs FP64 on the host, in channel order):
 * ``adjoint``            N = 2048, rmax = 100, l = 0..15 with all m (256 channels),
   psi0 and V as in ``tdse``; 200 strengths s_t ~ U[0.9, 1.1], dt = 0.01, and a
   target phi with N(0,1) + i N(0,1) entries, norm 1 (loss |<phi|psi_T>|^2).
+* ``hydrogen``           rmax = 102.4, N = rmax/dr (dr = 0.2, 0.1, 0.05 give 512, 1024,
+  2048): two l = 1 channels and one l = 2 channel (the l > 0 states of the
+  bound-state table of Sec. 4.3), V = -1/r, starting states either generic
+  (r^(l+1) exp(-r/2), r^(l+2) exp(-r/3)) or the hydrogen functions r^2 exp(-r/2),
+  r^2 (1 - r/6) exp(-r/3), r^3 exp(-r/3), each scaled to norm 1; the channel sets
+  [0, 2, 3] group the two l = 1 states.
 """
 from __future__ import annotations
 
@@ -30,7 +36,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-__all__ = ["Workload", "gaussian_orbitals", "batched_all_m", "uneven", "tdse", "adjoint", "grid",
+__all__ = ["Workload", "gaussian_orbitals", "batched_all_m", "uneven", "tdse", "adjoint", "hydrogen", "grid",
            "gaussian_sum"]
 
 
@@ -145,3 +151,19 @@ def adjoint(seed: int = 5, N: int = 2048, rmax: float = 100.0, lmax: int = 15, n
     w.name = f"adjoint N={N} rmax={rmax} lmax={lmax} ({len(w.channels)} channels, {nsteps} steps)"
     w.extra.update({"s": s, "phi": phi})
     return w
+
+
+def hydrogen(dr: float = 0.2, rmax: float = 102.4, start: str = "generic") -> Workload:
+    N = int(round(rmax / dr))
+    r = grid(N, rmax)
+    if start == "generic":
+        funcs = [(1, r ** 2 * np.exp(-r / 2)), (1, r ** 3 * np.exp(-r / 3)), (2, r ** 3 * np.exp(-r / 2))]
+    elif start == "hydrogen":
+        funcs = [(1, r ** 2 * np.exp(-r / 2)), (1, r ** 2 * (1 - r / 6) * np.exp(-r / 3)), (2, r ** 3 * np.exp(-r / 3))]
+    else:
+        raise ValueError(start)
+    chs = [(N, ell, rmax, (f / np.linalg.norm(f)).astype(np.complex128)) for ell, f in funcs]
+    channels, psi = _pack(chs)
+    V = np.concatenate([-1.0 / r] * len(chs))
+    return Workload(f"hydrogen l>0 states dr={dr} rmax={rmax} ({start} start)", channels, psi,
+                    {"V": V, "sets": [0, 2, 3], "states": [(1, 0), (1, 1), (2, 0)]})

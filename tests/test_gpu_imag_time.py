@@ -1,0 +1,206 @@
+"""Imaginary-time method on the GPU (Sec. 4.3) through the C ABI: the decaying
+step, the energy terms and the Gram-Schmidt kernel against the FP64 oracle,
+and the l > 0 bound-state energies of the hydrogen table."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import dsbt, tdse
+from paper_1509_07115_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_hydrogen.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu(built_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def Plan(*a, **k):
+    from paper_1509_07115_amd import Plan as P
+    return P(*a, **k)
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def mixed_channels():
+    """Channels of several l and two N, packed with a gap (offsets not contiguous)."""
+    spec = [(256, 0, 25.6), (256, 1, 25.6), (256, 2, 25.6), (256, 5, 25.6), (512, 3, 51.2), (512, 40, 51.2),
+            (256, 1, 25.6)]
+    chs, off = [], 0
+    for N, ell, rmax in spec:
+        chs.append((N, ell, rmax, off))
+        off += N + 16
+    return chs, off
+
+
+def random_state(chs, elems, seed):
+    rng = np.random.default_rng(seed)
+    psi = np.zeros(elems, dtype=np.complex128)
+    for N, _, _, off in chs:
+        x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        psi[off:off + N] = x / np.linalg.norm(x)
+    return psi
+
+
+def coulomb(chs, elems):
+    V = np.zeros(elems)
+    for N, _, rmax, off in chs:
+        V[off:off + N] = -1.0 / dsbt.grid_r(N, rmax)
+    return V
+
+
+TOL = {"c64": 1e-5, "c64x": 1e-5, "c128": 1e-11}
+
+
+@pytest.mark.parametrize("precision", ["c64", "c64x", "c128"])
+def test_imag_steps_match_oracle(precision):
+    chs, elems = mixed_channels()
+    psi = random_state(chs, elems, 11)
+    V, dt, nsteps = coulomb(chs, elems), 0.02, 3
+    plan = Plan(chs, precision=precision, kinetic="corrected")
+    plan.set_potential(V, dt, imaginary=True)
+    x = dev(psi, plan.dtype)
+    plan.kinetic_step(x, nsteps)
+    got = x.cpu().numpy().astype(np.complex128)
+    worst = 0.0
+    for N, ell, rmax, off in chs:
+        E = tdse.kinetic_energies(N, rmax, ell, corrected=True)
+        ref = psi[off:off + N]
+        for _ in range(nsteps):
+            ref = tdse.imag_step(ref, ell, V[off:off + N], E, dt)
+        worst = max(worst, np.linalg.norm(got[off:off + N] - ref) / np.linalg.norm(ref))
+    print(f"{precision}: worst per-channel relative error {worst:.2e}")
+    assert worst <= TOL[precision]
+
+
+def test_imag_graph_replay_equals_eager_and_rejects_strengths():
+    from paper_1509_07115_amd import DsbtError
+    chs, elems = mixed_channels()
+    psi = random_state(chs, elems, 12)
+    plan = Plan(chs, kinetic="corrected")
+    plan.set_potential(coulomb(chs, elems), 0.02, imaginary=True)
+    a, b = dev(psi, plan.dtype), dev(psi, plan.dtype)
+    for _ in range(3):   # the captured graph is replayed, with eager work between replays
+        plan.kinetic_step(b, 4, graph=True)
+        plan.kinetic_step(a, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(DsbtError, match="INVALID_ARG"):
+        plan.kinetic_step(a, 2, s=torch.ones(2, dtype=torch.float32, device="cuda"))
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(DsbtError, match="PLAN_MISMATCH"):
+        plan.step_grad_s(a, a, a, a, out)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_energy_terms_match_oracle(precision):
+    chs, elems = mixed_channels()
+    psi = random_state(chs, elems, 13)
+    V = coulomb(chs, elems)
+    plan = Plan(chs, precision=precision, kinetic="corrected")
+    plan.set_potential(V, 0.01, imaginary=True)
+    e = plan.energy(dev(psi, plan.dtype)).cpu().numpy()
+    for c, (N, ell, rmax, off) in enumerate(chs):
+        ref = tdse.energy_terms(psi[off:off + N], ell, V[off:off + N], tdse.kinetic_energies(N, rmax, ell, True))
+        np.testing.assert_allclose(e[c], ref, rtol=TOL[precision], atol=0)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_orthonormalize_matches_oracle(precision):
+    from paper_1509_07115_amd import DsbtError
+    spec = [(256, 1), (256, 1), (256, 1), (256, 2), (512, 3), (512, 3), (256, 0)]
+    chs, off = [], 0
+    for N, ell in spec:
+        chs.append((N, ell, 0.1 * N, off))
+        off += N
+    psi = random_state(chs, off, 14)
+    # correlated states, so that the projections are large
+    psi[256:512] += 0.8 * psi[0:256]
+    psi[512:768] += 0.5 * psi[256:512] - 0.3 * psi[0:256]
+    plan = Plan(chs, precision=precision)
+    x = dev(psi, plan.dtype)
+    for sets in ([0, 3, 4, 6], [0, 2]):    # two tables: the second call uploads a new one
+        y = x.clone()
+        plan.orthonormalize(y, sets)
+        got = y.cpu().numpy().astype(np.complex128)
+        ref = x.cpu().numpy().astype(np.complex128)
+        touched = set()
+        for a, b in zip(sets[:-1], sets[1:]):
+            N = chs[a][0]
+            cols = np.stack([ref[chs[c][3]:chs[c][3] + N] for c in range(a, b)], 1)
+            Q = tdse.orthonormalize(cols)
+            for j, c in enumerate(range(a, b)):
+                o = chs[c][3]
+                err = np.linalg.norm(got[o:o + N] - Q[:, j])
+                assert err <= 10 * TOL[precision], (sets, c, err)
+                touched.add(c)
+        for c in range(len(chs)):
+            if c not in touched:
+                o, N = chs[c][3], chs[c][0]
+                assert np.array_equal(got[o:o + N], ref[o:o + N])
+    for bad in ([0, 0], [0, 8], [3, 5], [2, 1]):
+        with pytest.raises(DsbtError, match="INVALID_ARG"):
+            plan.orthonormalize(x, bad)
+
+
+def imag_time_energies(w, precision, dt, nsteps, every=10):
+    plan = Plan(w.channels, precision=precision, kinetic="corrected")
+    plan.set_potential(w.extra["V"], dt, imaginary=True)
+    x = dev(w.psi, plan.dtype)
+    sets = w.extra["sets"]
+    plan.orthonormalize(x, sets)
+    for _ in range(nsteps // every):
+        plan.kinetic_step(x, every, graph=True)
+        plan.orthonormalize(x, sets)
+    e = plan.energy(x).cpu().numpy()
+    return (e[:, 1] + e[:, 2]) / e[:, 0], e[:, 0]
+
+
+def printed(g, col):
+    return {(row["l"], row["index"]): row["E"][col] for row in g["rows"]}
+
+
+@pytest.mark.parametrize("col", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_table1_hydrogen_from_hydrogen_start(precision, col):
+    # Sec. 4.3, the bound-state table, l > 0 rows: imaginary-time steps with the
+    # corrected momenta of eq. kcorr and orthogonalisation to the lower l = 1
+    # state, started from the hydrogen functions.  dt = 0.01 keeps the
+    # splitting error of the energies below 3e-9 (oracle, dr = 0.2).  complex128
+    # reproduces every printed digit; complex64 is within 3e-7 (FP32 rounding of
+    # the state and the sums) of the printed value's rounding interval.
+    g = json.load(open(GOLDEN))
+    dr = g["dr_columns"][col]
+    w = workloads.hydrogen(dr=dr, rmax=g["rmax"], start="hydrogen")
+    E, norms = imag_time_energies(w, precision, 0.01, 3000)
+    want = printed(g, col)
+    print(f"{precision} dr={dr}: E = {E}")
+    np.testing.assert_allclose(norms, 1.0, atol=1e-5)
+    for c, key in enumerate(w.extra["states"]):
+        if precision == "c128":
+            assert round(float(E[c]), 6) == pytest.approx(want[key], abs=1e-12), (key, E[c])
+        else:
+            assert abs(E[c] - want[key]) <= 5e-7 + 3e-7, (key, E[c])
+
+
+def test_table1_hydrogen_from_generic_start():
+    # the same from generic starting states (r^(l+1) e^(-r/2), r^(l+2) e^(-r/3)):
+    # 30000 steps of dt = 0.01 bring the slowest component (3p against 4p) below
+    # 1e-9 in the energy (oracle, dr = 0.2)
+    g = json.load(open(GOLDEN))
+    w = workloads.hydrogen(dr=g["dr_columns"][0], rmax=g["rmax"], start="generic")
+    E, _ = imag_time_energies(w, "c64", 0.01, 30000)
+    want = printed(g, 0)
+    print(f"c64 dr=0.2 generic start: E = {E}")
+    for c, key in enumerate(w.extra["states"]):
+        assert abs(E[c] - want[key]) <= 5e-7 + 3e-7, (key, E[c])
