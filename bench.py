@@ -213,6 +213,10 @@ def main():
     ap.add_argument("--split-step-profile", action="store_true",
                     help="only run --steps split steps of the 1000-step TDSE workload per precision "
                          "(c64, c64x), launched one by one, for a kernel trace")
+    ap.add_argument("--imag-time-profile", action="store_true",
+                    help="only time the imaginary-time method: the hydrogen l > 0 states (dr = 0.05, "
+                         "10 --steps steps per graph replay, then Gram-Schmidt) in c64 and c128, and the "
+                         "energy and orthonormalisation calls on the 1024-channel TDSE batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -247,6 +251,48 @@ def main():
             torch.cuda.synchronize()
             out[prec] = {"workload": w.name, "ms_per_step": e0.elapsed_time(e1) / args.steps, "steps": args.steps}
             del plan
+        print(json.dumps(out))
+        return
+
+    if args.imag_time_profile:
+        def timed(fn, n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        out = {}
+        w = workloads.hydrogen(dr=0.05, start="hydrogen")
+        for prec in ("c64", "c128"):
+            plan = Plan(w.channels, precision=prec, kinetic="corrected")
+            plan.set_potential(w.extra["V"], 0.01, imaginary=True)
+            x = torch.from_numpy(w.psi).to(plan.dtype).cuda()
+            sets = w.extra["sets"]
+
+            def block():
+                plan.kinetic_step(x, 10, graph=True)
+                plan.orthonormalize(x, sets)
+            timed(block, max(args.warmup, 1))
+            ms = timed(block, args.steps) / 10
+            e = plan.energy(x).cpu().numpy()
+            out[prec] = {"workload": w.name, "ms_per_step": ms, "steps": 10 * args.steps,
+                         "energies": [float(v) for v in (e[:, 1] + e[:, 2]) / e[:, 0]]}
+            del plan
+        w = workloads.tdse()
+        plan = Plan(w.channels, kinetic="corrected")
+        plan.set_potential(w.extra["V"], w.extra["dt"], imaginary=True)
+        x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+        work = plan.empty()
+        eo = torch.empty((len(w.channels), 3), dtype=torch.float64, device="cuda")
+        single = list(range(len(w.channels) + 1))
+        timed(lambda: plan.energy(x, work, eo), max(args.warmup, 1))
+        timed(lambda: plan.orthonormalize(x, single), max(args.warmup, 1))
+        out["batch"] = {"workload": w.name,
+                        "ms_energy": timed(lambda: plan.energy(x, work, eo), args.steps),
+                        "ms_orthonormalize_single": timed(lambda: plan.orthonormalize(x, single), args.steps),
+                        "calls": args.steps}
         print(json.dumps(out))
         return
 

@@ -152,8 +152,11 @@ class Plan:
 
     def orthonormalize(self, psi, sets: Sequence[int], stream=None):
         """Gram-Schmidt within channel sets [sets[k], sets[k+1]) in place (``dsbt_orthonormalize``)."""
-        arr = (ctypes.c_int32 * len(sets))(*[int(x) for x in sets])
-        _lib.check(self._lib.dsbt_orthonormalize(self._h, self._check_buf(psi, "psi"), arr, len(sets) - 1,
+        key = tuple(int(x) for x in sets)
+        if getattr(self, "_sets_key", None) != key:    # marshal a set table once, not per call
+            self._sets_arr = (ctypes.c_int32 * len(key))(*key)
+            self._sets_key = key
+        _lib.check(self._lib.dsbt_orthonormalize(self._h, self._check_buf(psi, "psi"), self._sets_arr, len(key) - 1,
                                                  _stream_handle(stream)), "dsbt_orthonormalize")
         return psi
 
