@@ -11,5 +11,6 @@ dsbt     dense FP64 transform built straight from the definitions (Sec. 2.2-2.5)
 exact    exact-rational (``fractions``) DLOP / DDLOP / T for tiny grids (Sec. 2.3-2.5, App. A)
 tdse     dense split-operator step, propagation and adjoint gradient (Sec. 4.1)
 sbf      spherical-Bessel references: closed forms, quadrature, corrected momenta (Sec. 3)
+monomial the paper's own monomial-moment fast multiplication (Sec. 2.6), FP64, for its error envelope
 """
-from . import dsbt, exact, tdse, sbf  # noqa: F401
+from . import dsbt, exact, tdse, sbf, monomial  # noqa: F401
