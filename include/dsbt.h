@@ -100,8 +100,21 @@ typedef struct {
                              blocks are computed by GPU kernels; DSBT_PLAN_ON_HOST: by host threads */
     int32_t tile;         /* moment tile B (power of two >= ceil((l+1)/2)); 0 = automatic */
     int32_t chans_per_block; /* channels per workgroup in the transform stage; 0 = automatic */
-    int32_t reserved[9];
+    int32_t algorithm;    /* DSBT_ALG_TILED (default) or DSBT_ALG_MONOMIAL, see below */
+    int32_t reserved[8];
 } dsbt_plan_opts;
+
+/* Moment-stage algorithm.  DSBT_ALG_TILED: the numerically stable tiled moment
+ * form.  DSBT_ALG_MONOMIAL: the paper's own fast multiplication of Sec. 2.6
+ * (eqs. DP_expan, fast_b_f, sum_in_b_f, rec_sum_b_f and, inverse, fast_f_b,
+ * sum_in_f_b, fast_f_b_lowm, rec_sum_f_b): prefix and suffix sums of m^nu f_m
+ * against the monomial coefficients xi_nu(n) of the DDLOP, in FP64, one wave per
+ * channel.  Exact in exact arithmetic, but its sums cancel terms that grow
+ * quickly with l, so its FP64 error rises from ~1e-15 at l <= 8 to ~1e-11 at
+ * l = 16 and ~1e-7 at l = 24; it is kept to measure that.  Needs DSBT_C128 and
+ * DSBT_MODE_BATCHED, l <= 128 and N^(l-1) within the FP64 range (else
+ * DSBT_ERR_UNSUPPORTED).  Plan creation expands xi in binary128 on the host. */
+enum { DSBT_ALG_TILED = 0, DSBT_ALG_MONOMIAL = 1 };
 
 /* Fill *o with the defaults above (all zero). */
 void dsbt_plan_opts_default(dsbt_plan_opts* o);
@@ -221,6 +234,17 @@ dsbt_status dsbt_profile_read(dsbt_plan p, double* ms, int64_t* launches, int32_
  * [J B, J B + B).  If out is NULL or out_len is too small only *needed is set. */
 dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
                                  int64_t out_len, int64_t* needed);
+
+/* Host FP64 tables of the monomial variant (DSBT_ALG_MONOMIAL) for one (N, l),
+ * for testing without a GPU.  With k = ceil(l/2), p = 1 for even l (else 0),
+ * n_0 = ceil((l+1)/2) and R = N + p - n_0 regular rows n = n_0 .. N + p - 1:
+ * xi[(n - n_0) k + q] = xi_nu(n) of eq. DP_expan for nu = (l+1) mod 2 + 2q,
+ * alpha[n - n_0] = alpha_n (Sec. 2.4), comp[q N + j] = T_{p+q, j+p} (the
+ * completion rows, slot order).  sizes (3 values, may be NULL) receives
+ * R k, R and k N; any array may be NULL (not written), else it must hold its
+ * size. */
+dsbt_status dsbt_host_monomial_tables(int32_t N, int32_t ell, double* xi, double* alpha, double* comp,
+                                      int64_t* sizes);
 
 /* The same blocks computed by the device plan generator (the FP64 kernels that
  * dsbt_plan_create runs with DSBT_PLAN_ON_DEVICE) on the current HIP device,

@@ -44,11 +44,13 @@ class Plan:
     mode: "batched" (default) or "plain" (one launch per channel and stage).
     plan_where: "device" (default, FP64 plan kernels on the GPU) or "host".
     kinetic: "plain" (k_n = n dk) or "corrected" (roots of eq. kcorr) momenta of the step.
+    algorithm: "tiled" (default, the stable tiled moment form) or "monomial" (the paper's own
+        monomial-moment fast multiplication of Sec. 2.6, FP64, complex128 plans only).
     """
 
     def __init__(self, channels: Sequence, precision: str = "c64", mode: str = "batched", tile: int = 0,
                  chans_per_block: int = 0, sign: bool = True, plan_where: str = "device", kinetic: str = "plain",
-                 stream=None, _create=True):
+                 algorithm: str = "tiled", stream=None, _create=True):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         self.precision = precision
@@ -58,13 +60,13 @@ class Plan:
         arr = (_lib.Channel * len(self.channels))()
         for i, (N, ell, rmax, off) in enumerate(self.channels):
             arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
-        opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where, kinetic)
+        opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where, kinetic, algorithm)
         _lib.check(self._lib.dsbt_plan_create(ctypes.byref(self._h), arr, len(self.channels), ctypes.byref(opts),
                                               _stream_handle(stream)), "dsbt_plan_create")
         self._info()
 
     @staticmethod
-    def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device", kinetic="plain"):
+    def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device", kinetic="plain", algorithm="tiled"):
         o = _lib.PlanOpts()
         o.precision = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128, "c64x": _lib.DSBT_C64_FP64}[precision]
         o.mode = {"batched": _lib.DSBT_MODE_BATCHED, "plain": _lib.DSBT_MODE_PLAIN}[mode]
@@ -73,6 +75,7 @@ class Plan:
         o.sign = _lib.DSBT_SIGN_C if sign else _lib.DSBT_SIGN_PRINTED_F
         o.plan_where = {"device": _lib.DSBT_PLAN_ON_DEVICE, "host": _lib.DSBT_PLAN_ON_HOST}[plan_where]
         o.kinetic = {"plain": _lib.DSBT_K_PLAIN, "corrected": _lib.DSBT_K_CORRECTED}[kinetic]
+        o.algorithm = {"tiled": _lib.DSBT_ALG_TILED, "monomial": _lib.DSBT_ALG_MONOMIAL}[algorithm]
         return o
 
     @classmethod
@@ -223,6 +226,17 @@ def host_ftb_tables(N: int, ell: int, B: int) -> np.ndarray:
     k = (ell + 1) // 2
     R = B + k
     return out.reshape(N // B, R, R)
+
+
+def host_monomial_tables(N: int, ell: int):
+    """(xi, alpha, comp) of the monomial variant for one (N, l) (``dsbt_host_monomial_tables``)."""
+    lib = _lib.load()
+    sz = (ctypes.c_int64 * 3)()
+    _lib.check(lib.dsbt_host_monomial_tables(N, ell, None, None, None, sz), "dsbt_host_monomial_tables")
+    out = [np.zeros(max(int(n), 1)) for n in sz]
+    ptr = [o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in out]
+    _lib.check(lib.dsbt_host_monomial_tables(N, ell, *ptr, sz), "dsbt_host_monomial_tables")
+    return tuple(o[: int(n)] for o, n in zip(out, sz))
 
 
 def device_ftb_tables(N: int, ell: int, B: int, stream=None) -> np.ndarray:

@@ -15,6 +15,7 @@ DSBT_MODE_BATCHED, DSBT_MODE_PLAIN = 0, 1
 DSBT_PLAN_ON_DEVICE, DSBT_PLAN_ON_HOST = 0, 1
 DSBT_STEP_ADJOINT, DSBT_STEP_GRAPH, DSBT_STEP_RESIDENT = 1, 2, 4
 DSBT_TIME_IMAGINARY = 1
+DSBT_ALG_TILED, DSBT_ALG_MONOMIAL = 0, 1
 
 STATUS_NAMES = {
     0: "DSBT_OK", -1: "DSBT_ERR_INVALID_ARG", -2: "DSBT_ERR_UNSUPPORTED", -3: "DSBT_ERR_OOM",
@@ -26,7 +27,8 @@ EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_set_potential_ex",
     "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
-    "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_device_ftb_tables", "dsbt_kinetic_momenta",
+    "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
+    "dsbt_kinetic_momenta",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -39,7 +41,8 @@ class Channel(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("kinetic", ctypes.c_int32), ("sign", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("plan_where", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("chans_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("chans_per_block", ctypes.c_int32), ("algorithm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class DsbtError(RuntimeError):
@@ -80,6 +83,8 @@ def load() -> ctypes.CDLL:
         "dsbt_profile_enable": (i32, [P, i32]),
         "dsbt_profile_read": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "dsbt_host_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]),
+        "dsbt_host_monomial_tables": (i32, [i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                            ctypes.POINTER(i64)]),
         "dsbt_device_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64), P]),
         "dsbt_kinetic_momenta": (i32, [i32, i32, dbl, i32, ctypes.POINTER(dbl)]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),

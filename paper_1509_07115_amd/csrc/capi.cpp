@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "plan_device.h"
 #include "plan_host.h"
+#include "monomial.h"
 #include "state.h"
 
 namespace {
@@ -172,6 +173,10 @@ struct dsbt_plan_s {
     bool imaginary = false;       // tables hold exp(-V tau/2), exp(-K tau) (DSBT_TIME_IMAGINARY)
     dsbt::EChan* d_echans = nullptr;   // per channel, for dsbt_energy
 
+    // monomial-moment variant (DSBT_ALG_MONOMIAL): per channel, in channel order
+    std::vector<dsbt::LChan> h_lchans;
+    dsbt::LChan* d_lchans = nullptr;
+
     // dsbt_orthonormalize: channel offsets and sizes, and the last set table
     int64_t* d_off = nullptr;
     int* d_nch = nullptr;
@@ -311,6 +316,30 @@ void upload_fchans_n(dsbt_plan_s* P) {
     std::vector<dsbt::FChan> v(P->ch.size());
     for (size_t i = 0; i < v.size(); ++i) v[i] = P->h_fchans[P->order_n[i]];
     hip_check(hipMemcpy(P->d_fchans_n, v.data(), sizeof(dsbt::FChan) * v.size(), hipMemcpyHostToDevice), "fchans");
+}
+
+// Tables and channel descriptors of the monomial-moment variant, per (N, l) group.
+void build_monomial(dsbt_plan_s* P) {
+    P->h_lchans.assign(P->ch.size(), dsbt::LChan{});
+    for (auto& g : P->groups) {
+        std::vector<double> xi, alpha, comp;
+        dsbt::monomial_tables(g.N, g.ell, xi, alpha, comp);
+        auto up = [&](const std::vector<double>& v) -> const double* {
+            auto* d = (double*)P->dalloc(sizeof(double) * v.size());
+            if (!v.empty())
+                hip_check(hipMemcpy(d, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice), "monomial tables");
+            return d;
+        };
+        const double* dx = up(xi);
+        const double* da = up(alpha);
+        const double* dc = up(comp);
+        for (int c : g.chans)
+            P->h_lchans[c] = dsbt::LChan{P->ch[c].offset, g.N, g.ell, g.p, dsbt::n0_of(g.ell), g.k, (g.ell + 1) % 2,
+                                         dx, da, dc, nullptr};
+    }
+    P->d_lchans = (dsbt::LChan*)P->dalloc(sizeof(dsbt::LChan) * P->h_lchans.size());
+    hip_check(hipMemcpy(P->d_lchans, P->h_lchans.data(), sizeof(dsbt::LChan) * P->h_lchans.size(),
+                        hipMemcpyHostToDevice), "monomial channels");
 }
 
 template <typename T>
@@ -605,6 +634,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     hip_check(dsbt::set_lds_limits_chain<float>(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_chain<double>(), "set LDS limits");
     hip_check(dsbt::set_lds_limits_fstage_n<T>(), "set LDS limits");
+    if (P->opts.algorithm == DSBT_ALG_MONOMIAL) build_monomial(P);
 }
 
 // Runs `launch` between two recorded events when profiling is on.
@@ -636,6 +666,12 @@ hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, int ncb, c
 
 template <typename T, typename S>
 void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
+    if (P->d_lchans) {
+        timed(P, DSBT_STAGE_MOMENT, s, [&] {
+            hip_check(dsbt::launch_monomial(P->d_lchans, (int)P->h_lchans.size(), src, dst, inverse, ph, s), "monomial");
+        });
+        return;
+    }
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
             hip_check(launch_mf<T>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
@@ -749,6 +785,17 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
             return fail(DSBT_ERR_INVALID_ARG, "unknown mode");
         if (opts.plan_where != DSBT_PLAN_ON_DEVICE && opts.plan_where != DSBT_PLAN_ON_HOST)
             return fail(DSBT_ERR_INVALID_ARG, "unknown plan_where");
+        if (opts.algorithm != DSBT_ALG_TILED && opts.algorithm != DSBT_ALG_MONOMIAL)
+            return fail(DSBT_ERR_INVALID_ARG, "unknown algorithm");
+        if (opts.algorithm == DSBT_ALG_MONOMIAL) {
+            if (opts.precision != DSBT_C128 || opts.mode != DSBT_MODE_BATCHED)
+                return fail(DSBT_ERR_UNSUPPORTED, "the monomial variant needs DSBT_C128 and DSBT_MODE_BATCHED");
+            for (int c = 0; ch && c < nch; ++c) {
+                const int k = (ch[c].ell + 1) / 2;
+                if (k > 64 || (ch[c].ell > 1 && (ch[c].ell - 1) * std::log10((double)ch[c].N) > 300.0))
+                    return fail(DSBT_ERR_UNSUPPORTED, "monomial variant: N^(l-1) exceeds the FP64 range or l > 128");
+            }
+        }
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(DSBT_ERR_NO_DEVICE, "no HIP device");
         int dev = 0;
@@ -920,6 +967,11 @@ dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32
                 if (it.nch > 0) it.kphase = by_off[it.off[0]];
             if (d) hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::MItem) * v.size(), hipMemcpyHostToDevice), "items");
         };
+        if (p->d_lchans) {
+            for (auto& x : p->h_lchans) x.kphase = by_off[x.off];
+            hip_check(hipMemcpy(p->d_lchans, p->h_lchans.data(), sizeof(dsbt::LChan) * p->h_lchans.size(),
+                                hipMemcpyHostToDevice), "monomial channels");
+        }
         refresh(p->h_items_mf, p->d_items_mf);
         refresh(p->h_items_v1, p->d_items_v1);
         refresh(p->h_items1, p->d_items1);
@@ -1138,6 +1190,24 @@ dsbt_status dsbt_host_ftb_tables(int32_t N, int32_t ell, int32_t B, double* out,
         std::vector<double> blk;
         dsbt::build_ftb_blocks(ell, B, NT, blk, 0);
         std::memcpy(out, blk.data(), sizeof(double) * blk.size());
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_host_monomial_tables(int32_t N, int32_t ell, double* xi, double* alpha, double* comp,
+                                      int64_t* sizes) {
+    if (N < 2 || ell < 0 || ell > 2 * N - 2 || (ell + 1) / 2 > 64) return fail(DSBT_ERR_UNSUPPORTED, "bad N or l");
+    return guarded([&]() -> dsbt_status {
+        std::vector<double> x, a, c;
+        dsbt::monomial_tables(N, ell, x, a, c);
+        if (sizes) {
+            sizes[0] = (int64_t)x.size();
+            sizes[1] = (int64_t)a.size();
+            sizes[2] = (int64_t)c.size();
+        }
+        if (xi) std::copy(x.begin(), x.end(), xi);
+        if (alpha) std::copy(a.begin(), a.end(), alpha);
+        if (comp) std::copy(c.begin(), c.end(), comp);
         return DSBT_OK;
     });
 }
