@@ -217,6 +217,9 @@ def main():
                     help="only time the imaginary-time method: the hydrogen l > 0 states (dr = 0.05, "
                          "10 --steps steps per graph replay, then Gram-Schmidt) in c64 and c128, and the "
                          "energy and orthonormalisation calls on the 1024-channel TDSE batch")
+    ap.add_argument("--monomial-profile", action="store_true",
+                    help="only time the paper-literal monomial moment stage against the tiled one (complex128, "
+                         "N = 1024, l = 0..31 with all m) and report its error per l")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -251,6 +254,43 @@ def main():
             torch.cuda.synchronize()
             out[prec] = {"workload": w.name, "ms_per_step": e0.elapsed_time(e1) / args.steps, "steps": args.steps}
             del plan
+        print(json.dumps(out))
+        return
+
+    if args.monomial_profile:
+        def timed(fn, n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        N, rmax = 1024, 102.4
+        chs, off = [], 0
+        for ell in range(32):
+            for _ in range(2 * ell + 1):
+                chs.append((N, ell, rmax, off))
+                off += N
+        rng = np.random.default_rng(9)
+        psi = torch.from_numpy(rng.standard_normal(off) + 1j * rng.standard_normal(off)).cuda()
+        out = {"workload": f"N={N} rmax={rmax} l=0..31 all m ({len(chs)} channels), complex128"}
+        res = {}
+        for alg in ("tiled", "monomial"):
+            plan = Plan(chs, precision="c128", algorithm=alg)
+            b, x = plan.empty(), plan.empty()
+            timed(lambda: plan.forward(psi, b), max(args.warmup, 1))
+            out[alg] = {"ms_forward": timed(lambda: plan.forward(psi, b), args.steps),
+                        "ms_inverse": timed(lambda: plan.inverse(b, x), args.steps)}
+            res[alg] = b.clone()
+            del plan
+        err = {}
+        for c, (N_, ell, _, o) in enumerate(chs):
+            if ell in err:
+                continue
+            d = torch.linalg.vector_norm(res["monomial"][o:o + N] - res["tiled"][o:o + N])
+            err[ell] = float(d / torch.linalg.vector_norm(res["tiled"][o:o + N]))
+        out["monomial_error_vs_tiled"] = {str(k): v for k, v in sorted(err.items())}
         print(json.dumps(out))
         return
 
