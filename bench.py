@@ -30,7 +30,7 @@ PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP 
 # sources at the time of the measurement; after any change to them the figure
 # no longer applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h"],
-                  "sha256": "a53895c3604c631e3116378419a118af26c75eb91bee39df73830d2cb4f20a1f",
+                  "sha256": "30160e0fb1da4660c5ac3f5a0620c49b57ec24b39d7ebefef6cd8cfd2fc814c2",
                   "fetch_bytes": 143461592, "write_bytes": 67482528}
 
 

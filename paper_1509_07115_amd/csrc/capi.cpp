@@ -386,7 +386,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     struct Tab { const void* f; const void* i; const void* mf; const void* mi; int NB; };
     std::map<int, Tab> tabs;
     const bool fp32 = std::is_same<T, float>::value;
-    const bool c64x = P->precision == DSBT_C64_FP64;   // complex64 data, FP64 arithmetic
+    const bool fp64mf = P->precision == DSBT_C64_FP64 || P->precision == DSBT_C128;   // FP64 arithmetic
     // FP64 blocks generated on the device (default) or by host threads
     DeviceScratch scratch;
     if (P->opts.plan_where == DSBT_PLAN_ON_DEVICE) {
@@ -413,7 +413,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
             t.mf = upload_converted<float>(P, arr, s);
             dsbt::arrange_mfma_blocks(blk, B, k, dsbt::parity_p(ell), NT, t.NB, true, arr);
             t.mi = upload_converted<float>(P, arr, s);
-        } else if (c64x && B == 32 && R <= R16) {
+        } else if (fp64mf && B == 32 && R <= R16) {
             // FP64 tables in the same operand layout for the FP64 four-wave pipeline
             t.NB = 4;
             std::vector<double> arr;
@@ -655,12 +655,12 @@ void timed(dsbt_plan_s* P, int stage, hipStream_t s, F&& launch) {
 // Matrix-core moment stage: the four-wave pipeline when every item has B = 32,
 // else the row-block kernel (B = 64 items need 8 waves).  ncb: the largest
 // column-block count of the launched items.
-// T: arithmetic precision (FP64 only for complex64 data with FP64 arithmetic,
-// whose tables are all B = 32).
-template <typename T>
+// T: arithmetic precision, S: data scalar (T = double: FP64 arithmetic on
+// complex64 or complex128 data, whose matrix-core tables are all B = 32).
+template <typename T, typename S>
 hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, int ncb, const void* src, void* dst,
                      bool inverse, dsbt::PhaseArgs ph, hipStream_t s) {
-    if (P->mf_waves == 4) return dsbt::launch_mstage_chain<T>(items, n, ncb, src, dst, inverse, ph, s);
+    if (P->mf_waves == 4) return dsbt::launch_mstage_chain<T, S>(items, n, ncb, src, dst, inverse, ph, s);
     return dsbt::launch_mstage_mfma(items, n, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s);
 }
 
@@ -674,7 +674,7 @@ void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hi
     }
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(launch_mf<T>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T, S>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
@@ -688,7 +688,7 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
                         dsbt::PhaseArgs ph) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
         if (P->items1_mf[c])
-            hip_check(launch_mf<T>(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T, S>(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
         else
             hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
     });

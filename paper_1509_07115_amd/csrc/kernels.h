@@ -113,13 +113,15 @@ inline size_t mfma_lds_bytes_for(int NB, int NCB, int B) {
 }
 hipError_t set_lds_limits_mfma();
 // Moment stage for items with NB = 4 (B = 32, k <= 32) as a four-wave pipeline
-// per item (Q x, moment chain, two result row blocks); 256 threads.  Complex64
-// data; T = float (FP32 tables and arithmetic) or double (FP64 tables and
-// arithmetic, items of one column block).  An item has NCB = 1 or 2 blocks of
+// per item (Q x, moment chain, two result row blocks); 256 threads.  T = float
+// (FP32 tables and arithmetic, complex64 data) or double (FP64 tables and
+// arithmetic, items of one column block, complex64 or complex128 data).  An item has NCB = 1 or 2 blocks of
 // 8 channels (off[]: slots past nch repeat a real channel); ncb is the largest
 // NCB of the launched items and sizes the LDS.  Runs in place.  Phases
 // (ph.use, complex of T per slot) are supported on the forward direction only.
-template <typename T>
+// D: data scalar in memory, float (complex64) or, with T = double, double
+// (complex128).
+template <typename T, typename D>
 hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s);
 template <typename T>

@@ -1,8 +1,9 @@
 // Moment stage for tiles of B = 32 on the CDNA4 matrix cores, as a pipeline
 // of four waves per item: 8 NCB complex channels with the same l and N, in
 // NCB = 1 or 2 blocks of 16 matrix columns.  Every table operand a lane loads
-// feeds NCB matrix instructions.  Data in memory are complex64; the arithmetic
-// type T is float (FP32 tables) or double (FP64 tables, NCB = 1).
+// feeds NCB matrix instructions.  The arithmetic type T is float (FP32 tables)
+// or double (FP64 tables, NCB = 1); data in memory are complex64, or
+// complex128 with FP64 arithmetic (D, the data scalar).
 //
 // Per tile J the tiled moment form (Sec. 2.4-2.5) maps [x_J; mu_J] to
 // [o_J; mu_J+1] with the zero-padded 64 x 64 block A' (M_J forward, M_J^T
@@ -50,9 +51,21 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 // 16-byte global access of two complex64 values, which are 8-byte aligned
 typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
 
+// Data in memory: four scalars (two consecutive complex slots of a channel) per
+// lane access, 8-byte aligned for complex64, 16-byte aligned for complex128.
+template <typename D>
+struct Data;
+template <>
+struct Data<float> {
+    typedef float v4 __attribute__((ext_vector_type(4), aligned(8)));
+};
+template <>
+struct Data<double> {
+    typedef double v4 __attribute__((ext_vector_type(4), aligned(16)));
+};
+
 // Arithmetic precision of the pipeline: float (complex64 plans) or double
-// (complex64 data with FP64 arithmetic and tables).  Data in memory are
-// complex64 either way.
+// (FP64 arithmetic and tables, complex64 or complex128 data).
 template <typename T>
 struct Arith;
 template <>
@@ -124,8 +137,9 @@ __device__ __forceinline__ void result_to_operand(Arith<double>::v4 m, double* o
     for (int j = 0; j < 4; ++j) out[j] = m[j];
 }
 
-template <typename T, bool INV, bool KPH, int KB, bool TAIL, int NCB>
+template <typename T, typename D, bool INV, bool KPH, int KB, bool TAIL, int NCB>
 struct Pipe {
+    using DV4 = typename Data<D>::v4;
     using V4 = typename Arith<T>::v4;
     using V2 = typename Arith<T>::v2;
     // chunk kc = A' columns 4 kc .. 4 kc + 3 (0..7 tile data, 8.. moments)
@@ -140,8 +154,8 @@ struct Pipe {
     static constexpr int YWAVE = NCB * 16 * kYCol;          // result staging per result wave
     static constexpr int LPC = 8 / NCB, FPL = 8 * NCB;      // pre-wave loads: lanes per channel, floats per lane
 
-    const float DSBT_GLOBAL* src;
-    float DSBT_GLOBAL* dst;
+    const D DSBT_GLOBAL* src;
+    D DSBT_GLOBAL* dst;
     const T DSBT_GLOBAL* tab;
     const V2 DSBT_GLOBAL* kphase;   // complex of the arithmetic precision
     T* xring;
@@ -149,18 +163,18 @@ struct Pipe {
     T* mring;
     T* yring;
     int NT, k, p, lane, q, col, nact;
-    int64_t e0[NCB];   // float index of (channel 8 cb + col/2, slot 0, re/im col%2)
+    int64_t e0[NCB];   // scalar index of (channel 8 cb + col/2, slot 0, re/im col%2)
     // natural layout: the pre wave's lane l loads channel l/LPC, FPL floats
     // from slot 4 (l%LPC) NCB of a tile; a result wave's lane l stores slots
     // 2 (l%8), 2 (l%8) + 1 of channel 8 cb + l/8 in a 16-row block
-    int64_t gpre;      // float index of the pre wave's first float in tile 0
-    int64_t g0[NCB];   // float index of (channel 8 cb + l/8, slot 0)
+    int64_t gpre;      // scalar index of the pre wave's first scalar in tile 0
+    int64_t g0[NCB];   // scalar index of (channel 8 cb + l/8, slot 0)
     int xnat;          // offset of the pre wave's loaded values in a data slot
     int xop[NCB];      // offset of operand (slot l/16, column l%16 of block cb) in a data slot
     bool conj;
 
-    __device__ Pipe(const MItem& it, const float2* s_, float2* d_, const PhaseArgs& ph, T* lds)
-        : src(as_global(reinterpret_cast<const float*>(s_))), dst(as_global_rw(reinterpret_cast<float*>(d_))) {
+    __device__ Pipe(const MItem& it, const void* s_, void* d_, const PhaseArgs& ph, T* lds)
+        : src(as_global(static_cast<const D*>(s_))), dst(as_global_rw(static_cast<D*>(d_))) {
         NT = it.NT;
         k = it.k;
         p = it.p;
@@ -230,7 +244,7 @@ struct Pipe {
     // read-out of tile t - 1 (in the same phase) while tile t's instructions run.
     struct Pre {
         V4 a[kSets][2 * KB];                // tables, tile t in set t % kSets
-        f4 x[kSets][2 * NCB];               // natural-layout data (complex64), tile t in set t % kSets
+        DV4 x[kSets][2 * NCB];              // natural-layout data, tile t in set t % kSets
         T xv[2][NCB * 8];                   // operand layout of tile t in xv[t % 2]
         V4 c0[kPhase][KB][NCB], c1[kPhase][KB][NCB];   // accumulators per step of a phase
     };
@@ -242,7 +256,7 @@ struct Pipe {
     }
     template <int S>
     __device__ void pre_load_dat(Pre& r, int t) const {
-        const f4u DSBT_GLOBAL* g = reinterpret_cast<const f4u DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)tile(t));
+        const DV4 DSBT_GLOBAL* g = reinterpret_cast<const DV4 DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)tile(t));
 #pragma unroll
         for (int i = 0; i < 2 * NCB; ++i) r.x[S][i] = g[i];
     }
@@ -450,7 +464,7 @@ struct Pipe {
                 const int row = 4 * j + q;
                 T x = sgn * bm[4 * KB * cb + j];
                 if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
-                if (row < k) dst[e0[cb] + 2 * row] = (float)x;
+                if (row < k) dst[e0[cb] + 2 * row] = (D)x;
             }
     }
 
@@ -506,8 +520,8 @@ struct Pipe {
                 v = V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
             }
             // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
-            *reinterpret_cast<f4u DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) =
-                __builtin_convertvector(v, f4u);
+            *reinterpret_cast<DV4 DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) =
+                __builtin_convertvector(v, DV4);
         }
     }
     template <int RB, int S, bool FIRST>
@@ -607,20 +621,20 @@ struct Pipe {
     }
 };
 
-template <typename T, bool INV, bool KPH, int NCB>
-__device__ void run_item(const MItem& it, const float2* src, float2* dst, const PhaseArgs& ph, T* lds) {
+template <typename T, typename D, bool INV, bool KPH, int NCB>
+__device__ void run_item(const MItem& it, const void* src, void* dst, const PhaseArgs& ph, T* lds) {
     const bool tail = it.NT % kSets != 0;
     if (it.k > 16) {
-        if (tail) Pipe<T, INV, KPH, 2, true, NCB>(it, src, dst, ph, lds).run();
-        else Pipe<T, INV, KPH, 2, false, NCB>(it, src, dst, ph, lds).run();
+        if (tail) Pipe<T, D, INV, KPH, 2, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<T, D, INV, KPH, 2, false, NCB>(it, src, dst, ph, lds).run();
     } else {
-        if (tail) Pipe<T, INV, KPH, 1, true, NCB>(it, src, dst, ph, lds).run();
-        else Pipe<T, INV, KPH, 1, false, NCB>(it, src, dst, ph, lds).run();
+        if (tail) Pipe<T, D, INV, KPH, 1, true, NCB>(it, src, dst, ph, lds).run();
+        else Pipe<T, D, INV, KPH, 1, false, NCB>(it, src, dst, ph, lds).run();
     }
 }
 
-template <typename T, bool INV, bool KPH>
-__global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const float2* src, float2* dst,
+template <typename T, typename D, bool INV, bool KPH>
+__global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const void* src, void* dst,
                                                     PhaseArgs ph) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
@@ -628,11 +642,11 @@ __global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ it
     if (it.nch == 0) return;   // idle slot of the per-XCD schedule
     if constexpr (sizeof(T) == sizeof(float)) {
         if (it.NCB == 2) {
-            run_item<T, INV, KPH, 2>(it, src, dst, ph, lds);
+            run_item<T, D, INV, KPH, 2>(it, src, dst, ph, lds);
             return;
         }
     }
-    run_item<T, INV, KPH, 1>(it, src, dst, ph, lds);   // FP64 items have one column block
+    run_item<T, D, INV, KPH, 1>(it, src, dst, ph, lds);   // FP64 items have one column block
 }
 
 }  // namespace
@@ -649,27 +663,31 @@ hipError_t set_lds_limits_chain() {
     auto set = [&](const void* f) {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     };
-    set((const void*)mstage_chain<T, true, false>);
-    set((const void*)mstage_chain<T, false, true>);
-    set((const void*)mstage_chain<T, false, false>);
+    set((const void*)mstage_chain<T, float, true, false>);
+    set((const void*)mstage_chain<T, float, false, true>);
+    set((const void*)mstage_chain<T, float, false, false>);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        set((const void*)mstage_chain<T, double, true, false>);
+        set((const void*)mstage_chain<T, double, false, true>);
+        set((const void*)mstage_chain<T, double, false, false>);
+    }
     return e;
 }
 
-template <typename T>
+template <typename T, typename D>
 hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (inverse && ph.use) return hipErrorInvalidValue;   // phases are applied on the forward output only
     if (sizeof(T) != sizeof(float) && ncb != 1) return hipErrorInvalidValue;
-    const float2* a = (const float2*)src;
-    float2* b = (float2*)dst;
+    if (sizeof(D) > sizeof(T)) return hipErrorInvalidValue;
     const size_t lds = chain_lds_bytes<T>(ncb);
     if (inverse)
-        hipLaunchKernelGGL((mstage_chain<T, true, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, D, true, false>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
     else if (ph.use)
-        hipLaunchKernelGGL((mstage_chain<T, false, true>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, D, false, true>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
     else
-        hipLaunchKernelGGL((mstage_chain<T, false, false>), dim3(nitems), dim3(256), lds, s, d_items, a, b, ph);
+        hipLaunchKernelGGL((mstage_chain<T, D, false, false>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
     return hipGetLastError();
 }
 
@@ -677,8 +695,11 @@ template size_t chain_lds_bytes<float>(int);
 template size_t chain_lds_bytes<double>(int);
 template hipError_t set_lds_limits_chain<float>();
 template hipError_t set_lds_limits_chain<double>();
-template hipError_t launch_mstage_chain<float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs, hipStream_t);
-template hipError_t launch_mstage_chain<double>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
-                                                hipStream_t);
+template hipError_t launch_mstage_chain<float, float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                      hipStream_t);
+template hipError_t launch_mstage_chain<double, float>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                       hipStream_t);
+template hipError_t launch_mstage_chain<double, double>(const MItem*, int, int, const void*, void*, bool, PhaseArgs,
+                                                        hipStream_t);
 
 }  // namespace dsbt
