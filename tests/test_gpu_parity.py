@@ -87,7 +87,8 @@ SMALL_CASES = [
 
 
 @pytest.mark.parametrize("N,ells", SMALL_CASES)
-@pytest.mark.parametrize("mode,precision", [("batched", "c64"), ("plain", "c64"), ("batched", "c64x")])
+@pytest.mark.parametrize("mode,precision", [("batched", "c64"), ("plain", "c64"), ("batched", "c64x"),
+                                            ("batched", "c128"), ("plain", "c128")])
 def test_c64_parity_small(N, ells, mode, precision):
     rng = np.random.default_rng(N)
     chans, parts, off = [], [], 0
@@ -99,8 +100,9 @@ def test_c64_parity_small(N, ells, mode, precision):
             off += N
     x = np.concatenate(parts)
     plan = Plan(chans, mode=mode, precision=precision)
-    # c64x rounds only the stored input and output to FP32: two roundings
-    tol = 2e-6 if precision == "c64" else 2.5e-7
+    # c64x rounds only the stored input and output to FP32: two roundings;
+    # c128 is FP64 throughout (four-wave pipeline for l <= 63, generic kernel above)
+    tol = {"c64": 2e-6, "c64x": 2.5e-7, "c128": 1e-12}[precision]
     b = run(plan, x)
     ref = oracle_apply(chans, x)
     assert per_channel_rel(b, ref, chans).max() < tol
