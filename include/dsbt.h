@@ -216,6 +216,22 @@ dsbt_status dsbt_energy(dsbt_plan p, const void* psi, void* work, double* out, v
  * calls only enqueue one launch on `stream`. */
 dsbt_status dsbt_orthonormalize(dsbt_plan p, void* psi, const int32_t* sets, int32_t nsets, void* stream);
 
+/* Autotuner: picks the moment tile B and the channels per moment work item for
+ * a channel set by measurement.  Candidates: tile 0 (the plan's own choice
+ * per l), 32 and 64, crossed with chans_per_block 0 (the plan's own choice),
+ * 8 and 4; candidates the channels do not admit are skipped.  Each is built
+ * as a plan from *base (NULL = defaults) and timed with HIP events over nrep
+ * forward + inverse pairs (after one untimed pair) on device scratch buffers
+ * that the call allocates and frees.  *best receives *base with the fastest
+ * tile and chans_per_block; ms (may be NULL) the time of one pair in ms.
+ * cache_path (may be NULL): a JSON-lines file; a line whose key matches this
+ * device architecture, precision, mode, algorithm and (N, l, rmax) multiset is
+ * returned without timing, and a new result is appended.  Synchronises
+ * `stream`.  DSBT_ERR_UNSUPPORTED if no candidate is admitted (the message
+ * is the last candidate's), DSBT_ERR_NO_DEVICE without a device. */
+dsbt_status dsbt_autotune(const dsbt_channel* ch, int32_t nch, const dsbt_plan_opts* base, int32_t nrep,
+                          const char* cache_path, dsbt_plan_opts* best, double* ms, void* stream);
+
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is
  * bracketed by HIP events recorded on the launch stream.  enable == 1 clears

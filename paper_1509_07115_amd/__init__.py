@@ -79,6 +79,28 @@ class Plan:
         return o
 
     @classmethod
+    def autotuned(cls, channels: Sequence, nrep: int = 10, cache: Optional[str] = None, stream=None, **kw) -> "Plan":
+        """A plan with the tile and channels per work item chosen by measurement (``dsbt_autotune``);
+        ``cache``: JSON-lines file of earlier results.  The choice is in ``plan.tuning``."""
+        lib = _lib.load()
+        chans = [tuple(c) for c in channels]
+        arr = (_lib.Channel * len(chans))()
+        for i, (N, ell, rmax, off) in enumerate(chans):
+            arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
+        opts = cls._opts(kw.get("precision", "c64"), kw.get("mode", "batched"), 0, 0, kw.get("sign", True),
+                         kw.get("plan_where", "device"), kw.get("kinetic", "plain"), kw.get("algorithm", "tiled"))
+        best = _lib.PlanOpts()
+        ms = ctypes.c_double()
+        _lib.check(lib.dsbt_autotune(arr, len(chans), ctypes.byref(opts), int(nrep),
+                                     cache.encode() if cache else None, ctypes.byref(best), ctypes.byref(ms),
+                                     _stream_handle(stream)), "dsbt_autotune")
+        kw = dict(kw)
+        kw["tile"], kw["chans_per_block"] = best.tile, best.chans_per_block
+        plan = cls(chans, stream=stream, **kw)
+        plan.tuning = {"tile": best.tile, "chans_per_block": best.chans_per_block, "ms_per_fwd_inv": ms.value}
+        return plan
+
+    @classmethod
     def uniform(cls, N: int, rmax: float, ells: Iterable[int], all_m: bool = False, **kw) -> "Plan":
         ells = [int(e) for e in ells]
         ch, off = [], 0

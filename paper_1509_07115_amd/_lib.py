@@ -28,7 +28,7 @@ EXPORTED = [
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_set_potential_ex",
     "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
     "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
-    "dsbt_kinetic_momenta",
+    "dsbt_kinetic_momenta", "dsbt_autotune",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -87,6 +87,8 @@ def load() -> ctypes.CDLL:
                                             ctypes.POINTER(i64)]),
         "dsbt_device_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64), P]),
         "dsbt_kinetic_momenta": (i32, [i32, i32, dbl, i32, ctypes.POINTER(dbl)]),
+        "dsbt_autotune": (i32, [ctypes.POINTER(Channel), i32, ctypes.POINTER(PlanOpts), i32, ctypes.c_char_p,
+                                ctypes.POINTER(PlanOpts), ctypes.POINTER(dbl), P]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),
     }

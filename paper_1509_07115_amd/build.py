@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsbt.so")
 SOURCES = ["kernels.hip", "fstage.hip", "mstage_mfma.hip", "mstage_chain.hip", "plan_device.hip", "state.hip",
-           "monomial.hip", "capi.cpp", "plan_host.cpp", "monomial_host.cpp"]
+           "monomial.hip", "capi.cpp", "autotune.cpp", "plan_host.cpp", "monomial_host.cpp"]
 ARCH = os.environ.get("DSBT_OFFLOAD_ARCH", "gfx950")
 
 
@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> str:
         objs = []
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            lang = ["-x", "hip"] if src.endswith((".hip", "capi.cpp")) else []
+            lang = ["-x", "hip"] if src.endswith((".hip", "capi.cpp", "autotune.cpp")) else []
             cmd = [cc, *flags, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)

@@ -40,6 +40,7 @@ def test_status_strings_and_host_errors(built_lib):
     assert lib.dsbt_plan_create(None, None, 0, None, None) == -1
     assert lib.dsbt_plan_create(ctypes.byref(h), None, 0, None, None) in (-1, -7)
     assert lib.dsbt_forward(None, None, None, None) == -1
+    assert lib.dsbt_autotune(None, 0, None, 1, None, None, None, None) == -1
 
 
 def tiled_forward(blocks, f, ell):
