@@ -220,6 +220,9 @@ def main():
     ap.add_argument("--monomial-profile", action="store_true",
                     help="only time the paper-literal monomial moment stage against the tiled one (complex128, "
                          "N = 1024, l = 0..31 with all m) and report its error per l")
+    ap.add_argument("--autotune-profile", action="store_true",
+                    help="only run the autotuner on the batched all-m and the uneven workloads and compare the "
+                         "tuned plan with the default one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -254,6 +257,33 @@ def main():
             torch.cuda.synchronize()
             out[prec] = {"workload": w.name, "ms_per_step": e0.elapsed_time(e1) / args.steps, "steps": args.steps}
             del plan
+        print(json.dumps(out))
+        return
+
+    if args.autotune_profile:
+        def timed(fn, n):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        out = {}
+        for w in (workloads.batched_all_m(), workloads.uneven()):
+            t0 = time.time()
+            tuned = Plan.autotuned(w.channels, nrep=max(args.steps, 1))
+            t_tune = time.time() - t0
+            default = Plan(w.channels)
+            x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+            b = torch.empty_like(x)
+            res = {"tuning": tuned.tuning, "tune_seconds": t_tune}
+            for name, p in (("default", default), ("tuned", tuned)):
+                res[f"ms_fwd_inv_{name}"] = timed(lambda: (p.forward(x, b), p.inverse(b, x)), max(args.steps, 1))
+            out[w.name] = res
+            del tuned, default
         print(json.dumps(out))
         return
 

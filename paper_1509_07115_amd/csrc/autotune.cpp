@@ -5,8 +5,9 @@
 // 8, 4).  Each candidate is a full plan; those the channel set does not admit
 // (a tile below ceil((l+1)/2) or above N) are skipped.  A candidate is timed
 // with HIP events over `nrep` forward + inverse pairs on device scratch
-// buffers, after one untimed pair.  The transforms have no data-dependent
-// control flow, so zero-filled buffers time like real data.
+// buffers, after one untimed pair.  The buffers hold hashed pseudo-random
+// values in [-1, 1): the transforms have no data-dependent control flow, but
+// constant data draws less power and can run at higher clocks than real data.
 //
 // Results are cached as JSON lines, one object per tuned channel set:
 //   {"key": "<16 hex>", "tile": B, "chans_per_block": C, "ms": t}
@@ -26,6 +27,18 @@
 #include "../../include/dsbt.h"
 
 namespace {
+
+// x[i] = a value in [-1, 1) hashed from i (one 32-bit mix per scalar)
+template <typename S>
+__global__ void fill_hashed(S* x, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    x[i] = (S)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+}
 
 uint64_t fnv1a(const std::string& s) {
     uint64_t h = 1469598103934665603ull;
@@ -117,8 +130,13 @@ extern "C" dsbt_status dsbt_autotune(const dsbt_channel* ch, int32_t nch, const 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     dsbt_status result = DSBT_ERR_UNSUPPORTED;
     double best_ms = 0;
-    if (hipMemsetAsync(x, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess) {
+    const size_t nscal = (size_t)elems * 2;
+    const unsigned grid = (unsigned)((nscal + 255) / 256);
+    if (o.precision == DSBT_C128)
+        hipLaunchKernelGGL(fill_hashed<double>, dim3(grid), dim3(256), 0, s, (double*)x, nscal);
+    else
+        hipLaunchKernelGGL(fill_hashed<float>, dim3(grid), dim3(256), 0, s, (float*)x, nscal);
+    if (hipGetLastError() != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         result = DSBT_ERR_HIP;
     } else {
         for (int t : {0, 32, 64}) {
