@@ -12,5 +12,6 @@ exact    exact-rational (``fractions``) DLOP / DDLOP / T for tiny grids (Sec. 2.
 tdse     dense split-operator step, propagation and adjoint gradient (Sec. 4.1)
 sbf      spherical-Bessel references: closed forms, quadrature, corrected momenta (Sec. 3)
 monomial the paper's own monomial-moment fast multiplication (Sec. 2.6), FP64, for its error envelope
+angular  the angular transform Y = P Phi of the DSBT-DVR solver (Sec. 4.1)
 """
-from . import dsbt, exact, tdse, sbf, monomial  # noqa: F401
+from . import dsbt, exact, tdse, sbf, monomial, angular  # noqa: F401
