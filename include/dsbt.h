@@ -232,6 +232,38 @@ dsbt_status dsbt_orthonormalize(dsbt_plan p, void* psi, const int32_t* sets, int
 dsbt_status dsbt_autotune(const dsbt_channel* ch, int32_t nch, const dsbt_plan_opts* base, int32_t nrep,
                           const char* cache_path, dsbt_plan_opts* best, double* ms, void* stream);
 
+/* Angular transform Y = P Phi of the DSBT-DVR solver (Sec. 4.1), applied at
+ * every radial point: grid values on N_theta Gauss-Legendre nodes eta_j
+ * (ascending) and N_phi = 2M + 1 azimuths phi_k = 2 pi k / N_phi, carrying the
+ * weights sqrt(w_j dphi), map to coefficients of the spherical harmonics
+ * (l, m), m = -M..M, l = |m| .. |m| + N_theta - 1.  Phi is the unitary DFT
+ * exp(-i m phi_k) / sqrt(N_phi) (the projection onto Y_lm); P, per m, holds
+ * the associated Legendre functions Pbar_l^m(eta_j) sqrt(w_j) (unit norm on
+ * [-1, 1], Condon-Shortley phase) orthonormalised on the quadrature in l order,
+ * so Y is unitary.  Layouts (complex, interleaved, radius fastest):
+ *   grid  psi[j][k][i]   (j < N_theta, k < N_phi, i < Nr)
+ *   coef  c[q][t][i]     (m = q - M, l = |m| + t): channel q N_theta + t of a
+ *                        DSBT plan with N = Nr, that l and offset (q N_theta + t) Nr.
+ * 1 <= N_theta <= 64, N_phi odd in [1, 17] (else DSBT_ERR_UNSUPPORTED): for
+ * |m| > 8 the orthonormalisation on the quadrature is too ill-conditioned in
+ * FP64 to fix the blocks to FP32 accuracy (two FP64 constructions differ by
+ * 7e-6 at N_theta = 16, |m| = 15). */
+typedef struct dsbt_sht_s* dsbt_sht;   /* opaque; owns its tables and an Nr N_theta N_phi workspace */
+
+/* Host: nodes eta[N_theta], weights w[N_theta], azimuths phi[N_phi] (any may be NULL). */
+dsbt_status dsbt_sht_grid(int32_t n_theta, int32_t n_phi, double* eta, double* w, double* phi);
+/* Host FP64 P blocks for testing, P[(q N_theta + t) N_theta + j]. */
+dsbt_status dsbt_sht_host_tables(int32_t n_theta, int32_t n_phi, double* P);
+/* precision: DSBT_C64 (complex64 data, FP32 tables and arithmetic) or
+ * DSBT_C128 (complex128, FP64).  Allocates its tables and workspace. */
+dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t n_phi, int32_t precision);
+dsbt_status dsbt_sht_destroy(dsbt_sht s);
+/* coef = Y grid and grid = Y^H coef on device buffers of Nr N_theta N_phi
+ * complex values; enqueued on `stream` (two launches through the workspace,
+ * so calls on one transform must not overlap); grid and coef may alias. */
+dsbt_status dsbt_sht_forward(dsbt_sht s, const void* grid, void* coef, void* stream);
+dsbt_status dsbt_sht_inverse(dsbt_sht s, const void* coef, void* grid, void* stream);
+
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is
  * bracketed by HIP events recorded on the launch stream.  enable == 1 clears

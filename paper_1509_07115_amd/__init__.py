@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _lib
 
-__all__ = ["Plan", "DsbtError", "exported_symbols"]
+__all__ = ["Plan", "AngularTransform", "DsbtError", "exported_symbols"]
 
 DsbtError = _lib.DsbtError
 
@@ -248,6 +248,92 @@ def host_ftb_tables(N: int, ell: int, B: int) -> np.ndarray:
     k = (ell + 1) // 2
     R = B + k
     return out.reshape(N // B, R, R)
+
+
+class AngularTransform:
+    """The angular transform Y = P Phi of Sec. 4.1 at every radial point (``dsbt_sht_*``).
+
+    grid  [j][k][i]: Gauss-Legendre node eta_j (ascending), azimuth phi_k, radial point i;
+    coef  [q][t][i]: m = q - M, l = |m| + t (N_phi = 2M + 1), i.e. channel q*N_theta + t of a
+    DSBT plan built from ``channels(rmax)``.
+    """
+
+    def __init__(self, Nr: int, n_theta: int, n_phi: int, precision: str = "c64"):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        self.Nr, self.n_theta, self.n_phi, self.precision = int(Nr), int(n_theta), int(n_phi), precision
+        prec = {"c64": _lib.DSBT_C64, "c128": _lib.DSBT_C128}[precision]
+        _lib.check(self._lib.dsbt_sht_create(ctypes.byref(self._h), self.Nr, self.n_theta, self.n_phi, prec),
+                   "dsbt_sht_create")
+
+    @property
+    def size(self) -> int:
+        return self.Nr * self.n_theta * self.n_phi
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.precision == "c128" else torch.complex64
+
+    def lm(self):
+        """[(l, m)] per coefficient channel, in channel order."""
+        M = (self.n_phi - 1) // 2
+        return [(abs(q - M) + t, q - M) for q in range(self.n_phi) for t in range(self.n_theta)]
+
+    def channels(self, rmax: float):
+        """DSBT channels (Nr, l, rmax, offset) of the coefficient layout."""
+        return [(self.Nr, l, float(rmax), c * self.Nr) for c, (l, _) in enumerate(self.lm())]
+
+    def _buf(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.dtype:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor of {self.dtype}")
+        if not t.is_contiguous() or t.numel() < self.size:
+            raise ValueError(f"{name} must be contiguous with at least {self.size} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def forward(self, grid, out=None, stream=None):
+        import torch
+        out = torch.empty(self.size, dtype=self.dtype, device="cuda") if out is None else out
+        _lib.check(self._lib.dsbt_sht_forward(self._h, self._buf(grid, "grid"), self._buf(out, "out"),
+                                              _stream_handle(stream)), "dsbt_sht_forward")
+        return out
+
+    def inverse(self, coef, out=None, stream=None):
+        import torch
+        out = torch.empty(self.size, dtype=self.dtype, device="cuda") if out is None else out
+        _lib.check(self._lib.dsbt_sht_inverse(self._h, self._buf(coef, "coef"), self._buf(out, "out"),
+                                              _stream_handle(stream)), "dsbt_sht_inverse")
+        return out
+
+    def close(self):
+        if self._h:
+            self._lib.dsbt_sht_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sht_grid(n_theta: int, n_phi: int):
+    """(eta, w, phi) of the angular grid (``dsbt_sht_grid``)."""
+    lib = _lib.load()
+    eta, w, phi = np.zeros(n_theta), np.zeros(n_theta), np.zeros(n_phi)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _lib.check(lib.dsbt_sht_grid(n_theta, n_phi, dp(eta), dp(w), dp(phi)), "dsbt_sht_grid")
+    return eta, w, phi
+
+
+def sht_host_tables(n_theta: int, n_phi: int) -> np.ndarray:
+    """P[q, t, j] of the angular transform (``dsbt_sht_host_tables``)."""
+    lib = _lib.load()
+    out = np.zeros((n_phi, n_theta, n_theta))
+    _lib.check(lib.dsbt_sht_host_tables(n_theta, n_phi, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "dsbt_sht_host_tables")
+    return out
 
 
 def host_monomial_tables(N: int, ell: int):

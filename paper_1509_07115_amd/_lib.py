@@ -28,7 +28,8 @@ EXPORTED = [
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_set_potential_ex",
     "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
     "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
-    "dsbt_kinetic_momenta", "dsbt_autotune",
+    "dsbt_kinetic_momenta", "dsbt_autotune", "dsbt_sht_grid", "dsbt_sht_host_tables", "dsbt_sht_create",
+    "dsbt_sht_destroy", "dsbt_sht_forward", "dsbt_sht_inverse",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -89,6 +90,12 @@ def load() -> ctypes.CDLL:
         "dsbt_kinetic_momenta": (i32, [i32, i32, dbl, i32, ctypes.POINTER(dbl)]),
         "dsbt_autotune": (i32, [ctypes.POINTER(Channel), i32, ctypes.POINTER(PlanOpts), i32, ctypes.c_char_p,
                                 ctypes.POINTER(PlanOpts), ctypes.POINTER(dbl), P]),
+        "dsbt_sht_grid": (i32, [i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+        "dsbt_sht_host_tables": (i32, [i32, i32, ctypes.POINTER(dbl)]),
+        "dsbt_sht_create": (i32, [ctypes.POINTER(P), i32, i32, i32, i32]),
+        "dsbt_sht_destroy": (i32, [P]),
+        "dsbt_sht_forward": (i32, [P, P, P, P]),
+        "dsbt_sht_inverse": (i32, [P, P, P, P]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),
     }

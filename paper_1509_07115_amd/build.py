@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsbt.so")
 SOURCES = ["kernels.hip", "fstage.hip", "mstage_mfma.hip", "mstage_chain.hip", "plan_device.hip", "state.hip",
-           "monomial.hip", "capi.cpp", "autotune.cpp", "plan_host.cpp", "monomial_host.cpp"]
+           "monomial.hip", "angular.hip", "capi.cpp", "autotune.cpp", "angular_capi.cpp", "plan_host.cpp",
+           "monomial_host.cpp", "angular_host.cpp"]
 ARCH = os.environ.get("DSBT_OFFLOAD_ARCH", "gfx950")
 
 

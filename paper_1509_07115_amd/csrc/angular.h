@@ -1,0 +1,37 @@
+// Angular transform Y = P Phi of the DSBT-DVR solver (Sec. 4.1), internal header.
+//
+// Grid values psi[j][k][i] on Gauss-Legendre nodes eta_j (ascending), azimuths
+// phi_k = 2 pi k / N_phi and radial points i (fastest) map to coefficients
+// c[q][t][i] of the spherical harmonics (l, m), m = q - M (N_phi = 2M + 1),
+// l = |m| + t.  Forward: a[j][q][i] = sum_k Phi[q][k] psi[j][k][i], then
+// c[q][t][i] = sum_j P[q][t][j] a[j][q][i]; inverse: the conjugate transpose.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/dsbt.h"
+
+namespace dsbt {
+
+constexpr int kShtMaxQ = 64;   // largest N_theta and N_phi of the axis kernel
+constexpr int kShtMaxPhi = 17; // largest N_phi accepted (|m| <= 8)
+
+// Records msg as the thread's last error (dsbt_last_error) and returns s.
+dsbt_status set_error(dsbt_status s, const char* msg);
+
+// FP64 host tables: Gauss-Legendre nodes (ascending) and weights, and
+// P[q][t][j] = Pbar_{|m|+t}^m(eta_j) sqrt(w_j) orthonormalised in t (modified
+// Gram-Schmidt over t in FP64), Pbar normalised to unit L2 norm on [-1, 1]
+// with the Condon-Shortley phase.
+void gauss_legendre(int n, std::vector<double>& eta, std::vector<double>& w);
+void sht_p_tables(int n_theta, int n_phi, std::vector<double>& P);
+
+// dst[o*dout + q'*dq + i] = sum_q A_o(q', q) src[o*so + q*sq + i] for o < nouter,
+// q, q' < Q, i < Nr; A_o(q', q) = mat[o*mso + (tr ? q*Q + q' : q'*Q + q)], conjugated
+// with cj.  S: float or double; CA: complex (interleaved) or real matrix.
+template <typename S, bool CA>
+hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,
+                             void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);
+
+}  // namespace dsbt

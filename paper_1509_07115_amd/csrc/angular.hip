@@ -1,0 +1,85 @@
+// Axis contraction of the angular transform (Sec. 4.1): one small dense matrix
+// (the azimuthal DFT, or the per-m associated Legendre block) applied along one
+// grid axis for every radial point.  A workgroup takes one outer index and 64
+// consecutive radial points: their Q input vectors are staged in LDS with
+// coalesced loads (radius is the fastest axis of both layouts), and each of the
+// four waves accumulates every fourth output row for its 64 points; the matrix
+// element of a row is wave-uniform.
+#include "angular.h"
+
+namespace dsbt {
+
+namespace {
+
+template <typename S> struct Cx;
+template <> struct Cx<float> { typedef float2 t; };
+template <> struct Cx<double> { typedef double2 t; };
+
+constexpr int kRows = kShtMaxQ / 4;   // output rows per thread
+
+template <typename S, bool CA>
+__global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int64_t mso, int tr, int cj,
+                                                  const typename Cx<S>::t* __restrict__ src, int64_t so, int64_t sq,
+                                                  typename Cx<S>::t* __restrict__ dst, int64_t dout, int64_t dq,
+                                                  int Q, int Nr) {
+    using V = typename Cx<S>::t;
+    __shared__ V X[kShtMaxQ][64];
+    const int o = blockIdx.y;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = threadIdx.x >> 6;
+    const bool live = i < Nr;
+    for (int q = r; q < Q; q += 4) X[q][threadIdx.x & 63] = live ? src[o * so + q * sq + i] : V{0, 0};
+    __syncthreads();
+    const S* A = mat + o * mso;
+    V acc[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) acc[u] = V{0, 0};
+    for (int q = 0; q < Q; ++q) {
+        const V x = X[q][threadIdx.x & 63];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+            const int qo = r + 4 * u;
+            if (qo < Q) {
+                const int64_t e = tr ? (int64_t)q * Q + qo : (int64_t)qo * Q + q;
+                if constexpr (CA) {
+                    const S ar = A[2 * e], ai = cj ? -A[2 * e + 1] : A[2 * e + 1];
+                    acc[u].x += ar * x.x - ai * x.y;
+                    acc[u].y += ar * x.y + ai * x.x;
+                } else {
+                    const S a = A[e];
+                    acc[u].x += a * x.x;
+                    acc[u].y += a * x.y;
+                }
+            }
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+        const int qo = r + 4 * u;
+        if (qo < Q) dst[o * dout + qo * dq + i] = acc[u];
+    }
+}
+
+}  // namespace
+
+template <typename S, bool CA>
+hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,
+                             void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
+    using V = typename Cx<S>::t;
+    if (Q < 1 || Q > kShtMaxQ || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((axis_apply<S, CA>), dim3((Nr + 63) / 64, nouter), dim3(256), 0, s, mat, mso, tr ? 1 : 0,
+                       cj ? 1 : 0, (const V*)src, so, sq, (V*)dst, dout, dq, Q, Nr);
+    return hipGetLastError();
+}
+
+template hipError_t launch_axis_apply<float, true>(const float*, int64_t, bool, bool, const void*, int64_t, int64_t,
+                                                   void*, int64_t, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_axis_apply<float, false>(const float*, int64_t, bool, bool, const void*, int64_t, int64_t,
+                                                    void*, int64_t, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_axis_apply<double, true>(const double*, int64_t, bool, bool, const void*, int64_t, int64_t,
+                                                    void*, int64_t, int64_t, int, int, int, hipStream_t);
+template hipError_t launch_axis_apply<double, false>(const double*, int64_t, bool, bool, const void*, int64_t,
+                                                     int64_t, void*, int64_t, int64_t, int, int, int, hipStream_t);
+
+}  // namespace dsbt

@@ -1,0 +1,152 @@
+// C ABI of the angular transform Y = P Phi (Sec. 4.1): dsbt_sht_* in include/dsbt.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dsbt.h"
+#include "angular.h"
+
+struct dsbt_sht_s {
+    int Nr = 0, nt = 0, nphi = 0, precision = DSBT_C64;
+    void* d_phi = nullptr;   // Phi[q][k] complex (interleaved), precision of the data
+    void* d_p = nullptr;     // P[q][t][j] real
+    void* d_work = nullptr;  // a[j][q][i], complex
+    void release() {
+        if (d_phi) (void)hipFree(d_phi);
+        if (d_p) (void)hipFree(d_p);
+        if (d_work) (void)hipFree(d_work);
+        d_phi = d_p = d_work = nullptr;
+    }
+};
+
+namespace {
+
+template <typename S>
+hipError_t upload(const std::vector<double>& h, void** d) {
+    std::vector<S> v(h.begin(), h.end());
+    hipError_t e = hipMalloc(d, sizeof(S) * (v.empty() ? 1 : v.size()));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*d, v.data(), sizeof(S) * v.size(), hipMemcpyHostToDevice);
+}
+
+template <typename S>
+hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStream_t s) {
+    const int nt = p->nt, nf = p->nphi, Nr = p->Nr;
+    const int64_t lf = (int64_t)nf * Nr, lt = (int64_t)nt * Nr;
+    const S* F = static_cast<const S*>(p->d_phi);
+    const S* P = static_cast<const S*>(p->d_p);
+    hipError_t e;
+    if (!inverse) {
+        // a[j][q][i] = sum_k Phi[q][k] psi[j][k][i]; c[q][t][i] = sum_j P[q][t][j] a[j][q][i]
+        e = dsbt::launch_axis_apply<S, true>(F, 0, false, false, src, lf, Nr, p->d_work, lf, Nr, nf, nt, Nr, s);
+        if (e == hipSuccess)
+            e = dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, false, false, p->d_work, Nr, lf, dst, lt, Nr,
+                                                  nt, nf, Nr, s);
+    } else {
+        // a[j][q][i] = sum_t P[q][t][j] c[q][t][i]; psi[j][k][i] = sum_q conj(Phi[q][k]) a[j][q][i]
+        e = dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, true, false, src, lt, Nr, p->d_work, Nr, lf, nt,
+                                              nf, Nr, s);
+        if (e == hipSuccess)
+            e = dsbt::launch_axis_apply<S, true>(F, 0, true, true, p->d_work, lf, Nr, dst, lf, Nr, nf, nt, Nr, s);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+dsbt_status dsbt_sht_grid(int32_t n_theta, int32_t n_phi, double* eta, double* w, double* phi) {
+    // N_phi <= 17 (|m| <= 8): for larger |m| the orthonormalisation of the
+    // associated Legendre functions on the Gauss-Legendre nodes is too
+    // ill-conditioned in FP64 to define the blocks to FP32 accuracy
+    if (n_theta < 1 || n_theta > dsbt::kShtMaxQ || n_phi < 1 || n_phi > dsbt::kShtMaxPhi || n_phi % 2 == 0)
+        return dsbt::set_error(DSBT_ERR_UNSUPPORTED, "need 1 <= N_theta <= 64 and odd 1 <= N_phi <= 17");
+    std::vector<double> e, ww;
+    dsbt::gauss_legendre(n_theta, e, ww);
+    for (int j = 0; j < n_theta; ++j) {
+        if (eta) eta[j] = e[j];
+        if (w) w[j] = ww[j];
+    }
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; phi && k < n_phi; ++k) phi[k] = 2.0 * pi * k / n_phi;
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_sht_host_tables(int32_t n_theta, int32_t n_phi, double* P) {
+    if (!P) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "P is NULL");
+    dsbt_status st = dsbt_sht_grid(n_theta, n_phi, nullptr, nullptr, nullptr);
+    if (st != DSBT_OK) return st;
+    std::vector<double> h;
+    dsbt::sht_p_tables(n_theta, n_phi, h);
+    for (size_t i = 0; i < h.size(); ++i) P[i] = h[i];
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t n_phi, int32_t precision) {
+    if (!out) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (Nr < 1) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "Nr must be positive");
+    if (precision != DSBT_C64 && precision != DSBT_C128)
+        return dsbt::set_error(DSBT_ERR_UNSUPPORTED, "precision must be DSBT_C64 or DSBT_C128");
+    dsbt_status st = dsbt_sht_grid(n_theta, n_phi, nullptr, nullptr, nullptr);
+    if (st != DSBT_OK) return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return dsbt::set_error(DSBT_ERR_NO_DEVICE, "no HIP device");
+    dsbt_sht_s* p = new (std::nothrow) dsbt_sht_s();
+    if (!p) return dsbt::set_error(DSBT_ERR_OOM, "host allocation failed");
+    p->Nr = Nr;
+    p->nt = n_theta;
+    p->nphi = n_phi;
+    p->precision = precision;
+    std::vector<double> P, F((size_t)2 * n_phi * n_phi);
+    dsbt::sht_p_tables(n_theta, n_phi, P);
+    const int M = (n_phi - 1) / 2;
+    const double pi = 3.14159265358979323846, sc = 1.0 / std::sqrt((double)n_phi);
+    for (int q = 0; q < n_phi; ++q)
+        for (int k = 0; k < n_phi; ++k) {
+            const int mk = (((q - M) * k) % n_phi + n_phi) % n_phi;   // m k mod N_phi, exact
+            const double a = 2.0 * pi * mk / n_phi;
+            F[2 * ((size_t)q * n_phi + k)] = std::cos(a) * sc;
+            F[2 * ((size_t)q * n_phi + k) + 1] = -std::sin(a) * sc;
+        }
+    const size_t work = (size_t)n_theta * n_phi * Nr * (precision == DSBT_C128 ? 16 : 8);
+    hipError_t e = precision == DSBT_C128 ? upload<double>(F, &p->d_phi) : upload<float>(F, &p->d_phi);
+    if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(P, &p->d_p) : upload<float>(P, &p->d_p);
+    if (e == hipSuccess) e = hipMalloc(&p->d_work, work);
+    if (e != hipSuccess) {
+        p->release();
+        delete p;
+        return dsbt::set_error(e == hipErrorOutOfMemory ? DSBT_ERR_OOM : DSBT_ERR_HIP, hipGetErrorString(e));
+    }
+    *out = p;
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_sht_destroy(dsbt_sht p) {
+    if (!p) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL transform");
+    p->release();
+    delete p;
+    return DSBT_OK;
+}
+
+static dsbt_status sht_apply(dsbt_sht p, const void* src, void* dst, bool inverse, void* stream) {
+    if (!p || !src || !dst) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    const hipError_t e = p->precision == DSBT_C128 ? run<double>(p, src, dst, inverse, (hipStream_t)stream)
+                                                   : run<float>(p, src, dst, inverse, (hipStream_t)stream);
+    if (e != hipSuccess) return dsbt::set_error(DSBT_ERR_HIP, hipGetErrorString(e));
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_sht_forward(dsbt_sht p, const void* grid, void* coef, void* stream) {
+    return sht_apply(p, grid, coef, false, stream);
+}
+
+dsbt_status dsbt_sht_inverse(dsbt_sht p, const void* coef, void* grid, void* stream) {
+    return sht_apply(p, coef, grid, true, stream);
+}
+
+}  // extern "C"

@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "plan_device.h"
 #include "plan_host.h"
+#include "angular.h"
 #include "monomial.h"
 #include "state.h"
 
@@ -124,6 +125,10 @@ std::vector<unsigned char> decay_table(const std::vector<double>& ex, bool fp64)
 }
 
 }  // namespace
+
+namespace dsbt {
+dsbt_status set_error(dsbt_status s, const char* msg) { return fail(s, msg); }
+}  // namespace dsbt
 
 struct dsbt_plan_s {
     int device = 0;
