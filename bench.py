@@ -223,6 +223,9 @@ def main():
     ap.add_argument("--autotune-profile", action="store_true",
                     help="only run the autotuner on the batched all-m and the uneven workloads and compare the "
                          "tuned plan with the default one")
+    ap.add_argument("--angular-profile", action="store_true",
+                    help="only time the angular transform Y = P Phi (N_r = 4096, N_theta = 64, N_phi = 17, "
+                         "complex64) forward and inverse, and B Y psi with the radial transform")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -257,6 +260,35 @@ def main():
             torch.cuda.synchronize()
             out[prec] = {"workload": w.name, "ms_per_step": e0.elapsed_time(e1) / args.steps, "steps": args.steps}
             del plan
+        print(json.dumps(out))
+        return
+
+    if args.angular_profile:
+        from paper_1509_07115_amd import AngularTransform
+
+        def timed(fn, n):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        nr, nt, nphi, rmax = 4096, 64, 17, 200.0
+        Y = AngularTransform(nr, nt, nphi)
+        plan = Plan(Y.channels(rmax))
+        g = torch.randn(Y.size, dtype=torch.complex64, device="cuda")
+        c, b = torch.empty_like(g), torch.empty_like(g)
+        steps = max(args.steps, 1)
+        out = {"workload": f"angular transform N_r={nr} N_theta={nt} N_phi={nphi} ({nt * nphi} channels, "
+                           f"l <= {nt - 1 + (nphi - 1) // 2}), complex64",
+               "ms_forward": timed(lambda: Y.forward(g, c), steps),
+               "ms_inverse": timed(lambda: Y.inverse(c, g), steps),
+               "ms_B_Y_psi": timed(lambda: plan.forward(Y.forward(g, c), b), steps),
+               "flops_per_direction": 8 * nt * nphi * nphi * nr + 4 * nphi * nt * nt * nr,
+               "bytes_per_direction": 4 * Y.size * 8}
         print(json.dumps(out))
         return
 

@@ -30,6 +30,9 @@ void sht_p_tables(int n_theta, int n_phi, std::vector<double>& P);
 // dst[o*dout + q'*dq + i] = sum_q A_o(q', q) src[o*so + q*sq + i] for o < nouter,
 // q, q' < Q, i < Nr; A_o(q', q) = mat[o*mso + (tr ? q*Q + q' : q'*Q + q)], conjugated
 // with cj.  S: float or double; CA: complex (interleaved) or real matrix.
+// Raise the dynamic-LDS limit of the axis kernel (up to 128 KiB for FP64
+// complex matrices); call before launching or capturing.
+hipError_t set_lds_limits_axis();
 template <typename S, bool CA>
 hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,
                              void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);

@@ -2,9 +2,10 @@
 // (the azimuthal DFT, or the per-m associated Legendre block) applied along one
 // grid axis for every radial point.  A workgroup takes one outer index and 64
 // consecutive radial points: their Q input vectors are staged in LDS with
-// coalesced loads (radius is the fastest axis of both layouts), and each of the
-// four waves accumulates every fourth output row for its 64 points; the matrix
-// element of a row is wave-uniform.
+// coalesced loads (radius is the fastest axis of both layouts), the Q x Q
+// matrix is staged in LDS beside them, and each of the four waves accumulates
+// every fourth output row for its 64 points, reading the matrix as LDS
+// broadcasts (one element per row and input, the same for the whole wave).
 #include "angular.h"
 
 namespace dsbt {
@@ -17,32 +18,50 @@ template <> struct Cx<double> { typedef double2 t; };
 
 constexpr int kRows = kShtMaxQ / 4;   // output rows per thread
 
+// LDS bytes of one workgroup: 64 points x Q inputs, and the Q x Q matrix
+template <typename S, bool CA>
+constexpr size_t axis_lds_bytes(int Q) {
+    return sizeof(typename Cx<S>::t) * 64 * (size_t)Q + sizeof(S) * (CA ? 2 : 1) * (size_t)Q * Q;
+}
+
 template <typename S, bool CA>
 __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int64_t mso, int tr, int cj,
                                                   const typename Cx<S>::t* __restrict__ src, int64_t so, int64_t sq,
                                                   typename Cx<S>::t* __restrict__ dst, int64_t dout, int64_t dq,
                                                   int Q, int Nr) {
     using V = typename Cx<S>::t;
-    __shared__ V X[kShtMaxQ][64];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V* X = reinterpret_cast<V*>(lds_raw);                    // X[q * 64 + point]
+    S* A = reinterpret_cast<S*>(lds_raw + sizeof(V) * 64 * Q);   // A[(q' Q + q) (2 if complex)], untransposed
     const int o = blockIdx.y;
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int r = threadIdx.x >> 6;
+    const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
     const bool live = i < Nr;
-    for (int q = r; q < Q; q += 4) X[q][threadIdx.x & 63] = live ? src[o * so + q * sq + i] : V{0, 0};
+    for (int q = r; q < Q; q += 4) X[q * 64 + (threadIdx.x & 63)] = live ? src[o * so + q * sq + i] : V{0, 0};
+    const S* Ag = mat + o * mso;
+    for (int e = threadIdx.x; e < Q * Q; e += 256) {
+        const int qo = e / Q, q = e - qo * Q;
+        const int64_t g = tr ? (int64_t)q * Q + qo : (int64_t)e;
+        if constexpr (CA) {
+            A[2 * e] = Ag[2 * g];
+            A[2 * e + 1] = cj ? -Ag[2 * g + 1] : Ag[2 * g + 1];
+        } else {
+            A[e] = Ag[g];
+        }
+    }
     __syncthreads();
-    const S* A = mat + o * mso;
     V acc[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) acc[u] = V{0, 0};
     for (int q = 0; q < Q; ++q) {
-        const V x = X[q][threadIdx.x & 63];
+        const V x = X[q * 64 + (threadIdx.x & 63)];
 #pragma unroll
         for (int u = 0; u < kRows; ++u) {
             const int qo = r + 4 * u;
             if (qo < Q) {
-                const int64_t e = tr ? (int64_t)q * Q + qo : (int64_t)qo * Q + q;
+                const int e = qo * Q + q;
                 if constexpr (CA) {
-                    const S ar = A[2 * e], ai = cj ? -A[2 * e + 1] : A[2 * e + 1];
+                    const S ar = A[2 * e], ai = A[2 * e + 1];
                     acc[u].x += ar * x.x - ai * x.y;
                     acc[u].y += ar * x.y + ai * x.x;
                 } else {
@@ -68,9 +87,26 @@ hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const 
                              void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
     using V = typename Cx<S>::t;
     if (Q < 1 || Q > kShtMaxQ || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((axis_apply<S, CA>), dim3((Nr + 63) / 64, nouter), dim3(256), 0, s, mat, mso, tr ? 1 : 0,
+    const size_t lds = axis_lds_bytes<S, CA>(Q);
+    hipLaunchKernelGGL((axis_apply<S, CA>), dim3((Nr + 63) / 64, nouter), dim3(256), lds, s, mat, mso, tr ? 1 : 0,
                        cj ? 1 : 0, (const V*)src, so, sq, (V*)dst, dout, dq, Q, Nr);
     return hipGetLastError();
+}
+
+hipError_t set_lds_limits_axis() {
+    hipError_t e = hipFuncSetAttribute((const void*)axis_apply<float, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)axis_lds_bytes<float, true>(kShtMaxQ));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)axis_apply<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)axis_lds_bytes<float, false>(kShtMaxQ));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)axis_apply<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)axis_lds_bytes<double, true>(kShtMaxQ));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)axis_apply<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)axis_lds_bytes<double, false>(kShtMaxQ));
+    return e;
 }
 
 template hipError_t launch_axis_apply<float, true>(const float*, int64_t, bool, bool, const void*, int64_t, int64_t,

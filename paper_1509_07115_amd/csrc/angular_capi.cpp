@@ -114,7 +114,8 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
             F[2 * ((size_t)q * n_phi + k) + 1] = -std::sin(a) * sc;
         }
     const size_t work = (size_t)n_theta * n_phi * Nr * (precision == DSBT_C128 ? 16 : 8);
-    hipError_t e = precision == DSBT_C128 ? upload<double>(F, &p->d_phi) : upload<float>(F, &p->d_phi);
+    hipError_t e = dsbt::set_lds_limits_axis();
+    if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(F, &p->d_phi) : upload<float>(F, &p->d_phi);
     if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(P, &p->d_p) : upload<float>(P, &p->d_p);
     if (e == hipSuccess) e = hipMalloc(&p->d_work, work);
     if (e != hipSuccess) {
