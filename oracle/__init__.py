@@ -13,5 +13,6 @@ tdse     dense split-operator step, propagation and adjoint gradient (Sec. 4.1)
 sbf      spherical-Bessel references: closed forms, quadrature, corrected momenta (Sec. 3)
 monomial the paper's own monomial-moment fast multiplication (Sec. 2.6), FP64, for its error envelope
 angular  the angular transform Y = P Phi of the DSBT-DVR solver (Sec. 4.1)
+tdse3d   dense 3D split step in the coordinate gauge (Sec. 4.1) for the oscillator test of Sec. 4.2
 """
-from . import dsbt, exact, tdse, sbf, monomial, angular  # noqa: F401
+from . import dsbt, exact, tdse, sbf, monomial, angular, tdse3d  # noqa: F401

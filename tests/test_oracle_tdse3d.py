@@ -1,0 +1,54 @@
+"""Pins of the oracle's 3D split step (Sec. 4.1, coordinate gauge) on the driven
+harmonic oscillator of Sec. 4.2 (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import angular, tdse3d
+
+
+def oscillator(rmax, dr=0.2, nt=16, nphi=1):
+    nr = int(round(rmax / dr))
+    r, eta = tdse3d.grid_r_eta(nr, rmax, nt, nphi)
+    _, w, _ = angular.grid(nt, nphi)
+    radial = math.pi ** -0.75 * np.exp(-r ** 2 / 2) * r * math.sqrt(rmax / nr)   # ground state r psi sqrt(dr)
+    psi = radial[None, None, :] * np.sqrt(w * 2 * math.pi / nphi)[:, None, None] * np.ones((nt, nphi, 1))
+    V0 = np.broadcast_to(0.5 * r ** 2, (nt, nphi, nr)).copy()
+    V1 = -(eta[:, None, None] * r[None, None, :]) * np.ones((1, nphi, 1))      # -z: U = r^2/2 - F(t) z
+    return psi.astype(np.complex128), V0, V1, r, eta
+
+
+def z_classical(t, omega, A0):
+    # z'' + z = omega A0 cos(omega t), z(0) = z'(0) = 0 (Ehrenfest is exact for this potential)
+    if omega == 1.0:
+        return A0 * t * math.sin(t) / 2
+    return omega * A0 / (1 - omega ** 2) * (math.cos(omega * t) - math.cos(t))
+
+
+def propagate(rmax, omega=2.0, A0=0.25, dt=0.01, T=10.0):
+    psi, V0, V1, r, eta = oscillator(rmax)
+    for s in range(int(round(T / dt))):
+        psi = tdse3d.step3d(psi, rmax, V0, V1, omega * A0 * math.cos(omega * (s + 0.5) * dt), dt)
+    return psi, r, eta
+
+
+def test_ground_state_is_stationary_and_norm_is_kept():
+    psi0, V0, V1, r, eta = oscillator(12.8)
+    psi = psi0
+    for _ in range(200):
+        psi = tdse3d.step3d(psi, 12.8, V0, V1, 0.0, 0.01)
+    assert abs(np.sum(np.abs(psi) ** 2) - 1) < 1e-12
+    assert abs(abs(np.vdot(psi0, psi)) - 1) < 1e-6       # |<psi_0|psi(t)>| = 1 for an eigenstate
+    assert abs(tdse3d.expect_z(psi, r, eta)) < 1e-12
+
+
+def test_driven_oscillator_follows_the_classical_path_with_rmax_convergence():
+    # Sec. 4.2: the error of the scheme falls as rmax^-2 at fixed dr = 0.2; here
+    # the error of <z>(t = 10) against the classical trajectory, omega = 2
+    errs = []
+    for rmax in (12.8, 25.6):
+        psi, r, eta = propagate(rmax)
+        errs.append(abs(tdse3d.expect_z(psi, r, eta) - z_classical(10.0, 2.0, 0.25)))
+    assert errs[0] < 5e-3 and errs[1] < 1.5e-3
+    assert errs[0] / errs[1] > 3.0
