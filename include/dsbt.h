@@ -263,6 +263,14 @@ dsbt_status dsbt_sht_destroy(dsbt_sht s);
  * so calls on one transform must not overlap); grid and coef may alias. */
 dsbt_status dsbt_sht_forward(dsbt_sht s, const void* grid, void* coef, void* stream);
 dsbt_status dsbt_sht_inverse(dsbt_sht s, const void* coef, void* grid, void* stream);
+/* Potential factor of the 3D split step (Sec. 4.1, coordinate gauge), in place
+ * on a grid buffer: grid *= exp(-i (V0 + F V1) dt/2), V0 and V1 device FP64
+ * arrays in grid layout (either may be NULL: zero), F the step's field strength;
+ * angles formed and reduced mod 2 pi in FP64.  With Y and a plan over
+ * Y's channels whose potential is zero, one step is: this call, Y forward,
+ * dsbt_kinetic_step (B^T exp(-i K dt) B), Y inverse, this call. */
+dsbt_status dsbt_sht_potential_phase(dsbt_sht s, void* grid, const double* V0, const double* V1, double F, double dt,
+                                     void* stream);
 
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is

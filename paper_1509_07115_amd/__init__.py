@@ -306,6 +306,23 @@ class AngularTransform:
                                               _stream_handle(stream)), "dsbt_sht_inverse")
         return out
 
+    def potential_phase(self, grid, V0=None, V1=None, F: float = 0.0, dt: float = 0.0, stream=None):
+        """grid *= exp(-i (V0 + F V1) dt/2) in place (``dsbt_sht_potential_phase``);
+        V0, V1: cuda float64 tensors in grid layout, or None."""
+        import torch
+
+        def ptr(v, name):
+            if v is None:
+                return None
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+                    and v.numel() >= self.size):
+                raise TypeError(f"{name} must be a contiguous cuda float64 tensor of the grid size")
+            return ctypes.c_void_p(v.data_ptr())
+        _lib.check(self._lib.dsbt_sht_potential_phase(self._h, self._buf(grid, "grid"), ptr(V0, "V0"), ptr(V1, "V1"),
+                                                      float(F), float(dt), _stream_handle(stream)),
+                   "dsbt_sht_potential_phase")
+        return grid
+
     def close(self):
         if self._h:
             self._lib.dsbt_sht_destroy(self._h)
@@ -316,6 +333,16 @@ class AngularTransform:
             self.close()
         except Exception:
             pass
+
+
+def step3d(Y: "AngularTransform", plan: "Plan", grid, V0, V1, F: float, dt: float, coef=None, stream=None):
+    """One 3D split step in the coordinate gauge (Sec. 4.1) in place on ``grid``:
+    exp(-i U dt/2) Y^H B^T exp(-i K dt) B Y exp(-i U dt/2), U = V0 + F V1.  ``plan`` is a
+    Plan over ``Y.channels(rmax)`` whose potential was set to zero with the same dt."""
+    coef = Y.forward(Y.potential_phase(grid, V0, V1, F, dt, stream), coef, stream)
+    plan.kinetic_step(coef, 1, stream=stream)
+    Y.inverse(coef, grid, stream)
+    return Y.potential_phase(grid, V0, V1, F, dt, stream)
 
 
 def sht_grid(n_theta: int, n_phi: int):

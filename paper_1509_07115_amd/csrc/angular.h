@@ -37,4 +37,10 @@ template <typename S, bool CA>
 hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,
                              void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);
 
+// x[i] *= exp(-i (V0[i] + F V1[i]) dt/2) for i < n (complex of S; V0, V1 FP64
+// device arrays or null), angles reduced mod 2 pi in FP64.
+template <typename S>
+hipError_t launch_grid_phase(void* x, const double* V0, const double* V1, double F, double dt, int64_t n,
+                             hipStream_t s);
+
 }  // namespace dsbt

@@ -80,7 +80,41 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
     }
 }
 
+// x[i] *= exp(-i (V0[i] + F V1[i]) dt/2), the angle formed and reduced mod 2 pi
+// in FP64 (V0 or V1 may be null: zero)
+template <typename S>
+__global__ void __launch_bounds__(256) grid_phase(typename Cx<S>::t* __restrict__ x, const double* __restrict__ V0,
+                                                  const double* __restrict__ V1, double F, double half_dt,
+                                                  int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double a = ((V0 ? V0[i] : 0.0) + (V1 ? F * V1[i] : 0.0)) * half_dt;
+    const double twopi = 6.283185307179586476925286766559;
+    a -= twopi * rint(a / twopi);
+    S sn, cs;
+    if constexpr (sizeof(S) == sizeof(float)) {
+        sincosf((float)a, &sn, &cs);
+    } else {
+        sincos(a, &sn, &cs);
+    }
+    const typename Cx<S>::t z = x[i];
+    x[i] = {z.x * cs + z.y * sn, z.y * cs - z.x * sn};
+}
+
 }  // namespace
+
+template <typename S>
+hipError_t launch_grid_phase(void* x, const double* V0, const double* V1, double F, double dt, int64_t n,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(grid_phase<S>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (typename Cx<S>::t*)x, V0, V1, F, 0.5 * dt, n);
+    return hipGetLastError();
+}
+template hipError_t launch_grid_phase<float>(void*, const double*, const double*, double, double, int64_t,
+                                             hipStream_t);
+template hipError_t launch_grid_phase<double>(void*, const double*, const double*, double, double, int64_t,
+                                              hipStream_t);
 
 template <typename S, bool CA>
 hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,

@@ -150,4 +150,16 @@ dsbt_status dsbt_sht_inverse(dsbt_sht p, const void* coef, void* grid, void* str
     return sht_apply(p, coef, grid, true, stream);
 }
 
+dsbt_status dsbt_sht_potential_phase(dsbt_sht p, void* grid, const double* V0, const double* V1, double F, double dt,
+                                     void* stream) {
+    if (!p || !grid) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!std::isfinite(F) || !std::isfinite(dt)) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "non-finite F or dt");
+    const int64_t n = (int64_t)p->Nr * p->nt * p->nphi;
+    const hipError_t e = p->precision == DSBT_C128
+                             ? dsbt::launch_grid_phase<double>(grid, V0, V1, F, dt, n, (hipStream_t)stream)
+                             : dsbt::launch_grid_phase<float>(grid, V0, V1, F, dt, n, (hipStream_t)stream);
+    if (e != hipSuccess) return dsbt::set_error(DSBT_ERR_HIP, hipGetErrorString(e));
+    return DSBT_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,93 @@
+"""3D split step (Sec. 4.1, coordinate gauge) on the GPU: angular transform,
+radial DSBT step and the grid potential factor, against the oracle, and the
+driven oscillator of Sec. 4.2."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import angular, tdse3d
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu(built_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def setup(nt, nphi, nr, rmax, precision, kinetic="plain"):
+    from paper_1509_07115_amd import AngularTransform, Plan
+    Y = AngularTransform(nr, nt, nphi, precision)
+    plan = Plan(Y.channels(rmax), precision=precision, kinetic=kinetic)
+    return Y, plan
+
+
+def fields(nt, nphi, nr, rmax, tilt=0.0):
+    r, eta = tdse3d.grid_r_eta(nr, rmax, nt, nphi)
+    _, _, phi = angular.grid(nt, nphi)
+    sin_t = np.sqrt(1 - eta ** 2)
+    V0 = 0.5 * r[None, None, :] ** 2 + tilt * r[None, None, :] * sin_t[:, None, None] * np.cos(phi)[None, :, None]
+    V1 = -(eta[:, None, None] * r[None, None, :]) * np.ones((1, nphi, 1))
+    return np.ascontiguousarray(V0 * np.ones((nt, nphi, nr))), np.ascontiguousarray(V1), r, eta
+
+
+def d64(x):
+    return torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).to(torch.float64).cuda()
+
+
+@pytest.mark.parametrize("precision,tol", [("c128", 1e-10), ("c64", 5e-5)])
+def test_steps_match_oracle(precision, tol):
+    # a potential that couples m (x-tilt) and a time-dependent z field
+    from paper_1509_07115_amd import step3d
+    nt, nphi, nr, rmax, dt = 8, 5, 64, 12.8, 0.02
+    V0, V1, r, eta = fields(nt, nphi, nr, rmax, tilt=0.3)
+    rng = np.random.default_rng(31)
+    psi = rng.standard_normal((nt, nphi, nr)) + 1j * rng.standard_normal((nt, nphi, nr))
+    psi /= np.linalg.norm(psi)
+    Y, plan = setup(nt, nphi, nr, rmax, precision)
+    plan.set_potential(np.zeros(plan.elems), dt)
+    g = torch.from_numpy(psi.reshape(-1)).to(Y.dtype).cuda()
+    v0, v1 = d64(V0), d64(V1)
+    ref = psi
+    for s in range(10):
+        F = 0.5 * math.cos(0.7 * (s + 0.5) * dt)
+        step3d(Y, plan, g, v0, v1, F, dt)
+        ref = tdse3d.step3d(ref, rmax, V0, V1, F, dt)
+    got = g.cpu().numpy().reshape(nt, nphi, nr)
+    assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+    assert abs(np.linalg.norm(got) - 1) < 10 * tol
+
+
+def test_driven_oscillator_rmax_convergence():
+    # Sec. 4.2 (N_theta = 16, N_phi = 1, dr = 0.2, A0 = 0.25, omega = 2): <z>(t = 10)
+    # against the classical path, on the GPU in complex64; the error falls about
+    # 4x from rmax = 12.8 to 25.6 (oracle: 3.1e-3 and 7.2e-4)
+    from paper_1509_07115_amd import step3d
+    nt, nphi, dr, dt, omega, A0 = 16, 1, 0.2, 0.01, 2.0, 0.25
+    t_end = 10.0
+    zc = omega * A0 / (1 - omega ** 2) * (math.cos(omega * t_end) - math.cos(t_end))
+    errs = []
+    for rmax in (12.8, 25.6):
+        nr = int(round(rmax / dr))
+        V0, V1, r, eta = fields(nt, nphi, nr, rmax)
+        _, w, _ = angular.grid(nt, nphi)
+        radial = math.pi ** -0.75 * np.exp(-r ** 2 / 2) * r * math.sqrt(dr)
+        psi = radial[None, None, :] * np.sqrt(w * 2 * math.pi)[:, None, None] * np.ones((nt, nphi, 1))
+        Y, plan = setup(nt, nphi, nr, rmax, "c64")
+        plan.set_potential(np.zeros(plan.elems), dt)
+        g = torch.from_numpy(psi.reshape(-1)).to(torch.complex64).cuda()
+        v0, v1 = d64(V0), d64(V1)
+        coef = torch.empty_like(g)
+        for s in range(int(round(t_end / dt))):
+            step3d(Y, plan, g, v0, v1, omega * A0 * math.cos(omega * (s + 0.5) * dt), dt, coef)
+        got = g.cpu().numpy().astype(np.complex128).reshape(nt, nphi, nr)
+        norm = np.sum(np.abs(got) ** 2)
+        errs.append(abs(tdse3d.expect_z(got, r, eta) / norm - zc))
+        # complex64 data with FP32 arithmetic drifts about 1.5e-4 in norm per 1000 steps
+        assert abs(norm - 1) < 5e-4
+    print(f"<z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}")
+    assert errs[0] < 5e-3 and errs[1] < 1.5e-3 and errs[0] / errs[1] > 3.0
