@@ -264,7 +264,7 @@ def main():
         return
 
     if args.angular_profile:
-        from paper_1509_07115_amd import AngularTransform
+        from paper_1509_07115_amd import AngularTransform, sht_grid
 
         def timed(fn, n):
             fn()
@@ -282,11 +282,25 @@ def main():
         g = torch.randn(Y.size, dtype=torch.complex64, device="cuda")
         c, b = torch.empty_like(g), torch.empty_like(g)
         steps = max(args.steps, 1)
+
+        def step3d_ms():
+            # one split step of U = r^2/2 - F z on this grid (the potential factor twice, Y, the radial
+            # kinetic step, Y^H)
+            from paper_1509_07115_amd import step3d
+            r = (torch.arange(nr, dtype=torch.float64, device="cuda") + 0.5) * (rmax / nr)
+            eta = torch.from_numpy(sht_grid(nt, nphi)[0]).cuda()
+            v0 = (0.5 * r * r).repeat(nt * nphi).contiguous()
+            v1 = (-eta[:, None, None] * r[None, None, :]).expand(nt, nphi, nr).contiguous().reshape(-1)
+            step_plan = Plan(Y.channels(rmax))
+            step_plan.set_potential(np.zeros(step_plan.elems), 0.01)
+            x = g.clone()
+            return timed(lambda: step3d(Y, step_plan, x, v0, v1, 0.3, 0.01, c), steps)
         out = {"workload": f"angular transform N_r={nr} N_theta={nt} N_phi={nphi} ({nt * nphi} channels, "
                            f"l <= {nt - 1 + (nphi - 1) // 2}), complex64",
                "ms_forward": timed(lambda: Y.forward(g, c), steps),
                "ms_inverse": timed(lambda: Y.inverse(c, g), steps),
                "ms_B_Y_psi": timed(lambda: plan.forward(Y.forward(g, c), b), steps),
+               "ms_step3d": step3d_ms(),
                "flops_per_direction": 8 * nt * nphi * nphi * nr + 4 * nphi * nt * nt * nr,
                "bytes_per_direction": 4 * Y.size * 8}
         print(json.dumps(out))
