@@ -19,7 +19,7 @@ import numpy as np
 
 from . import angular, dsbt, tdse
 
-__all__ = ["step3d", "expect_z", "grid_r_eta"]
+__all__ = ["step3d", "expect_z", "grid_r_eta", "to_momentum_order", "from_momentum_order", "step3d_velocity"]
 
 
 def grid_r_eta(nr: int, rmax: float, nt: int, nphi: int):
@@ -46,3 +46,49 @@ def step3d(psi: np.ndarray, rmax: float, V0: np.ndarray, V1: np.ndarray, F: floa
 def expect_z(psi: np.ndarray, r: np.ndarray, eta: np.ndarray) -> float:
     """<z> = sum |psi_jki|^2 r_i eta_j (the grid values carry the volume weights)."""
     return float(np.sum(np.abs(psi) ** 2 * r[None, None, :] * eta[:, None, None]))
+
+
+# --- velocity gauge (Sec. 4.1, the printed nine-line sequence) ---------------
+#
+# With a vector potential A(t) along z the step passes through the momentum
+# DVR: c = B Y psi, a half kinetic factor, phi = Ytilde^H c on the unified
+# momentum grid k~_n = n dk (n = 1..N, eq. tilde_k_grid), the factor
+# exp(i A k~_n eta_j tau), back with Ytilde, the second half kinetic factor,
+# psi = Y^H B^T c.  Ytilde = i^l Y (modified spherical harmonics).  On the
+# unified grid the slots of even l (n = 1..N) stay in place; for odd l the slot
+# of n = 0 moves to n = N (reading: it stands for the top momentum).
+
+
+def to_momentum_order(c: np.ndarray, ell: int) -> np.ndarray:
+    """Channel coefficients in slot order -> unified order n = 1..N."""
+    return c if ell % 2 == 0 else np.roll(c, -1, axis=-1)
+
+
+def from_momentum_order(u: np.ndarray, ell: int) -> np.ndarray:
+    return u if ell % 2 == 0 else np.roll(u, 1, axis=-1)
+
+
+def step3d_velocity(psi: np.ndarray, rmax: float, V0: np.ndarray, A: float, dt: float,
+                    corrected: bool = False) -> np.ndarray:
+    nt, nphi, nr = psi.shape
+    M = (nphi - 1) // 2
+    eta, _, _ = angular.grid(nt, nphi)
+    ktil = np.arange(1, nr + 1) * dsbt.delta_k(rmax)
+    pu = np.exp(-1j * V0 * dt / 2.0)
+    c = angular.forward(pu * psi, nt, nphi)
+    ls = [[abs(q - M) + t for t in range(nt)] for q in range(nphi)]
+    half = {}
+    for q in range(nphi):
+        for t in range(nt):
+            ell = ls[q][t]
+            half[ell] = np.exp(-1j * tdse.kinetic_energies(nr, rmax, ell, corrected) * dt / 2.0)
+            c[q, t] = to_momentum_order(half[ell] * dsbt.forward(c[q, t], ell), ell) * (1j) ** (-ell)
+    phi = angular.inverse(c, nt, nphi)                                 # Ytilde^H on the momentum grid
+    phi *= np.exp(1j * A * ktil[None, None, :] * eta[:, None, None] * dt)
+    c = angular.forward(phi, nt, nphi)
+    for q in range(nphi):
+        for t in range(nt):
+            ell = ls[q][t]
+            b = from_momentum_order(c[q, t] * (1j) ** ell, ell)
+            c[q, t] = dsbt.inverse(half[ell] * b, ell)
+    return pu * angular.inverse(c, nt, nphi)
