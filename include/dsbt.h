@@ -271,6 +271,13 @@ dsbt_status dsbt_sht_inverse(dsbt_sht s, const void* coef, void* grid, void* str
  * dsbt_kinetic_step (B^T exp(-i K dt) B), Y inverse, this call. */
 dsbt_status dsbt_sht_potential_phase(dsbt_sht s, void* grid, const double* V0, const double* V1, double F, double dt,
                                      void* stream);
+/* Velocity gauge (Sec. 4.1): coefficient channels in slot order (c[q][t][i],
+ * i the DSBT slot) to the unified momentum grid k~_n = n dk, n = 1..Nr
+ * (eq. tilde_k_grid) and back.  Forward (inverse = 0): dst = i^-l src, with
+ * the n = 0 slot of odd l moved to n = Nr; then dsbt_sht_inverse gives
+ * Ytilde^H c, the plane-wave grid [j][k][n].  Inverse (inverse != 0) undoes
+ * it (i^l).  src and dst must not overlap (DSBT_ERR_INVALID_ARG). */
+dsbt_status dsbt_sht_momentum_order(dsbt_sht s, const void* src, void* dst, int32_t inverse, void* stream);
 
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is

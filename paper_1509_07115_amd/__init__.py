@@ -323,6 +323,32 @@ class AngularTransform:
                    "dsbt_sht_potential_phase")
         return grid
 
+    def momentum_order(self, src, dst=None, inverse: bool = False, stream=None):
+        """Channels <-> the unified momentum order with i^-l / i^l (``dsbt_sht_momentum_order``)."""
+        import torch
+        dst = torch.empty(self.size, dtype=self.dtype, device="cuda") if dst is None else dst
+        _lib.check(self._lib.dsbt_sht_momentum_order(self._h, self._buf(src, "src"), self._buf(dst, "dst"),
+                                                     1 if inverse else 0, _stream_handle(stream)),
+                   "dsbt_sht_momentum_order")
+        return dst
+
+    def kinetic(self, rmax: float, kinetic: str = "plain"):
+        """K_n = k_n^2/2 per channel slot (cuda float64, coefficient layout)."""
+        import torch
+        out = np.zeros((len(self.lm()), self.Nr))
+        for c, (l, _) in enumerate(self.lm()):
+            out[c] = 0.5 * kinetic_momenta(self.Nr, l, rmax, kinetic) ** 2
+        return torch.from_numpy(out.reshape(-1)).cuda()
+
+    def momentum_pz(self, rmax: float):
+        """-2 k~_n eta_j on the momentum grid [j][k][n] (cuda float64): with it as V1 and F = A,
+        ``potential_phase`` multiplies by exp(i A k~_n eta_j dt)."""
+        import torch
+        eta = sht_grid(self.n_theta, self.n_phi)[0]
+        k = np.arange(1, self.Nr + 1) * (np.pi / rmax)
+        v = -2.0 * eta[:, None, None] * k[None, None, :] * np.ones((1, self.n_phi, 1))
+        return torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).cuda()
+
     def close(self):
         if self._h:
             self._lib.dsbt_sht_destroy(self._h)
@@ -343,6 +369,26 @@ def step3d(Y: "AngularTransform", plan: "Plan", grid, V0, V1, F: float, dt: floa
     plan.kinetic_step(coef, 1, stream=stream)
     Y.inverse(coef, grid, stream)
     return Y.potential_phase(grid, V0, V1, F, dt, stream)
+
+
+def step3d_velocity(Y: "AngularTransform", plan: "Plan", grid, V0, K, Pz, A: float, dt: float, w1=None, w2=None,
+                    stream=None):
+    """One 3D split step in the velocity gauge (Sec. 4.1, the printed sequence) in place on ``grid``:
+    exp(-i V0 dt/2), c = B Y psi, exp(-i K dt/2), Ytilde^H, exp(i A k~ eta dt), Ytilde,
+    exp(-i K dt/2), Y^H B^T, exp(-i V0 dt/2).  K = ``Y.kinetic(rmax)``, Pz = ``Y.momentum_pz(rmax)``,
+    ``plan`` a Plan over ``Y.channels(rmax)``; w1, w2: optional work buffers of Y's size."""
+    import torch
+    w1 = torch.empty_like(grid) if w1 is None else w1
+    w2 = torch.empty_like(grid) if w2 is None else w2
+    Y.potential_phase(grid, V0, None, 0.0, dt, stream)
+    c = plan.forward(Y.forward(grid, w1, stream), w1, stream)
+    Y.potential_phase(c, K, None, 0.0, dt, stream)
+    Y.inverse(Y.momentum_order(c, w2, False, stream), w1, stream)       # plane-wave grid in w1
+    Y.potential_phase(w1, None, Pz, A, dt, stream)
+    Y.momentum_order(Y.forward(w1, w2, stream), w1, True, stream)
+    Y.potential_phase(w1, K, None, 0.0, dt, stream)
+    Y.inverse(plan.inverse(w1, w1, stream), grid, stream)
+    return Y.potential_phase(grid, V0, None, 0.0, dt, stream)
 
 
 def sht_grid(n_theta: int, n_phi: int):

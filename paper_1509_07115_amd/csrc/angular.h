@@ -43,4 +43,10 @@ template <typename S>
 hipError_t launch_grid_phase(void* x, const double* V0, const double* V1, double F, double dt, int64_t n,
                              hipStream_t s);
 
+// Coefficient channels (layout c[q][t][i]) to the unified momentum order and
+// back, with the factor i^-l (forward) or i^l (inverse) of the modified
+// spherical harmonics; src and dst must not overlap.
+template <typename S>
+hipError_t launch_momentum_order(const void* src, void* dst, int nt, int nphi, int Nr, bool inverse, hipStream_t s);
+
 }  // namespace dsbt

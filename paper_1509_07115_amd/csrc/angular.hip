@@ -101,7 +101,42 @@ __global__ void __launch_bounds__(256) grid_phase(typename Cx<S>::t* __restrict_
     x[i] = {z.x * cs + z.y * sn, z.y * cs - z.x * sn};
 }
 
+// Channel (q, t), l = |q - M| + t, of Nr slots: forward, out[u] = i^-l in[j(u)]
+// with j(u) = (u + 1) mod Nr for odd l (the n = 0 slot moves to the top of the
+// unified grid n = 1..Nr) and j(u) = u for even l; inverse, out[j] = i^l in[u(j)].
+template <typename S>
+__global__ void __launch_bounds__(256) momentum_order(const typename Cx<S>::t* __restrict__ src,
+                                                      typename Cx<S>::t* __restrict__ dst, int nt, int M, int Nr,
+                                                      int inverse) {
+    const int c = blockIdx.y;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= Nr) return;
+    const int q = c / nt, t = c - q * nt;
+    const int l = (q > M ? q - M : M - q) + t;
+    int from = x;
+    if (l & 1) from = inverse ? (x + Nr - 1) % Nr : (x + 1) % Nr;
+    const typename Cx<S>::t z = src[(int64_t)c * Nr + from];
+    // multiply by i^e, e = -l (forward) or l (inverse), e mod 4
+    const int e = ((inverse ? l : -l) % 4 + 4) % 4;
+    typename Cx<S>::t w;
+    if (e == 0) w = z;
+    else if (e == 1) w = {-z.y, z.x};
+    else if (e == 2) w = {-z.x, -z.y};
+    else w = {z.y, -z.x};
+    dst[(int64_t)c * Nr + x] = w;
+}
+
 }  // namespace
+
+template <typename S>
+hipError_t launch_momentum_order(const void* src, void* dst, int nt, int nphi, int Nr, bool inverse, hipStream_t s) {
+    hipLaunchKernelGGL(momentum_order<S>, dim3((unsigned)((Nr + 255) / 256), (unsigned)(nt * nphi)), dim3(256), 0, s,
+                       (const typename Cx<S>::t*)src, (typename Cx<S>::t*)dst, nt, (nphi - 1) / 2, Nr,
+                       inverse ? 1 : 0);
+    return hipGetLastError();
+}
+template hipError_t launch_momentum_order<float>(const void*, void*, int, int, int, bool, hipStream_t);
+template hipError_t launch_momentum_order<double>(const void*, void*, int, int, int, bool, hipStream_t);
 
 template <typename S>
 hipError_t launch_grid_phase(void* x, const double* V0, const double* V1, double F, double dt, int64_t n,

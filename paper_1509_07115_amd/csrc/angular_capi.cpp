@@ -162,4 +162,18 @@ dsbt_status dsbt_sht_potential_phase(dsbt_sht p, void* grid, const double* V0, c
     return DSBT_OK;
 }
 
+dsbt_status dsbt_sht_momentum_order(dsbt_sht p, const void* src, void* dst, int32_t inverse, void* stream) {
+    if (!p || !src || !dst) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    const size_t bytes = (size_t)p->Nr * p->nt * p->nphi * (p->precision == DSBT_C128 ? 16 : 8);
+    const char* a = static_cast<const char*>(src);
+    const char* b = static_cast<const char*>(dst);
+    if (a < b + bytes && b < a + bytes) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "src and dst overlap");
+    const hipError_t e =
+        p->precision == DSBT_C128
+            ? dsbt::launch_momentum_order<double>(src, dst, p->nt, p->nphi, p->Nr, inverse != 0, (hipStream_t)stream)
+            : dsbt::launch_momentum_order<float>(src, dst, p->nt, p->nphi, p->Nr, inverse != 0, (hipStream_t)stream);
+    if (e != hipSuccess) return dsbt::set_error(DSBT_ERR_HIP, hipGetErrorString(e));
+    return DSBT_OK;
+}
+
 }  // extern "C"

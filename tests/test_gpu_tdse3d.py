@@ -91,3 +91,61 @@ def test_driven_oscillator_rmax_convergence():
         assert abs(norm - 1) < 5e-4
     print(f"<z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}")
     assert errs[0] < 5e-3 and errs[1] < 1.5e-3 and errs[0] / errs[1] > 3.0
+
+
+@pytest.mark.parametrize("precision,tol", [("c128", 1e-10), ("c64", 5e-5)])
+def test_velocity_gauge_steps_match_oracle(precision, tol):
+    from paper_1509_07115_amd import step3d_velocity
+    nt, nphi, nr, rmax, dt = 8, 5, 64, 12.8, 0.02
+    V0, _, r, eta = fields(nt, nphi, nr, rmax, tilt=0.3)
+    rng = np.random.default_rng(32)
+    psi = rng.standard_normal((nt, nphi, nr)) + 1j * rng.standard_normal((nt, nphi, nr))
+    psi /= np.linalg.norm(psi)
+    Y, plan = setup(nt, nphi, nr, rmax, precision)
+    K, Pz = Y.kinetic(rmax), Y.momentum_pz(rmax)
+    g = torch.from_numpy(psi.reshape(-1)).to(Y.dtype).cuda()
+    v0 = d64(V0)
+    ref = psi
+    for s in range(10):
+        A = -0.4 * math.sin(0.9 * (s + 0.5) * dt)
+        step3d_velocity(Y, plan, g, v0, K, Pz, A, dt)
+        ref = tdse3d.step3d_velocity(ref, rmax, V0, A, dt)
+    got = g.cpu().numpy().reshape(nt, nphi, nr)
+    assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+
+
+def test_momentum_order_round_trip_and_overlap_check():
+    from paper_1509_07115_amd import AngularTransform, DsbtError
+    Y = AngularTransform(32, 4, 5, "c128")
+    x = torch.randn(Y.size, dtype=torch.complex128, device="cuda")
+    back = Y.momentum_order(Y.momentum_order(x), inverse=True)
+    assert torch.equal(back, x)
+    with pytest.raises(DsbtError, match="INVALID_ARG"):
+        Y.momentum_order(x, x)
+
+
+def test_driven_oscillator_velocity_gauge():
+    # the same <z>(t) in the velocity gauge (oracle: 4.1e-3 and 9.9e-4)
+    from paper_1509_07115_amd import step3d_velocity
+    nt, nphi, dr, dt, omega, A0 = 16, 1, 0.2, 0.01, 2.0, 0.25
+    zc = omega * A0 / (1 - omega ** 2) * (math.cos(omega * 10.0) - math.cos(10.0))
+    errs = []
+    for rmax in (12.8, 25.6):
+        nr = int(round(rmax / dr))
+        V0, _, r, eta = fields(nt, nphi, nr, rmax)
+        _, w, _ = angular.grid(nt, nphi)
+        radial = math.pi ** -0.75 * np.exp(-r ** 2 / 2) * r * math.sqrt(dr)
+        psi = radial[None, None, :] * np.sqrt(w * 2 * math.pi)[:, None, None] * np.ones((nt, nphi, 1))
+        Y, plan = setup(nt, nphi, nr, rmax, "c64")
+        K, Pz = Y.kinetic(rmax), Y.momentum_pz(rmax)
+        g = torch.from_numpy(psi.reshape(-1)).to(torch.complex64).cuda()
+        v0 = d64(V0)
+        w1, w2 = torch.empty_like(g), torch.empty_like(g)
+        for s in range(1000):
+            step3d_velocity(Y, plan, g, v0, K, Pz, -A0 * math.sin(omega * (s + 0.5) * dt), dt, w1, w2)
+        got = g.cpu().numpy().astype(np.complex128).reshape(nt, nphi, nr)
+        norm = np.sum(np.abs(got) ** 2)
+        errs.append(abs(tdse3d.expect_z(got, r, eta) / norm - zc))
+        assert abs(norm - 1) < 5e-4
+    print(f"velocity gauge <z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}")
+    assert errs[0] < 6e-3 and errs[1] < 1.5e-3 and errs[0] / errs[1] > 3.0
