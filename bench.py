@@ -295,12 +295,22 @@ def main():
             step_plan.set_potential(np.zeros(step_plan.elems), 0.01)
             x = g.clone()
             return timed(lambda: step3d(Y, step_plan, x, v0, v1, 0.3, 0.01, c), steps)
+
+        def step3d_velocity_ms():
+            # one velocity-gauge step (the printed sequence through the momentum grid), A along z
+            from paper_1509_07115_amd import step3d_velocity
+            r = (torch.arange(nr, dtype=torch.float64, device="cuda") + 0.5) * (rmax / nr)
+            v0 = (0.5 * r * r).repeat(nt * nphi).contiguous()
+            K, Pz = Y.kinetic(rmax), Y.momentum_pz(rmax)
+            x, w1, w2 = g.clone(), torch.empty_like(g), torch.empty_like(g)
+            return timed(lambda: step3d_velocity(Y, plan, x, v0, K, Pz, 0.1, 0.01, w1, w2), steps)
         out = {"workload": f"angular transform N_r={nr} N_theta={nt} N_phi={nphi} ({nt * nphi} channels, "
                            f"l <= {nt - 1 + (nphi - 1) // 2}), complex64",
                "ms_forward": timed(lambda: Y.forward(g, c), steps),
                "ms_inverse": timed(lambda: Y.inverse(c, g), steps),
                "ms_B_Y_psi": timed(lambda: plan.forward(Y.forward(g, c), b), steps),
                "ms_step3d": step3d_ms(),
+               "ms_step3d_velocity": step3d_velocity_ms(),
                "flops_per_direction": 8 * nt * nphi * nphi * nr + 4 * nphi * nt * nt * nr,
                "bytes_per_direction": 4 * Y.size * 8}
         print(json.dumps(out))
