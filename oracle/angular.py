@@ -13,20 +13,28 @@ sqrt(w_j dphi).  Y is the product of
   Pbar_l^m(eta_j) sqrt(w_j), l = |m| .. |m| + N_theta - 1, orthonormalised on the
   quadrature (in l order).
 
-The normalised Pbar_l^m are read from a library routine: Pbar_l^m(eta) =
-sqrt(2 pi) Y_l^m(arccos eta, 0) (Condon-Shortley phase, so Pbar_l^{-m} =
-(-1)^m Pbar_l^m).  Coefficient layout: [m index q][l index t][radial i] with
-m = q - M and l = |m| + t; grid layout [j][k][i] with eta ascending.
+Pbar_l^m(eta) is (1 - eta^2)^{|m|/2} times a polynomial of degree l - |m| whose
+leading coefficient has the sign (-1)^m for m > 0 and + for m <= 0 (Condon-
+Shortley phase, Pbar_l^{-m} = (-1)^m Pbar_l^m).  So the first t + 1 functions
+on the nodes span {sqrt(W_j) p(eta_j): deg p <= t}, W_j = w_j (1 - eta_j^2)^|m|,
+and their orthonormalisation in order is sqrt(W) times the orthonormal
+polynomials of the discrete weights W, with that sign.  p_tables builds them
+by the Lanczos recurrence on the weighted nodes (multiply by eta, subtract the
+projections twice, normalise), which is accurate where Gram-Schmidt on the
+sampled Pbar loses digits (for large |m| those vectors are nearly dependent);
+p_tables_exact does the same Gram-Schmidt in exact rationals, for the pins.
+Coefficient layout: [m index q][l index t][radial i] with m = q - M and
+l = |m| + t; grid layout [j][k][i] with eta ascending.
 """
 from __future__ import annotations
 
 import functools
 import math
+from fractions import Fraction
 
 import numpy as np
-from scipy import special
 
-__all__ = ["grid", "m_values", "p_tables", "phi_matrix", "forward", "inverse", "dense_matrix"]
+__all__ = ["grid", "m_values", "p_tables", "p_tables_exact", "phi_matrix", "forward", "inverse", "dense_matrix"]
 
 
 def grid(n_theta: int, n_phi: int):
@@ -43,27 +51,51 @@ def m_values(n_phi: int) -> np.ndarray:
     return np.arange(-M, M + 1)
 
 
-def _gram_schmidt_rows(V: np.ndarray) -> np.ndarray:
-    Q = np.array(V, dtype=np.float64)
-    for t in range(Q.shape[0]):
-        for s in range(t):
-            Q[t] -= np.dot(Q[s], Q[t]) * Q[s]
-        Q[t] /= np.linalg.norm(Q[t])
-    return Q
+def _sign(m: int) -> int:
+    return (-1) ** m if m > 0 else 1
 
 
 @functools.lru_cache(maxsize=16)
 def p_tables(n_theta: int, n_phi: int) -> np.ndarray:
-    """P[q, t, j] = Pbar_{|m|+t}^m(eta_j) sqrt(w_j), rows orthonormalised in t."""
+    """P[q, t, j] = the orthonormalised Pbar_{|m|+t}^m(eta_j) sqrt(w_j) (Lanczos on the weighted nodes)."""
     eta, w, _ = grid(n_theta, n_phi)
-    theta = np.arccos(eta)
     out = np.zeros((n_phi, n_theta, n_theta))
     for q, m in enumerate(m_values(n_phi)):
-        V = np.zeros((n_theta, n_theta))
+        U = out[q]
+        sw = np.sqrt(w) * np.sqrt(1.0 - eta ** 2) ** abs(int(m))
+        U[0] = sw / np.linalg.norm(sw)
+        for t in range(1, n_theta):
+            v = eta * U[t - 1]
+            for _ in range(2):
+                v = v - U[:t].T @ (U[:t] @ v)
+            U[t] = v / np.linalg.norm(v)
+        U *= _sign(int(m))
+    return out
+
+
+def p_tables_exact(n_theta: int, n_phi: int, ms) -> dict:
+    """{m: block} by Gram-Schmidt of the monomials in exact rationals with the weights
+    W_j = w_j (1 - eta_j^2)^|m| (the FP64 nodes and weights taken as exact binary
+    fractions), evaluated in FP64 at the end.  Slow: small sizes only."""
+    eta, w, _ = grid(n_theta, n_phi)
+    E = [Fraction(float(x)) for x in eta]
+    out = {}
+    for m in ms:
+        W = [Fraction(float(wj)) * (1 - e * e) ** abs(m) for wj, e in zip(w, E)]
+        qs, norms = [], []
         for t in range(n_theta):
-            l = abs(int(m)) + t
-            V[t] = math.sqrt(2.0 * math.pi) * special.sph_harm_y(l, int(m), theta, 0.0).real * np.sqrt(w)
-        out[q] = _gram_schmidt_rows(V)
+            v = [e ** t for e in E]
+            for qv, nq in zip(qs, norms):
+                c = sum(Wj * a * b for Wj, a, b in zip(W, qv, v)) / nq
+                v = [a - c * b for a, b in zip(v, qv)]
+            qs.append(v)
+            norms.append(sum(Wj * a * a for Wj, a in zip(W, v)))
+        B = np.zeros((n_theta, n_theta))
+        for t in range(n_theta):
+            nrm = math.sqrt(float(norms[t]))
+            for j in range(n_theta):
+                B[t, j] = _sign(m) * math.sqrt(w[j]) * math.sqrt(1 - eta[j] ** 2) ** abs(m) * float(qs[t][j]) / nrm
+        out[m] = B
     return out
 
 

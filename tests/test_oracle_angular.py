@@ -47,3 +47,27 @@ def test_negative_m_is_the_condon_shortley_mirror():
     M = 4
     for m in range(1, M + 1):
         np.testing.assert_allclose(P[M - m], (-1) ** m * P[M + m], atol=1e-14)
+
+
+@pytest.mark.parametrize("nt,nphi,ms", [(8, 17, (8, -8, 3, 0)), (14, 27, (13, -13, 6, -1))])
+def test_blocks_match_exact_rational_orthonormalisation(nt, nphi, ms):
+    # the Lanczos blocks against Gram-Schmidt in exact rationals (same nodes and
+    # weights), including the largest |m|, where Gram-Schmidt on the sampled
+    # functions in FP64 loses up to 1e-5
+    P = angular.p_tables(nt, nphi)
+    M = (nphi - 1) // 2
+    for m, B in angular.p_tables_exact(nt, nphi, ms).items():
+        np.testing.assert_allclose(P[m + M], B, atol=1e-13)
+
+
+def test_low_blocks_are_the_library_functions():
+    # where the quadrature integrates the products exactly (l, l' <= N_theta - 1),
+    # the orthonormalised functions are the library's normalised Pbar_l^m
+    nt, nphi = 10, 9
+    eta, w, _ = angular.grid(nt, nphi)
+    P = angular.p_tables(nt, nphi)
+    for m in range(-4, 5):
+        for t in range(nt - abs(m)):
+            l = abs(m) + t
+            ref = math.sqrt(2 * math.pi) * special.sph_harm_y(l, m, np.arccos(eta), 0.0).real * np.sqrt(w)
+            np.testing.assert_allclose(P[m + 4, t], ref, atol=1e-13)
