@@ -239,15 +239,13 @@ dsbt_status dsbt_autotune(const dsbt_channel* ch, int32_t nch, const dsbt_plan_o
  * (l, m), m = -M..M, l = |m| .. |m| + N_theta - 1.  Phi is the unitary DFT
  * exp(-i m phi_k) / sqrt(N_phi) (the projection onto Y_lm); P, per m, holds
  * the associated Legendre functions Pbar_l^m(eta_j) sqrt(w_j) (unit norm on
- * [-1, 1], Condon-Shortley phase) orthonormalised on the quadrature in l order,
- * so Y is unitary.  Layouts (complex, interleaved, radius fastest):
+ * [-1, 1], Condon-Shortley phase) orthonormalised on the quadrature in l order
+ * (built as sqrt(w_j (1 - eta_j^2)^|m|) times the orthonormal polynomials of
+ * those weights, by a Lanczos recurrence), so Y is unitary.  Layouts (complex, interleaved, radius fastest):
  *   grid  psi[j][k][i]   (j < N_theta, k < N_phi, i < Nr)
  *   coef  c[q][t][i]     (m = q - M, l = |m| + t): channel q N_theta + t of a
  *                        DSBT plan with N = Nr, that l and offset (q N_theta + t) Nr.
- * 1 <= N_theta <= 64, N_phi odd in [1, 17] (else DSBT_ERR_UNSUPPORTED): for
- * |m| > 8 the orthonormalisation on the quadrature is too ill-conditioned in
- * FP64 to fix the blocks to FP32 accuracy (two FP64 constructions differ by
- * 7e-6 at N_theta = 16, |m| = 15). */
+ * 1 <= N_theta <= 64, N_phi odd in [1, 63] (else DSBT_ERR_UNSUPPORTED). */
 typedef struct dsbt_sht_s* dsbt_sht;   /* opaque; owns its tables and an Nr N_theta N_phi workspace */
 
 /* Host: nodes eta[N_theta], weights w[N_theta], azimuths phi[N_phi] (any may be NULL). */

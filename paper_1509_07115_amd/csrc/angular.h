@@ -15,15 +15,15 @@
 namespace dsbt {
 
 constexpr int kShtMaxQ = 64;   // largest N_theta and N_phi of the axis kernel
-constexpr int kShtMaxPhi = 17; // largest N_phi accepted (|m| <= 8)
+constexpr int kShtMaxPhi = 63; // largest N_phi accepted (|m| <= 31)
 
 // Records msg as the thread's last error (dsbt_last_error) and returns s.
 dsbt_status set_error(dsbt_status s, const char* msg);
 
 // FP64 host tables: Gauss-Legendre nodes (ascending) and weights, and
-// P[q][t][j] = Pbar_{|m|+t}^m(eta_j) sqrt(w_j) orthonormalised in t (modified
-// Gram-Schmidt over t in FP64), Pbar normalised to unit L2 norm on [-1, 1]
-// with the Condon-Shortley phase.
+// P[q][t][j] = Pbar_{|m|+t}^m(eta_j) sqrt(w_j) orthonormalised in t on the
+// quadrature (Pbar with unit L2 norm on [-1, 1], Condon-Shortley phase), built
+// by the Lanczos recurrence on the weighted nodes.
 void gauss_legendre(int n, std::vector<double>& eta, std::vector<double>& w);
 void sht_p_tables(int n_theta, int n_phi, std::vector<double>& P);
 

@@ -60,11 +60,8 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
 extern "C" {
 
 dsbt_status dsbt_sht_grid(int32_t n_theta, int32_t n_phi, double* eta, double* w, double* phi) {
-    // N_phi <= 17 (|m| <= 8): for larger |m| the orthonormalisation of the
-    // associated Legendre functions on the Gauss-Legendre nodes is too
-    // ill-conditioned in FP64 to define the blocks to FP32 accuracy
     if (n_theta < 1 || n_theta > dsbt::kShtMaxQ || n_phi < 1 || n_phi > dsbt::kShtMaxPhi || n_phi % 2 == 0)
-        return dsbt::set_error(DSBT_ERR_UNSUPPORTED, "need 1 <= N_theta <= 64 and odd 1 <= N_phi <= 17");
+        return dsbt::set_error(DSBT_ERR_UNSUPPORTED, "need 1 <= N_theta <= 64 and odd 1 <= N_phi <= 63");
     std::vector<double> e, ww;
     dsbt::gauss_legendre(n_theta, e, ww);
     for (int j = 0; j < n_theta; ++j) {

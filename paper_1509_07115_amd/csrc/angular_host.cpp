@@ -34,56 +34,46 @@ void gauss_legendre(int n, std::vector<double>& eta, std::vector<double>& w) {
     }
 }
 
-// Pbar_l^m(x) for l = m .. m + count - 1 (m >= 0), unit L2 norm on [-1, 1],
-// Condon-Shortley phase, by the recurrences in l for fixed m.
-static void assoc_legendre(int m, int count, double x, double* out) {
-    const double s = std::sqrt(std::fmax(0.0, 1.0 - x * x));
-    double pmm = std::sqrt(0.5);   // Pbar_0^0
-    for (int k = 1; k <= m; ++k) pmm *= -std::sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-    out[0] = pmm;
-    if (count == 1) return;
-    double pm1 = std::sqrt(2.0 * m + 3.0) * x * pmm;   // Pbar_{m+1}^m
-    out[1] = pm1;
-    double a2 = pmm, a1 = pm1;
-    for (int l = m + 2; l < m + count; ++l) {
-        const double al = std::sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
-        const double bl = std::sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
-        const double v = al * (x * a1 - bl * a2);
-        out[l - m] = v;
-        a2 = a1;
-        a1 = v;
-    }
-}
-
+// P[q] = the associated Legendre functions Pbar_{|m|+t}^m(eta_j) sqrt(w_j),
+// t < n_theta, orthonormalised in t on the quadrature.  Pbar_l^m is
+// (1 - eta^2)^{|m|/2} times a polynomial of degree l - |m| (leading coefficient
+// of sign (-1)^m for m > 0, + for m <= 0: Condon-Shortley phase), so the rows
+// are sqrt(W_j) times the orthonormal polynomials of the discrete weights
+// W_j = w_j (1 - eta_j^2)^|m|.  They are built by the Lanczos recurrence on the
+// weighted nodes (multiply by eta, remove the projections on the earlier rows
+// twice, normalise): for large |m| the sampled functions themselves are nearly
+// dependent and Gram-Schmidt on them loses digits, this form does not.
 void sht_p_tables(int n_theta, int n_phi, std::vector<double>& P) {
     std::vector<double> eta, w;
     gauss_legendre(n_theta, eta, w);
     const int M = (n_phi - 1) / 2;
     P.assign((size_t)n_phi * n_theta * n_theta, 0.0);
-    std::vector<double> col(n_theta);
+    std::vector<double> v(n_theta);
     for (int q = 0; q < n_phi; ++q) {
         const int m = q - M, am = m < 0 ? -m : m;
-        const double sgn = (m < 0 && (am & 1)) ? -1.0 : 1.0;   // Pbar_l^{-m} = (-1)^m Pbar_l^m
-        double* B = P.data() + (size_t)q * n_theta * n_theta;   // B[t][j]
+        double* U = P.data() + (size_t)q * n_theta * n_theta;   // U[t][j]
+        double nn = 0.0;
         for (int j = 0; j < n_theta; ++j) {
-            assoc_legendre(am, n_theta, eta[j], col.data());
-            const double sw = std::sqrt(w[j]);
-            for (int t = 0; t < n_theta; ++t) B[(size_t)t * n_theta + j] = sgn * col[t] * sw;
+            U[j] = std::sqrt(w[j]) * std::pow(std::sqrt(std::fmax(0.0, 1.0 - eta[j] * eta[j])), am);
+            nn += U[j] * U[j];
         }
-        // modified Gram-Schmidt over the rows t, in order
-        for (int t = 0; t < n_theta; ++t) {
-            double* rt = B + (size_t)t * n_theta;
-            for (int u = 0; u < t; ++u) {
-                const double* ru = B + (size_t)u * n_theta;
-                double d = 0.0;
-                for (int j = 0; j < n_theta; ++j) d += ru[j] * rt[j];
-                for (int j = 0; j < n_theta; ++j) rt[j] -= d * ru[j];
-            }
-            double nn = 0.0;
-            for (int j = 0; j < n_theta; ++j) nn += rt[j] * rt[j];
-            const double inv = 1.0 / std::sqrt(nn);
-            for (int j = 0; j < n_theta; ++j) rt[j] *= inv;
+        for (int j = 0; j < n_theta; ++j) U[j] /= std::sqrt(nn);
+        for (int t = 1; t < n_theta; ++t) {
+            for (int j = 0; j < n_theta; ++j) v[j] = eta[j] * U[(size_t)(t - 1) * n_theta + j];
+            for (int pass = 0; pass < 2; ++pass)
+                for (int u = 0; u < t; ++u) {
+                    const double* ru = U + (size_t)u * n_theta;
+                    double d = 0.0;
+                    for (int j = 0; j < n_theta; ++j) d += ru[j] * v[j];
+                    for (int j = 0; j < n_theta; ++j) v[j] -= d * ru[j];
+                }
+            double s2 = 0.0;
+            for (int j = 0; j < n_theta; ++j) s2 += v[j] * v[j];
+            const double inv = 1.0 / std::sqrt(s2);
+            for (int j = 0; j < n_theta; ++j) U[(size_t)t * n_theta + j] = v[j] * inv;
         }
+        if (m > 0 && (m & 1))
+            for (size_t e = 0; e < (size_t)n_theta * n_theta; ++e) U[e] = -U[e];
     }
 }
 
