@@ -18,10 +18,13 @@ template <> struct Cx<double> { typedef double2 t; };
 
 constexpr int kRows = kShtMaxQ / 4;   // output rows per thread
 
-// LDS bytes of one workgroup: 64 points x Q inputs, and the Q x Q matrix
+// LDS bytes of one workgroup: 64 points x Q4 inputs and the Q x Q4 matrix, Q4 =
+// Q rounded up to 4 (zero-padded), so that a wave reads four matrix columns as
+// one 16-byte (real) or two (complex) broadcasts
+__host__ __device__ constexpr int round4(int q) { return (q + 3) & ~3; }
 template <typename S, bool CA>
 constexpr size_t axis_lds_bytes(int Q) {
-    return sizeof(typename Cx<S>::t) * 64 * (size_t)Q + sizeof(S) * (CA ? 2 : 1) * (size_t)Q * Q;
+    return sizeof(typename Cx<S>::t) * 64 * (size_t)round4(Q) + sizeof(S) * (CA ? 2 : 1) * (size_t)Q * round4(Q);
 }
 
 template <typename S, bool CA>
@@ -30,44 +33,54 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
                                                   typename Cx<S>::t* __restrict__ dst, int64_t dout, int64_t dq,
                                                   int Q, int Nr) {
     using V = typename Cx<S>::t;
+    constexpr int AW = CA ? 2 : 1;   // scalars per matrix element
+    const int Q4 = round4(Q);
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    V* X = reinterpret_cast<V*>(lds_raw);                    // X[q * 64 + point]
-    S* A = reinterpret_cast<S*>(lds_raw + sizeof(V) * 64 * Q);   // A[(q' Q + q) (2 if complex)], untransposed
+    V* X = reinterpret_cast<V*>(lds_raw);                       // X[q * 64 + point], q < Q4
+    S* A = reinterpret_cast<S*>(lds_raw + sizeof(V) * 64 * Q4);  // A[(q' Q4 + q) AW], untransposed, q < Q4
     const int o = blockIdx.y;
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
     const bool live = i < Nr;
-    for (int q = r; q < Q; q += 4) X[q * 64 + (threadIdx.x & 63)] = live ? src[o * so + q * sq + i] : V{0, 0};
+    for (int q = r; q < Q4; q += 4)
+        X[q * 64 + (threadIdx.x & 63)] = (live && q < Q) ? src[o * so + q * sq + i] : V{0, 0};
     const S* Ag = mat + o * mso;
-    for (int e = threadIdx.x; e < Q * Q; e += 256) {
-        const int qo = e / Q, q = e - qo * Q;
-        const int64_t g = tr ? (int64_t)q * Q + qo : (int64_t)e;
+    for (int e = threadIdx.x; e < Q * Q4; e += 256) {
+        const int qo = e / Q4, q = e - qo * Q4;
+        const int64_t g = tr ? (int64_t)q * Q + qo : (int64_t)qo * Q + q;
         if constexpr (CA) {
-            A[2 * e] = Ag[2 * g];
-            A[2 * e + 1] = cj ? -Ag[2 * g + 1] : Ag[2 * g + 1];
+            A[2 * e] = q < Q ? Ag[2 * g] : S(0);
+            A[2 * e + 1] = q < Q ? (cj ? -Ag[2 * g + 1] : Ag[2 * g + 1]) : S(0);
         } else {
-            A[e] = Ag[g];
+            A[e] = q < Q ? Ag[g] : S(0);
         }
     }
     __syncthreads();
     V acc[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) acc[u] = V{0, 0};
-    for (int q = 0; q < Q; ++q) {
-        const V x = X[q * 64 + (threadIdx.x & 63)];
+    for (int q = 0; q < Q4; q += 4) {
+        V x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = X[(q + c) * 64 + (threadIdx.x & 63)];
 #pragma unroll
         for (int u = 0; u < kRows; ++u) {
             const int qo = r + 4 * u;
             if (qo < Q) {
-                const int e = qo * Q + q;
+                const S* a = A + ((size_t)qo * Q4 + q) * AW;
                 if constexpr (CA) {
-                    const S ar = A[2 * e], ai = A[2 * e + 1];
-                    acc[u].x += ar * x.x - ai * x.y;
-                    acc[u].y += ar * x.y + ai * x.x;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const S ar = a[2 * c], ai = a[2 * c + 1];
+                        acc[u].x += ar * x[c].x - ai * x[c].y;
+                        acc[u].y += ar * x[c].y + ai * x[c].x;
+                    }
                 } else {
-                    const S a = A[e];
-                    acc[u].x += a * x.x;
-                    acc[u].y += a * x.y;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        acc[u].x += a[c] * x[c].x;
+                        acc[u].y += a[c] * x[c].y;
+                    }
                 }
             }
         }
