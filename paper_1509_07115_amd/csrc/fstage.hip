@@ -201,6 +201,12 @@ __device__ __forceinline__ double2 phase_factor<double2>(const FChan& c, int i, 
 
 constexpr int fstage_threads(int N) { return N / 8 >= 256 ? N / 8 : 256; }
 
+// Two consecutive complex values of the data precision as one vector access
+// (8-byte aligned for complex64: channel offsets may be odd).
+template <typename S> struct Pair;
+template <> struct Pair<float> { typedef float t __attribute__((ext_vector_type(4), aligned(8))); };
+template <> struct Pair<double> { typedef double t __attribute__((ext_vector_type(4), aligned(16))); };
+
 // Complex value conversion between the storage and the arithmetic precision.
 template <typename V, typename W> __device__ __forceinline__ V to_prec(W w) {
     return {(decltype(V{}.x))w.x, (decltype(V{}.x))w.y};
@@ -229,14 +235,20 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     const Split<T> sc0 = split_const<T>(INV ? d0 : 0.5 * d0), sc1 = split_const<T>(INV ? d1 : 0.5 * d1);
     if constexpr (!INV) {
         if (live) {
+            // pairs x_{2j}, x_{2j+1} (one 16-byte load) go to v_j and v_{N-1-j}
             const SV* x = src + c.off;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = t + u * TPC;
-                V a = to_prec<V>(x[i]);
-                if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
-                if (c.p && (i & 1)) a = {-a.x, -a.y};
-                buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))] = a;
+            for (int u = 0; u < 4; ++u) {
+                const int j = t + u * TPC;
+                const typename Pair<S>::t w = *reinterpret_cast<const typename Pair<S>::t*>(x + 2 * j);
+                V a = to_prec<V>(SV{w[0], w[1]}), b = to_prec<V>(SV{w[2], w[3]});
+                if (ph.use) {
+                    a = f_mul(a, phase_factor<V>(c, 2 * j, ph));
+                    b = f_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                }
+                if (c.p) b = {-b.x, -b.y};
+                buf[pidx(j)] = a;
+                buf[pidx(N - 1 - j)] = b;
             }
         }
         lds_barrier();
@@ -283,14 +295,19 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         lds_barrier();
         fft_n<T, N>(buf, tw, t);
         if (live) {
+            // v_j and v_{N-1-j} go out as the pair x_{2j}, x_{2j+1} (one 16-byte store)
             SV* x = dst + c.off;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = t + u * TPC;
-                V a = buf[pidx((i & 1) ? (N - 1 - (i >> 1)) : (i >> 1))];
-                if (c.p && (i & 1)) a = {-a.x, -a.y};
-                if (ph.use) a = f_mul(a, phase_factor<V>(c, i, ph));
-                x[i] = to_prec<SV>(a);
+            for (int u = 0; u < 4; ++u) {
+                const int j = t + u * TPC;
+                V a = buf[pidx(j)], b = buf[pidx(N - 1 - j)];
+                if (c.p) b = {-b.x, -b.y};
+                if (ph.use) {
+                    a = f_mul(a, phase_factor<V>(c, 2 * j, ph));
+                    b = f_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                }
+                const SV sa = to_prec<SV>(a), sb = to_prec<SV>(b);
+                *reinterpret_cast<typename Pair<S>::t*>(x + 2 * j) = typename Pair<S>::t{sa.x, sa.y, sb.x, sb.y};
             }
         }
     }
