@@ -254,26 +254,42 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         lds_barrier();
         fft_n<T, N>(buf, tw, t);
         if (live) {
+            // X_k for k = 2m, 2m + 1, stored as one 16-byte pair (reversed for the sine form)
             SV* y = dst + c.off;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = t + u * TPC;
-                const V w = post[k];
-                const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
-                // w a + conj(w) b
-                V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
-                X = f_scale(X, k == 0 ? sc0 : sc1);
-                y[c.p ? (N - 1 - k) : k] = to_prec<SV>(X);
+            for (int u = 0; u < 4; ++u) {
+                const int m = t + u * TPC;
+                SV o[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int k = 2 * m + e;
+                    const V w = post[k];
+                    const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
+                    // w a + conj(w) b
+                    V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
+                    o[e] = to_prec<SV>(f_scale(X, k == 0 ? sc0 : sc1));
+                }
+                if (c.p)
+                    *reinterpret_cast<typename Pair<S>::t*>(y + (N - 2 - 2 * m)) =
+                        typename Pair<S>::t{o[1].x, o[1].y, o[0].x, o[0].y};
+                else
+                    *reinterpret_cast<typename Pair<S>::t*>(y + 2 * m) = typename Pair<S>::t{o[0].x, o[0].y, o[1].x, o[1].y};
             }
         }
     } else {
         if (live) {
+            // slots j = 2m, 2m + 1 loaded as one 16-byte pair
             const SV* f = src + c.off;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = t + u * TPC;
-                const int k = c.p ? (N - 1 - j) : j;
-                buf[pidx(k)] = f_scale(to_prec<V>(f[j]), k == 0 ? sc0 : sc1);
+            for (int u = 0; u < 4; ++u) {
+                const int m = t + u * TPC;
+                const typename Pair<S>::t v = *reinterpret_cast<const typename Pair<S>::t*>(f + 2 * m);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int j = 2 * m + e;
+                    const int k = c.p ? (N - 1 - j) : j;
+                    buf[pidx(k)] = f_scale(to_prec<V>(SV{v[2 * e], v[2 * e + 1]}), k == 0 ? sc0 : sc1);
+                }
             }
         }
         lds_barrier();
