@@ -1,0 +1,73 @@
+"""Every call enqueues on the stream it is given: results on a side stream are
+bitwise those of the default stream (the kernels are deterministic)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu(built_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def on_side(fn):
+    """Run fn(stream) on a fresh default-priority stream, ordered after the current one."""
+    side = torch.cuda.Stream()
+    cur = torch.cuda.current_stream()
+    side.wait_stream(cur)
+    with torch.cuda.stream(side):
+        out = fn(side)
+    cur.wait_stream(side)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_transforms_steps_and_state_kernels_on_a_side_stream():
+    from paper_1509_07115_amd import Plan, workloads
+    w = workloads.batched_all_m(seed=9, N=512, rmax=40.0, ells=[0, 5, 20, 40])
+    plan = Plan(w.channels)
+    x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+    ref_b = plan.forward(x)
+    ref_x = plan.inverse(ref_b)
+    b = on_side(lambda s: plan.forward(x, stream=s))
+    back = on_side(lambda s: plan.inverse(b, stream=s))
+    assert torch.equal(b, ref_b) and torch.equal(back, ref_x)
+    V = np.zeros(plan.elems)
+    plan.set_potential(V - 0.1, 0.01)
+    y0, y1 = x.clone(), x.clone()
+    plan.kinetic_step(y0, 7, graph=True)
+    on_side(lambda s: plan.kinetic_step(y1, 7, graph=True, stream=s))
+    assert torch.equal(y0, y1)
+    e0 = plan.energy(x)
+    e1 = on_side(lambda s: plan.energy(x, stream=s))
+    assert torch.equal(e0, e1)
+    sets = [0, 1, 12, len(w.channels)]
+    z0, z1 = x.clone(), x.clone()
+    plan.orthonormalize(z0, sets)
+    on_side(lambda s: plan.orthonormalize(z1, sets, stream=s))
+    assert torch.equal(z0, z1)
+
+
+def test_angular_transform_and_3d_step_on_a_side_stream():
+    from paper_1509_07115_amd import AngularTransform, Plan, step3d
+    nr, nt, nphi, rmax = 64, 6, 7, 12.8
+    Y = AngularTransform(nr, nt, nphi)
+    plan = Plan(Y.channels(rmax))
+    plan.set_potential(np.zeros(plan.elems), 0.02)
+    g = torch.randn(Y.size, dtype=torch.complex64, device="cuda")
+    c0 = Y.forward(g)
+    c1 = on_side(lambda s: Y.forward(g, stream=s))
+    assert torch.equal(c0, c1)
+    v0 = torch.rand(Y.size, dtype=torch.float64, device="cuda")
+    v1 = torch.rand(Y.size, dtype=torch.float64, device="cuda")
+    a, b = g.clone(), g.clone()
+    for k in range(3):
+        step3d(Y, plan, a, v0, v1, math.cos(k), 0.02)
+    on_side(lambda s: [step3d(Y, plan, b, v0, v1, math.cos(k), 0.02, stream=s) for k in range(3)])
+    assert torch.equal(a, b)
