@@ -277,6 +277,22 @@ dsbt_status dsbt_sht_potential_phase(dsbt_sht s, void* grid, const double* V0, c
  * it (i^l).  src and dst must not overlap (DSBT_ERR_INVALID_ARG). */
 dsbt_status dsbt_sht_momentum_order(dsbt_sht s, const void* src, void* dst, int32_t inverse, void* stream);
 
+/* One 3D split step (Sec. 4.1) in place on a grid buffer, enqueued on `stream`.
+ * p: a plan over the transform's channels (channel q N_theta + t: N = Nr, l = |m| + t,
+ * offset (q N_theta + t) Nr) with the potential set to zero for this dt; work (and
+ * work1, work2): device buffers of the grid size, not aliasing grid.
+ * Coordinate gauge: grid <- exp(-i U dt/2) Y^H B^T exp(-i K dt) B Y exp(-i U dt/2) grid,
+ * U = V0 + F V1 (device FP64 grid arrays, either may be NULL).
+ * Velocity gauge (A along z): the printed sequence through the momentum grid,
+ * with K the kinetic energies per channel slot (device FP64, coefficient
+ * layout) and Pz = -2 k~_n eta_j on the momentum grid (device FP64), so that
+ * the A.P factor is exp(i A k~_n eta_j dt).  The first failing call's status
+ * is returned (later calls are not enqueued). */
+dsbt_status dsbt_step3d(dsbt_sht y, dsbt_plan p, void* grid, void* work, const double* V0, const double* V1, double F,
+                        double dt, void* stream);
+dsbt_status dsbt_step3d_velocity(dsbt_sht y, dsbt_plan p, void* grid, void* work1, void* work2, const double* V0,
+                                 const double* K, const double* Pz, double A, double dt, void* stream);
+
 /* Stage timing.  With profiling enabled, every stage launch made by
  * dsbt_forward, dsbt_inverse and dsbt_kinetic_step (outside graph capture) is
  * bracketed by HIP events recorded on the launch stream.  enable == 1 clears

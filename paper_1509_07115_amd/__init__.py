@@ -361,34 +361,41 @@ class AngularTransform:
             pass
 
 
+def _f64_ptr(v, n, name):
+    import torch
+    if v is None:
+        return None
+    if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64 and v.is_contiguous()
+            and v.numel() >= n):
+        raise TypeError(f"{name} must be a contiguous cuda float64 tensor of the grid size")
+    return ctypes.c_void_p(v.data_ptr())
+
+
 def step3d(Y: "AngularTransform", plan: "Plan", grid, V0, V1, F: float, dt: float, coef=None, stream=None):
-    """One 3D split step in the coordinate gauge (Sec. 4.1) in place on ``grid``:
+    """One 3D split step in the coordinate gauge (Sec. 4.1) in place on ``grid`` (``dsbt_step3d``):
     exp(-i U dt/2) Y^H B^T exp(-i K dt) B Y exp(-i U dt/2), U = V0 + F V1.  ``plan`` is a
     Plan over ``Y.channels(rmax)`` whose potential was set to zero with the same dt."""
-    coef = Y.forward(Y.potential_phase(grid, V0, V1, F, dt, stream), coef, stream)
-    plan.kinetic_step(coef, 1, stream=stream)
-    Y.inverse(coef, grid, stream)
-    return Y.potential_phase(grid, V0, V1, F, dt, stream)
+    import torch
+    coef = torch.empty_like(grid) if coef is None else coef
+    _lib.check(Y._lib.dsbt_step3d(Y._h, plan._h, Y._buf(grid, "grid"), Y._buf(coef, "coef"),
+                                  _f64_ptr(V0, Y.size, "V0"), _f64_ptr(V1, Y.size, "V1"), float(F), float(dt),
+                                  _stream_handle(stream)), "dsbt_step3d")
+    return grid
 
 
 def step3d_velocity(Y: "AngularTransform", plan: "Plan", grid, V0, K, Pz, A: float, dt: float, w1=None, w2=None,
                     stream=None):
-    """One 3D split step in the velocity gauge (Sec. 4.1, the printed sequence) in place on ``grid``:
-    exp(-i V0 dt/2), c = B Y psi, exp(-i K dt/2), Ytilde^H, exp(i A k~ eta dt), Ytilde,
-    exp(-i K dt/2), Y^H B^T, exp(-i V0 dt/2).  K = ``Y.kinetic(rmax)``, Pz = ``Y.momentum_pz(rmax)``,
-    ``plan`` a Plan over ``Y.channels(rmax)``; w1, w2: optional work buffers of Y's size."""
+    """One 3D split step in the velocity gauge (Sec. 4.1, the printed sequence) in place on ``grid``
+    (``dsbt_step3d_velocity``).  K = ``Y.kinetic(rmax)``, Pz = ``Y.momentum_pz(rmax)``, ``plan`` a Plan
+    over ``Y.channels(rmax)``; w1, w2: optional work buffers of Y's size."""
     import torch
     w1 = torch.empty_like(grid) if w1 is None else w1
     w2 = torch.empty_like(grid) if w2 is None else w2
-    Y.potential_phase(grid, V0, None, 0.0, dt, stream)
-    c = plan.forward(Y.forward(grid, w1, stream), w1, stream)
-    Y.potential_phase(c, K, None, 0.0, dt, stream)
-    Y.inverse(Y.momentum_order(c, w2, False, stream), w1, stream)       # plane-wave grid in w1
-    Y.potential_phase(w1, None, Pz, A, dt, stream)
-    Y.momentum_order(Y.forward(w1, w2, stream), w1, True, stream)
-    Y.potential_phase(w1, K, None, 0.0, dt, stream)
-    Y.inverse(plan.inverse(w1, w1, stream), grid, stream)
-    return Y.potential_phase(grid, V0, None, 0.0, dt, stream)
+    _lib.check(Y._lib.dsbt_step3d_velocity(Y._h, plan._h, Y._buf(grid, "grid"), Y._buf(w1, "w1"), Y._buf(w2, "w2"),
+                                           _f64_ptr(V0, Y.size, "V0"), _f64_ptr(K, Y.size, "K"),
+                                           _f64_ptr(Pz, Y.size, "Pz"), float(A), float(dt), _stream_handle(stream)),
+               "dsbt_step3d_velocity")
+    return grid
 
 
 def sht_grid(n_theta: int, n_phi: int):

@@ -30,7 +30,7 @@ EXPORTED = [
     "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
     "dsbt_kinetic_momenta", "dsbt_autotune", "dsbt_sht_grid", "dsbt_sht_host_tables", "dsbt_sht_create",
     "dsbt_sht_destroy", "dsbt_sht_forward", "dsbt_sht_inverse", "dsbt_sht_potential_phase",
-    "dsbt_sht_momentum_order",
+    "dsbt_sht_momentum_order", "dsbt_step3d", "dsbt_step3d_velocity",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -99,6 +99,8 @@ def load() -> ctypes.CDLL:
         "dsbt_sht_inverse": (i32, [P, P, P, P]),
         "dsbt_sht_potential_phase": (i32, [P, P, P, P, dbl, dbl, P]),
         "dsbt_sht_momentum_order": (i32, [P, P, P, i32, P]),
+        "dsbt_step3d": (i32, [P, P, P, P, P, P, dbl, dbl, P]),
+        "dsbt_step3d_velocity": (i32, [P, P, P, P, P, P, P, P, dbl, dbl, P]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),
         "dsbt_last_error": (ctypes.c_char_p, []),
     }

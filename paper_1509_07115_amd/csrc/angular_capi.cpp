@@ -173,4 +173,34 @@ dsbt_status dsbt_sht_momentum_order(dsbt_sht p, const void* src, void* dst, int3
     return DSBT_OK;
 }
 
+dsbt_status dsbt_step3d(dsbt_sht y, dsbt_plan p, void* grid, void* work, const double* V0, const double* V1, double F,
+                        double dt, void* stream) {
+    if (!y || !p || !grid || !work) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    dsbt_status st = dsbt_sht_potential_phase(y, grid, V0, V1, F, dt, stream);
+    if (st == DSBT_OK) st = dsbt_sht_forward(y, grid, work, stream);
+    if (st == DSBT_OK) st = dsbt_kinetic_step(p, work, 1, nullptr, 0, stream);
+    if (st == DSBT_OK) st = dsbt_sht_inverse(y, work, grid, stream);
+    if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, grid, V0, V1, F, dt, stream);
+    return st;
+}
+
+dsbt_status dsbt_step3d_velocity(dsbt_sht y, dsbt_plan p, void* grid, void* work1, void* work2, const double* V0,
+                                 const double* K, const double* Pz, double A, double dt, void* stream) {
+    if (!y || !p || !grid || !work1 || !work2 || !K || !Pz) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    dsbt_status st = dsbt_sht_potential_phase(y, grid, V0, nullptr, 0.0, dt, stream);
+    if (st == DSBT_OK) st = dsbt_sht_forward(y, grid, work1, stream);
+    if (st == DSBT_OK) st = dsbt_forward(p, work1, work1, stream);                       // c = B Y psi
+    if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, work1, K, nullptr, 0.0, dt, stream);   // exp(-i K dt/2)
+    if (st == DSBT_OK) st = dsbt_sht_momentum_order(y, work1, work2, 0, stream);
+    if (st == DSBT_OK) st = dsbt_sht_inverse(y, work2, work1, stream);                   // Ytilde^H: plane waves
+    if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, work1, nullptr, Pz, A, dt, stream);   // exp(i A k eta dt)
+    if (st == DSBT_OK) st = dsbt_sht_forward(y, work1, work2, stream);
+    if (st == DSBT_OK) st = dsbt_sht_momentum_order(y, work2, work1, 1, stream);
+    if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, work1, K, nullptr, 0.0, dt, stream);
+    if (st == DSBT_OK) st = dsbt_inverse(p, work1, work1, stream);
+    if (st == DSBT_OK) st = dsbt_sht_inverse(y, work1, grid, stream);
+    if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, grid, V0, nullptr, 0.0, dt, stream);
+    return st;
+}
+
 }  // extern "C"

@@ -71,3 +71,40 @@ def test_angular_transform_and_3d_step_on_a_side_stream():
         step3d(Y, plan, a, v0, v1, math.cos(k), 0.02)
     on_side(lambda s: [step3d(Y, plan, b, v0, v1, math.cos(k), 0.02, stream=s) for k in range(3)])
     assert torch.equal(a, b)
+
+
+def test_3d_steps_replay_from_a_captured_graph():
+    # dsbt_step3d / dsbt_step3d_velocity only enqueue kernels (no memsets, no host
+    # synchronisation), so a caller can capture them; replays with eager work in
+    # between must each match the eager steps
+    from paper_1509_07115_amd import AngularTransform, Plan, step3d, step3d_velocity
+    nr, nt, nphi, rmax, dt = 64, 6, 5, 12.8, 0.02
+    Y = AngularTransform(nr, nt, nphi)
+    plan = Plan(Y.channels(rmax))
+    plan.set_potential(np.zeros(plan.elems), dt)
+    v0 = torch.rand(Y.size, dtype=torch.float64, device="cuda")
+    v1 = torch.rand(Y.size, dtype=torch.float64, device="cuda")
+    K, Pz = Y.kinetic(rmax), Y.momentum_pz(rmax)
+    g = torch.randn(Y.size, dtype=torch.complex64, device="cuda")
+    static = g.clone()
+    w1, w2 = torch.empty_like(g), torch.empty_like(g)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm the library's one-time setup outside the capture
+        step3d(Y, plan, g.clone(), v0, v1, 0.3, dt, w1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        step3d(Y, plan, static, v0, v1, 0.3, dt, w1)
+        step3d_velocity(Y, plan, static, v0, K, Pz, -0.2, dt, w1, w2)
+    ref = g.clone()
+    for rep in range(3):
+        static.copy_(ref)
+        graph.replay()
+        eager = ref.clone()
+        step3d(Y, plan, eager, v0, v1, 0.3, dt, torch.empty_like(g))
+        step3d_velocity(Y, plan, eager, v0, K, Pz, -0.2, dt)
+        torch.cuda.synchronize()
+        assert torch.equal(static, eager), rep
+        ref = eager * (1.0 + rep)
