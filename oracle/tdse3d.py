@@ -15,11 +15,14 @@ step's scalar strength F.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import angular, dsbt, tdse
 
-__all__ = ["step3d", "expect_z", "grid_r_eta", "to_momentum_order", "from_momentum_order", "step3d_velocity"]
+__all__ = ["step3d", "expect_z", "grid_r_eta", "to_momentum_order", "from_momentum_order", "step3d_velocity",
+           "oscillator_exact"]
 
 
 def grid_r_eta(nr: int, rmax: float, nt: int, nphi: int):
@@ -92,3 +95,25 @@ def step3d_velocity(psi: np.ndarray, rmax: float, V0: np.ndarray, A: float, dt: 
             b = from_momentum_order(c[q, t] * (1j) ** ell, ell)
             c[q, t] = dsbt.inverse(half[ell] * b, ell)
     return pu * angular.inverse(c, nt, nphi)
+
+
+def oscillator_exact(nr: int, rmax: float, nt: int, nphi: int, t: float, omega: float, A0: float) -> np.ndarray:
+    """Grid values of the exact solution for U = r^2/2 - F(t) z, F = omega A0 cos(omega t),
+    from the ground state at t = 0 (Sec. 4.2): the ground state moved to the classical
+    point (z_c, p_c), times exp(i p_c (z - z_c) + i S(t) - 3 i t / 2), with S the classical
+    action integral of p_c^2/2 - z_c^2/2 + F z_c (library quadrature)."""
+    from scipy.integrate import quad
+    w1 = omega * A0 / (1.0 - omega ** 2)
+    zc_f = lambda s: w1 * (math.cos(omega * s) - math.cos(s))
+    pc_f = lambda s: w1 * (math.sin(s) - omega * math.sin(omega * s))
+    lag = lambda s: 0.5 * pc_f(s) ** 2 - 0.5 * zc_f(s) ** 2 + omega * A0 * math.cos(omega * s) * zc_f(s)
+    S = quad(lag, 0.0, t, epsabs=1e-14, epsrel=1e-13, limit=500)[0]
+    zc, pc = zc_f(t), pc_f(t)
+    dr = rmax / nr
+    r = dsbt.grid_r(nr, rmax)
+    eta, w, _ = angular.grid(nt, nphi)
+    z = r[None, None, :] * eta[:, None, None]
+    rho2 = r[None, None, :] ** 2 * (1 - eta[:, None, None] ** 2)
+    psi = math.pi ** -0.75 * np.exp(-rho2 / 2 - (z - zc) ** 2 / 2 + 1j * (pc * (z - zc) + S - 1.5 * t))
+    wts = r[None, None, :] * math.sqrt(dr) * np.sqrt(w * 2 * math.pi / nphi)[:, None, None]
+    return psi * wts * np.ones((1, nphi, 1))

@@ -70,7 +70,7 @@ def test_driven_oscillator_rmax_convergence():
     nt, nphi, dr, dt, omega, A0 = 16, 1, 0.2, 0.01, 2.0, 0.25
     t_end = 10.0
     zc = omega * A0 / (1 - omega ** 2) * (math.cos(omega * t_end) - math.cos(t_end))
-    errs = []
+    errs, deltas = [], []
     for rmax in (12.8, 25.6):
         nr = int(round(rmax / dr))
         V0, V1, r, eta = fields(nt, nphi, nr, rmax)
@@ -89,8 +89,13 @@ def test_driven_oscillator_rmax_convergence():
         errs.append(abs(tdse3d.expect_z(got, r, eta) / norm - zc))
         # complex64 data with FP32 arithmetic drifts about 1.5e-4 in norm per 1000 steps
         assert abs(norm - 1) < 5e-4
-    print(f"<z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}")
+        ex = tdse3d.oscillator_exact(nr, rmax, nt, nphi, t_end, omega, A0)
+        deltas.append(abs(1 - np.vdot(ex, got / math.sqrt(norm))))
+    print(f"<z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}; "
+          f"delta {deltas[0]:.2e}, {deltas[1]:.2e}")
     assert errs[0] < 5e-3 and errs[1] < 1.5e-3 and errs[0] / errs[1] > 3.0
+    # the measure of Sec. 4.2 against the exact solution (oracle: 2.6e-3, 6.8e-4)
+    assert deltas[0] < 4e-3 and deltas[1] < 1.2e-3 and deltas[0] / deltas[1] > 3.0
 
 
 @pytest.mark.parametrize("precision,tol", [("c128", 1e-10), ("c64", 5e-5)])
