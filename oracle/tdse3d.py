@@ -15,6 +15,7 @@ step's scalar strength F.
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -31,6 +32,13 @@ def grid_r_eta(nr: int, rmax: float, nt: int, nphi: int):
     return dsbt.grid_r(nr, rmax), eta
 
 
+@functools.lru_cache(maxsize=256)
+def _kinetic(nr: int, rmax: float, ell: int, corrected: bool) -> np.ndarray:
+    E = tdse.kinetic_energies(nr, rmax, ell, corrected)
+    E.setflags(write=False)
+    return E
+
+
 def step3d(psi: np.ndarray, rmax: float, V0: np.ndarray, V1: np.ndarray, F: float, dt: float,
            corrected: bool = False) -> np.ndarray:
     nt, nphi, nr = psi.shape
@@ -40,7 +48,7 @@ def step3d(psi: np.ndarray, rmax: float, V0: np.ndarray, V1: np.ndarray, F: floa
     for q in range(nphi):
         for t in range(nt):
             ell = abs(q - M) + t
-            E = tdse.kinetic_energies(nr, rmax, ell, corrected)
+            E = _kinetic(nr, rmax, ell, corrected)
             b = dsbt.forward(c[q, t], ell)
             c[q, t] = dsbt.inverse(np.exp(-1j * E * dt) * b, ell)
     return ph * angular.inverse(c, nt, nphi)
@@ -84,7 +92,7 @@ def step3d_velocity(psi: np.ndarray, rmax: float, V0: np.ndarray, A: float, dt: 
     for q in range(nphi):
         for t in range(nt):
             ell = ls[q][t]
-            half[ell] = np.exp(-1j * tdse.kinetic_energies(nr, rmax, ell, corrected) * dt / 2.0)
+            half[ell] = np.exp(-1j * _kinetic(nr, rmax, ell, corrected) * dt / 2.0)
             c[q, t] = to_momentum_order(half[ell] * dsbt.forward(c[q, t], ell), ell) * (1j) ** (-ell)
     phi = angular.inverse(c, nt, nphi)                                 # Ytilde^H on the momentum grid
     phi *= np.exp(1j * A * ktil[None, None, :] * eta[:, None, None] * dt)

@@ -154,3 +154,28 @@ def test_driven_oscillator_velocity_gauge():
         assert abs(norm - 1) < 5e-4
     print(f"velocity gauge <z> error at t = 10: rmax 12.8 {errs[0]:.2e}, rmax 25.6 {errs[1]:.2e}")
     assert errs[0] < 6e-3 and errs[1] < 1.5e-3 and errs[0] / errs[1] > 3.0
+
+
+def test_driven_oscillator_corrected_momenta():
+    # the momenta of eq. kcorr on the GPU: delta(t = 10) about 5x below the plain
+    # momenta (oracle: 2.6e-3 -> 4.8e-4 at rmax = 12.8)
+    from paper_1509_07115_amd import step3d
+    nt, nphi, dr, dt, omega, A0, rmax = 16, 1, 0.2, 0.01, 2.0, 0.25, 12.8
+    nr = int(round(rmax / dr))
+    V0, V1, r, eta = fields(nt, nphi, nr, rmax)
+    _, w, _ = angular.grid(nt, nphi)
+    radial = math.pi ** -0.75 * np.exp(-r ** 2 / 2) * r * math.sqrt(dr)
+    psi = radial[None, None, :] * np.sqrt(w * 2 * math.pi)[:, None, None] * np.ones((nt, nphi, 1))
+    ex = tdse3d.oscillator_exact(nr, rmax, nt, nphi, 10.0, omega, A0)
+    deltas = []
+    for kinetic in ("plain", "corrected"):
+        Y, plan = setup(nt, nphi, nr, rmax, "c64", kinetic)
+        plan.set_potential(np.zeros(plan.elems), dt)
+        g = torch.from_numpy(psi.reshape(-1)).to(torch.complex64).cuda()
+        v0, v1, coef = d64(V0), d64(V1), torch.empty_like(g)
+        for s in range(1000):
+            step3d(Y, plan, g, v0, v1, omega * A0 * math.cos(omega * (s + 0.5) * dt), dt, coef)
+        got = g.cpu().numpy().astype(np.complex128).reshape(nt, nphi, nr)
+        deltas.append(abs(1 - np.vdot(ex, got / np.linalg.norm(got))))
+    print(f"delta plain {deltas[0]:.2e}, corrected {deltas[1]:.2e}")
+    assert deltas[1] < deltas[0] / 3.5 and deltas[1] < 1e-3
