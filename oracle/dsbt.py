@@ -17,7 +17,7 @@ Everything here is the plain definition written out as dense matrices:
 
 There is no FFT, no fast algorithm and no tiling: a reader can hold each
 function against the paper.  Readings of passages that are garbled or silent
-(all listed in DESIGN.md under "Readings of the paper"):
+(numbered as in the library's design notes):
 
 R1  F is orthonormal: scale sqrt((2 - delta_{n0})/N), and sqrt(1/N) for the
     n = N sine row of even l (the printed 1/sqrt((2-delta)N) is not orthonormal).
