@@ -239,7 +239,7 @@ def main():
                          "complex64) forward and inverse, and B Y psi with the radial transform")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU per process; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
