@@ -93,6 +93,89 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
     }
 }
 
+// Real-matrix axis step (the per-m Legendre blocks) on the matrix cores.  The
+// real matrix acts on the real and imaginary parts alike, so one workgroup's 64
+// complex points are 128 real columns of a (Q16 x Q16) x (Q16 x 128) FP32
+// product, Q16 = 16 NR >= Q.  The inputs are staged transposed in LDS
+// (Xt[column][q], row pitch Q16 + 4 floats, so that the 16-byte reads of
+// 16 lanes cover all 64 banks once); wave w takes columns 32 w .. 32 w + 31
+// and every row block.  v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16], result register v of lane l is D[4 (l/16) + v][l%16].
+// The contraction index is split as q = 16 G + 4 (l/16) + s for instruction s
+// of group G, so that each lane reads the four q of its four instructions as
+// one 16-byte word, from the zero-padded matrix (row-major [o][Q16][Q16] in
+// global memory, L2-resident) and from Xt.  Results pass through LDS (over Xt,
+// row pitch 132 floats: conflict-free) and are written back coalesced.
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kYPitch = 132;
+
+template <int NR>
+__global__ void __launch_bounds__(256) axis_real_mfma(const float* __restrict__ mat16,
+                                                      const float2* __restrict__ src, int64_t so, int64_t sq,
+                                                      float2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
+                                                      int Nr) {
+    constexpr int Q16 = 16 * NR, XS = Q16 + 4;
+    static_assert(Q16 * kYPitch <= 128 * XS, "result staging must fit in the input buffer");
+    __shared__ __align__(16) float Xt[128 * XS];
+    const int o = blockIdx.y;
+    const int i0 = blockIdx.x * 64;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float2* sp = src + o * so + i0;
+    // stage: lane il of item (qg, il) gathers rows 4 qg .. 4 qg + 3 of point il
+    for (int e = threadIdx.x; e < 256 * NR; e += 256) {
+        const int il = e & 63, qg = e >> 6;
+        const bool live = i0 + il < Nr;
+        f4v re, im;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int q = 4 * qg + c;
+            const float2 v = (live && q < Q) ? sp[q * sq + il] : float2{0.f, 0.f};
+            re[c] = v.x;
+            im[c] = v.y;
+        }
+        *reinterpret_cast<f4v*>(Xt + (2 * il) * XS + 4 * qg) = re;
+        *reinterpret_cast<f4v*>(Xt + (2 * il + 1) * XS + 4 * qg) = im;
+    }
+    const float* Am = mat16 + (int64_t)o * Q16 * Q16 + (lane & 15) * Q16 + 4 * (lane >> 4);
+    f4v acc[NR][2];
+#pragma unroll
+    for (int rb = 0; rb < NR; ++rb) acc[rb][0] = acc[rb][1] = f4v{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+#pragma unroll
+    for (int G = 0; G < NR; ++G) {
+        f4v a[NR], b[2];
+#pragma unroll
+        for (int rb = 0; rb < NR; ++rb) a[rb] = *reinterpret_cast<const f4v*>(Am + 16 * rb * Q16 + 16 * G);
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+            b[cb] = *reinterpret_cast<const f4v*>(Xt + (32 * w + 16 * cb + (lane & 15)) * XS + 16 * G +
+                                                  4 * (lane >> 4));
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
+    }
+    __syncthreads();
+    float* Ys = Xt;   // Ys[t][column], pitch kYPitch
+#pragma unroll
+    for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Ys[(16 * rb + 4 * (lane >> 4) + v) * kYPitch + 32 * w + 16 * cb + (lane & 15)] = acc[rb][cb][v];
+    __syncthreads();
+    float2* dp = dst + o * dout + i0;
+    for (int e = threadIdx.x; e < Q * 64; e += 256) {
+        const int t = e >> 6, il = e & 63;
+        if (i0 + il < Nr) dp[t * dq + il] = *reinterpret_cast<const float2*>(Ys + t * kYPitch + 2 * il);
+    }
+}
+
 // x[i] *= exp(-i (V0[i] + F V1[i]) dt/2), the angle formed and reduced mod 2 pi
 // in FP64 (V0 or V1 may be null: zero)
 template <typename S>
@@ -172,6 +255,21 @@ hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const 
     const size_t lds = axis_lds_bytes<S, CA>(Q);
     hipLaunchKernelGGL((axis_apply<S, CA>), dim3((Nr + 63) / 64, nouter), dim3(256), lds, s, mat, mso, tr ? 1 : 0,
                        cj ? 1 : 0, (const V*)src, so, sq, (V*)dst, dout, dq, Q, Nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_axis_real_mfma(const float* mat16, const void* src, int64_t so, int64_t sq, void* dst,
+                                 int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
+    if (Q < 1 || Q > kShtMaxQ || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((Nr + 63) / 64), (unsigned)nouter);
+    const float2* x = static_cast<const float2*>(src);
+    float2* y = static_cast<float2*>(dst);
+    switch ((Q + 15) / 16) {
+        case 1: hipLaunchKernelGGL(axis_real_mfma<1>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 2: hipLaunchKernelGGL(axis_real_mfma<2>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 3: hipLaunchKernelGGL(axis_real_mfma<3>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+        default: hipLaunchKernelGGL(axis_real_mfma<4>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+    }
     return hipGetLastError();
 }
 

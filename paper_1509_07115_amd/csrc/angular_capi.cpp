@@ -4,6 +4,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dsbt.h"
@@ -14,11 +15,14 @@ struct dsbt_sht_s {
     void* d_phi = nullptr;   // Phi[q][k] complex (interleaved), precision of the data
     void* d_p = nullptr;     // P[q][t][j] real
     void* d_work = nullptr;  // a[j][q][i], complex
+    float* d_pm = nullptr;   // complex64 only: [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse)
     void release() {
         if (d_phi) (void)hipFree(d_phi);
         if (d_p) (void)hipFree(d_p);
         if (d_work) (void)hipFree(d_work);
+        if (d_pm) (void)hipFree(d_pm);
         d_phi = d_p = d_work = nullptr;
+        d_pm = nullptr;
     }
 };
 
@@ -38,17 +42,24 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
     const int64_t lf = (int64_t)nf * Nr, lt = (int64_t)nt * Nr;
     const S* F = static_cast<const S*>(p->d_phi);
     const S* P = static_cast<const S*>(p->d_p);
+    const int64_t q16 = (nt + 15) / 16 * 16;
+    // the per-m real blocks: matrix cores for complex64, the vector kernel for complex128
+    auto legendre = [&](bool tr, const void* x, int64_t so, int64_t sq, void* y, int64_t dout, int64_t dq) {
+        if constexpr (std::is_same<S, float>::value)
+            return dsbt::launch_axis_real_mfma(p->d_pm + (tr ? nf * q16 * q16 : 0), x, so, sq, y, dout, dq, nt, nf,
+                                               Nr, s);
+        else
+            return dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, tr, false, x, so, sq, y, dout, dq, nt, nf,
+                                                     Nr, s);
+    };
     hipError_t e;
     if (!inverse) {
         // a[j][q][i] = sum_k Phi[q][k] psi[j][k][i]; c[q][t][i] = sum_j P[q][t][j] a[j][q][i]
         e = dsbt::launch_axis_apply<S, true>(F, 0, false, false, src, lf, Nr, p->d_work, lf, Nr, nf, nt, Nr, s);
-        if (e == hipSuccess)
-            e = dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, false, false, p->d_work, Nr, lf, dst, lt, Nr,
-                                                  nt, nf, Nr, s);
+        if (e == hipSuccess) e = legendre(false, p->d_work, Nr, lf, dst, lt, Nr);
     } else {
         // a[j][q][i] = sum_t P[q][t][j] c[q][t][i]; psi[j][k][i] = sum_q conj(Phi[q][k]) a[j][q][i]
-        e = dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, true, false, src, lt, Nr, p->d_work, Nr, lf, nt,
-                                              nf, Nr, s);
+        e = legendre(true, src, lt, Nr, p->d_work, Nr, lf);
         if (e == hipSuccess)
             e = dsbt::launch_axis_apply<S, true>(F, 0, true, true, p->d_work, lf, Nr, dst, lf, Nr, nf, nt, Nr, s);
     }
@@ -115,6 +126,19 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
     if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(F, &p->d_phi) : upload<float>(F, &p->d_phi);
     if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(P, &p->d_p) : upload<float>(P, &p->d_p);
     if (e == hipSuccess) e = hipMalloc(&p->d_work, work);
+    if (e == hipSuccess && precision == DSBT_C64) {
+        const size_t q16 = (size_t)(n_theta + 15) / 16 * 16, blk = q16 * q16;
+        std::vector<float> pm(2 * n_phi * blk, 0.0f);
+        for (int q = 0; q < n_phi; ++q)
+            for (int t = 0; t < n_theta; ++t)
+                for (int j = 0; j < n_theta; ++j) {
+                    const float v = (float)P[((size_t)q * n_theta + t) * n_theta + j];
+                    pm[q * blk + t * q16 + j] = v;                     // forward: rows t, columns j
+                    pm[(n_phi + q) * blk + j * q16 + t] = v;           // inverse: rows j, columns t
+                }
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_pm), sizeof(float) * pm.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_pm, pm.data(), sizeof(float) * pm.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         p->release();
         delete p;
