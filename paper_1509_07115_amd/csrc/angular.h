@@ -37,12 +37,15 @@ template <typename S, bool CA>
 hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const void* src, int64_t so, int64_t sq,
                              void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);
 
-// The real-matrix case of launch_axis_apply for complex64 data on the matrix
-// cores: dst[o*dout + q'*dq + i] = sum_q A_o(q', q) src[o*so + q*sq + i] with
-// A_o(q', q) = mat16[(o*Q16 + q')*Q16 + q], Q16 = Q rounded up to 16, the
-// table zero outside q, q' < Q (16-byte aligned).
-hipError_t launch_axis_real_mfma(const float* mat16, const void* src, int64_t so, int64_t sq, void* dst,
-                                 int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);
+// launch_axis_apply for complex64 data on the matrix cores, the matrix given
+// as a real FP32 table mat16 + o*mso, row-major Q16 x Q16, zero outside the
+// used block, 16-byte aligned.  Real matrix (complex_matrix false):
+// A_o(q', q) = mat16[o*mso + q'*Q16 + q], Q16 = Q rounded up to 16.  Complex
+// matrix: row 2 q' + a, column 2 q + b hold [[Re, -Im], [Im, Re]][a][b] of
+// A_o(q', q), Q16 = 2 Q rounded up to 16.  Q16 <= 64, else hipErrorInvalidValue.
+hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso, const void* src, int64_t so,
+                            int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
+                            hipStream_t s);
 
 // x[i] *= exp(-i (V0[i] + F V1[i]) dt/2) for i < n (complex of S; V0, V1 FP64
 // device arrays or null), angles reduced mod 2 pi in FP64.

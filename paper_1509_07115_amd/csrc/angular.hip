@@ -6,6 +6,9 @@
 // matrix is staged in LDS beside them, and each of the four waves accumulates
 // every fourth output row for its 64 points, reading the matrix as LDS
 // broadcasts (one element per row and input, the same for the whole wave).
+#include <algorithm>
+#include <atomic>
+
 #include "angular.h"
 
 namespace dsbt {
@@ -93,86 +96,133 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
     }
 }
 
-// Real-matrix axis step (the per-m Legendre blocks) on the matrix cores.  The
-// real matrix acts on the real and imaginary parts alike, so one workgroup's 64
-// complex points are 128 real columns of a (Q16 x Q16) x (Q16 x 128) FP32
-// product, Q16 = 16 NR >= Q.  The inputs are staged transposed in LDS
-// (Xt[column][q], row pitch Q16 + 4 floats, so that the 16-byte reads of
-// 16 lanes cover all 64 banks once); wave w takes columns 32 w .. 32 w + 31
-// and every row block.  v_mfma_f32_16x16x4_f32: lane l supplies A[l%16][l/16]
-// and B[l/16][l%16], result register v of lane l is D[4 (l/16) + v][l%16].
-// The contraction index is split as q = 16 G + 4 (l/16) + s for instruction s
-// of group G, so that each lane reads the four q of its four instructions as
-// one 16-byte word, from the zero-padded matrix (row-major [o][Q16][Q16] in
-// global memory, L2-resident) and from Xt.  Results pass through LDS (over Xt,
-// row pitch 132 floats: conflict-free) and are written back coalesced.
+// Axis step on the matrix cores, complex64 data, as one real FP32 product
+// D = A X of (Q16 x Q16) x (Q16 x NCOL) per block of 64 radial points,
+// Q16 = 16 NR:
+//  * real matrix (the per-m Legendre blocks): it acts on real and imaginary
+//    parts alike, so the 64 points are NCOL = 128 real columns (2 i + part)
+//    and the contraction index is q;
+//  * complex matrix (the azimuthal DFT): the contraction index is k = 2 q + part
+//    and the output row 2 q' + part', with A = [[Re, -Im], [Im, Re]] per element,
+//    so the 64 points are NCOL = 64 columns.
+// Workgroup (x, o) takes the point blocks x, x + gridDim.x, ... of outer index
+// o: its matrix fragments are loaded once into registers, and the inputs of the
+// next block are loaded into registers while the current one is multiplied and
+// stored, so that memory and matrix work overlap inside the workgroup.  The
+// inputs are staged transposed in LDS (Xt[column][k], row pitch Q16 + 4 floats,
+// so that the 16-byte reads of 16 lanes cover all 64 banks once); wave w takes
+// NCOL / 4 columns and every row block.  v_mfma_f32_16x16x4_f32: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16], result register v of lane l is
+// D[4 (l/16) + v][l%16].  The contraction index is split as
+// k = 16 G + 4 (l/16) + s for instruction s of group G, so that each lane holds
+// the four k of its four instructions as one 16-byte word, of the zero-padded
+// matrix (row-major [Q16][Q16] at mat16 + o mso in global memory) and of Xt.
+// Results pass through LDS (over Xt, row pitch NCOL + 4 floats: conflict-free)
+// and are written back coalesced.
 typedef float f4v __attribute__((ext_vector_type(4)));
-constexpr int kYPitch = 132;
 
-template <int NR>
-__global__ void __launch_bounds__(256) axis_real_mfma(const float* __restrict__ mat16,
-                                                      const float2* __restrict__ src, int64_t so, int64_t sq,
-                                                      float2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
-                                                      int Nr) {
+template <int NR, bool CPX>
+__global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16, int64_t mso,
+                                                 const float2* __restrict__ src, int64_t so, int64_t sq,
+                                                 float2* __restrict__ dst, int64_t dout, int64_t dq, int Q, int Nr) {
     constexpr int Q16 = 16 * NR, XS = Q16 + 4;
-    static_assert(Q16 * kYPitch <= 128 * XS, "result staging must fit in the input buffer");
-    __shared__ __align__(16) float Xt[128 * XS];
+    constexpr int NCOL = CPX ? 64 : 128, NCB = NCOL / 64, YP = NCOL + 4;
+    constexpr int NPF = CPX ? 2 : 4;   // input rows per staging item
+    static_assert(Q16 * YP <= NCOL * XS, "result staging must fit in the input buffer");
+    __shared__ __align__(16) float Xt[NCOL * XS];
     const int o = blockIdx.y;
-    const int i0 = blockIdx.x * 64;
+    const int nblk = (Nr + 63) / 64;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const float2* sp = src + o * so + i0;
-    // stage: lane il of item (qg, il) gathers rows 4 qg .. 4 qg + 3 of point il
-    for (int e = threadIdx.x; e < 256 * NR; e += 256) {
-        const int il = e & 63, qg = e >> 6;
-        const bool live = i0 + il < Nr;
-        f4v re, im;
+    const float2* sp = src + o * so;
+    float2* dp = dst + o * dout;
+    f4v a[NR][NR];   // [G][rb]
+    {
+        const float* Am = mat16 + o * mso + (lane & 15) * Q16 + 4 * (lane >> 4);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int q = 4 * qg + c;
-            const float2 v = (live && q < Q) ? sp[q * sq + il] : float2{0.f, 0.f};
-            re[c] = v.x;
-            im[c] = v.y;
+        for (int G = 0; G < NR; ++G)
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb) a[G][rb] = *reinterpret_cast<const f4v*>(Am + 16 * rb * Q16 + 16 * G);
+    }
+    // staging item (g, il) = threadIdx.x + 256 u holds the contraction indices
+    // 4 g .. 4 g + 3 of point il: input rows 2 g, 2 g + 1 (complex matrix) or
+    // 4 g .. 4 g + 3 (real matrix)
+    float2 pf[NR][NPF];
+    // Every lane loads from an address clamped into the rows and points that
+    // exist, with no branch, and the values outside are zeroed only when they
+    // are staged: a load under a branch, or a value selected right after its
+    // load, would be waited for at once, and the loads of the next block are
+    // meant to stay in flight while the current one is multiplied.  Past the
+    // last block every lane reads the same clamped element.
+    auto fetch = [&](int bx) {
+        const int ic = min(bx * 64 + (threadIdx.x & 63), Nr - 1);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int g = (threadIdx.x + 256 * u) >> 6;
+#pragma unroll
+            for (int c = 0; c < NPF; ++c) pf[u][c] = sp[min(NPF * g + c, Q - 1) * sq + ic];
         }
-        *reinterpret_cast<f4v*>(Xt + (2 * il) * XS + 4 * qg) = re;
-        *reinterpret_cast<f4v*>(Xt + (2 * il + 1) * XS + 4 * qg) = im;
-    }
-    const float* Am = mat16 + (int64_t)o * Q16 * Q16 + (lane & 15) * Q16 + 4 * (lane >> 4);
-    f4v acc[NR][2];
+    };
+    int bx = blockIdx.x;
+    fetch(bx);
+    for (; bx < nblk; bx += gridDim.x) {
+        const bool live = bx * 64 + (threadIdx.x & 63) < Nr;
 #pragma unroll
-    for (int rb = 0; rb < NR; ++rb) acc[rb][0] = acc[rb][1] = f4v{0.f, 0.f, 0.f, 0.f};
-    __syncthreads();
+        for (int u = 0; u < NR; ++u) {
+            const int e = threadIdx.x + 256 * u, il = e & 63, g = e >> 6;
+            float2 v[NPF];
 #pragma unroll
-    for (int G = 0; G < NR; ++G) {
-        f4v a[NR], b[2];
+            for (int c = 0; c < NPF; ++c) v[c] = (live && NPF * g + c < Q) ? pf[u][c] : float2{0.f, 0.f};
+            if constexpr (CPX) {
+                *reinterpret_cast<f4v*>(Xt + il * XS + 4 * g) = f4v{v[0].x, v[0].y, v[1].x, v[1].y};
+            } else {
+                *reinterpret_cast<f4v*>(Xt + (2 * il) * XS + 4 * g) = f4v{v[0].x, v[1].x, v[2].x, v[3].x};
+                *reinterpret_cast<f4v*>(Xt + (2 * il + 1) * XS + 4 * g) = f4v{v[0].y, v[1].y, v[2].y, v[3].y};
+            }
+        }
+        __syncthreads();
+        fetch(bx + gridDim.x);
+        f4v acc[NR][NCB];
 #pragma unroll
-        for (int rb = 0; rb < NR; ++rb) a[rb] = *reinterpret_cast<const f4v*>(Am + 16 * rb * Q16 + 16 * G);
+        for (int rb = 0; rb < NR; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-            b[cb] = *reinterpret_cast<const f4v*>(Xt + (32 * w + 16 * cb + (lane & 15)) * XS + 16 * G +
-                                                  4 * (lane >> 4));
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int G = 0; G < NR; ++G) {
+            f4v b[NCB];
 #pragma unroll
-            for (int rb = 0; rb < NR; ++rb)
+            for (int cb = 0; cb < NCB; ++cb)
+                b[cb] = *reinterpret_cast<const f4v*>(Xt + (16 * (NCB * w + cb) + (lane & 15)) * XS + 16 * G +
+                                                      4 * (lane >> 4));
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
-    }
-    __syncthreads();
-    float* Ys = Xt;   // Ys[t][column], pitch kYPitch
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int rb = 0; rb < NR; ++rb)
+                for (int rb = 0; rb < NR; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[rb][cb] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(a[G][rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
+        }
+        __syncthreads();
+        float* Ys = Xt;   // Ys[row][column], pitch YP
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Ys[(16 * rb + 4 * (lane >> 4) + v) * kYPitch + 32 * w + 16 * cb + (lane & 15)] = acc[rb][cb][v];
-    __syncthreads();
-    float2* dp = dst + o * dout + i0;
-    for (int e = threadIdx.x; e < Q * 64; e += 256) {
-        const int t = e >> 6, il = e & 63;
-        if (i0 + il < Nr) dp[t * dq + il] = *reinterpret_cast<const float2*>(Ys + t * kYPitch + 2 * il);
+        for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Ys[(16 * rb + 4 * (lane >> 4) + v) * YP + 16 * (NCB * w + cb) + (lane & 15)] = acc[rb][cb][v];
+        __syncthreads();
+        const int i0 = bx * 64;
+        for (int e = threadIdx.x; e < Q * 64; e += 256) {
+            const int t = e >> 6, il = e & 63;
+            if (i0 + il >= Nr) continue;
+            if constexpr (CPX)
+                dp[t * dq + i0 + il] = float2{Ys[(2 * t) * YP + il], Ys[(2 * t + 1) * YP + il]};
+            else
+                dp[t * dq + i0 + il] = *reinterpret_cast<const float2*>(Ys + t * YP + 2 * il);
+        }
+        __syncthreads();
     }
 }
 
@@ -258,22 +308,63 @@ hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const 
     return hipGetLastError();
 }
 
-hipError_t launch_axis_real_mfma(const float* mat16, const void* src, int64_t so, int64_t sq, void* dst,
-                                 int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
-    if (Q < 1 || Q > kShtMaxQ || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((Nr + 63) / 64), (unsigned)nouter);
+// Workgroups of axis_mfma<nr, CPX> resident on the device at once, queried on
+// the first call (set_lds_limits_axis makes that call before any launch, so
+// that no query falls inside a stream capture); -1 if the query fails.
+template <bool CPX>
+static int axis_mfma_fit(int nr) {
+    static std::atomic<int> fit[4] = {{0}, {0}, {0}, {0}};
+    if (nr < 1 || nr > 4) return -1;
+    int f = fit[nr - 1].load(std::memory_order_relaxed);
+    if (f > 0) return f;
+    const void* k = nr == 1   ? (const void*)axis_mfma<1, CPX>
+                    : nr == 2 ? (const void*)axis_mfma<2, CPX>
+                    : nr == 3 ? (const void*)axis_mfma<3, CPX>
+                              : (const void*)axis_mfma<4, CPX>;
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 256, 0) != hipSuccess)
+        return -1;
+    f = std::max(1, occ) * std::max(1, ncu);
+    fit[nr - 1].store(f, std::memory_order_relaxed);
+    return f;
+}
+
+template <bool CPX>
+static hipError_t launch_axis_mfma_t(const float* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
+                                     void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
+    const int nr = ((CPX ? 2 * Q : Q) + 15) / 16;
+    if (Q < 1 || nr > 4 || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
+    const int fit0 = axis_mfma_fit<CPX>(nr);
+    if (fit0 < 0) return hipErrorInvalidValue;
+    const int nblk = (Nr + 63) / 64;
+    // as many workgroups as fit on the device at once (at least one per outer
+    // index), each taking an equal share of the point blocks of its outer index
+    const int fit = std::max(1, std::min(nblk, fit0 / nouter));
+    const int per = (nblk + fit - 1) / fit;
+    const dim3 grid((unsigned)((nblk + per - 1) / per), (unsigned)nouter);
     const float2* x = static_cast<const float2*>(src);
     float2* y = static_cast<float2*>(dst);
-    switch ((Q + 15) / 16) {
-        case 1: hipLaunchKernelGGL(axis_real_mfma<1>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
-        case 2: hipLaunchKernelGGL(axis_real_mfma<2>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
-        case 3: hipLaunchKernelGGL(axis_real_mfma<3>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
-        default: hipLaunchKernelGGL(axis_real_mfma<4>, grid, dim3(256), 0, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+    switch (nr) {
+        case 1: hipLaunchKernelGGL((axis_mfma<1, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 2: hipLaunchKernelGGL((axis_mfma<2, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 3: hipLaunchKernelGGL((axis_mfma<3, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        default: hipLaunchKernelGGL((axis_mfma<4, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso, const void* src, int64_t so,
+                            int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
+                            hipStream_t s) {
+    return complex_matrix ? launch_axis_mfma_t<true>(mat16, mso, src, so, sq, dst, dout, dq, Q, nouter, Nr, s)
+                          : launch_axis_mfma_t<false>(mat16, mso, src, so, sq, dst, dout, dq, Q, nouter, Nr, s);
+}
+
 hipError_t set_lds_limits_axis() {
+    for (int nr = 1; nr <= 4; ++nr)
+        if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0) return hipErrorInvalidDeviceFunction;
     hipError_t e = hipFuncSetAttribute((const void*)axis_apply<float, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)axis_lds_bytes<float, true>(kShtMaxQ));

@@ -16,13 +16,15 @@ struct dsbt_sht_s {
     void* d_p = nullptr;     // P[q][t][j] real
     void* d_work = nullptr;  // a[j][q][i], complex
     float* d_pm = nullptr;   // complex64 only: [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse)
+    float* d_fm = nullptr;   // complex64, 2 N_phi <= 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded
     void release() {
         if (d_phi) (void)hipFree(d_phi);
         if (d_p) (void)hipFree(d_p);
         if (d_work) (void)hipFree(d_work);
         if (d_pm) (void)hipFree(d_pm);
+        if (d_fm) (void)hipFree(d_fm);
         d_phi = d_p = d_work = nullptr;
-        d_pm = nullptr;
+        d_pm = d_fm = nullptr;
     }
 };
 
@@ -43,25 +45,31 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
     const S* F = static_cast<const S*>(p->d_phi);
     const S* P = static_cast<const S*>(p->d_p);
     const int64_t q16 = (nt + 15) / 16 * 16;
-    // the per-m real blocks: matrix cores for complex64, the vector kernel for complex128
+    const int64_t f16 = (2 * nf + 15) / 16 * 16;
+    // matrix cores for complex64 (the DFT while 2 N_phi <= 64), the vector kernel otherwise
     auto legendre = [&](bool tr, const void* x, int64_t so, int64_t sq, void* y, int64_t dout, int64_t dq) {
         if constexpr (std::is_same<S, float>::value)
-            return dsbt::launch_axis_real_mfma(p->d_pm + (tr ? nf * q16 * q16 : 0), x, so, sq, y, dout, dq, nt, nf,
-                                               Nr, s);
+            return dsbt::launch_axis_mfma(false, p->d_pm + (tr ? nf * q16 * q16 : 0), q16 * q16, x, so, sq, y, dout,
+                                          dq, nt, nf, Nr, s);
         else
             return dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, tr, false, x, so, sq, y, dout, dq, nt, nf,
                                                      Nr, s);
     };
+    auto azimuth = [&](bool inv, const void* x, void* y) {
+        if (p->d_fm)
+            return dsbt::launch_axis_mfma(true, p->d_fm + (inv ? f16 * f16 : 0), 0, x, lf, Nr, y, lf, Nr, nf, nt, Nr,
+                                          s);
+        return dsbt::launch_axis_apply<S, true>(F, 0, inv, inv, x, lf, Nr, y, lf, Nr, nf, nt, Nr, s);
+    };
     hipError_t e;
     if (!inverse) {
         // a[j][q][i] = sum_k Phi[q][k] psi[j][k][i]; c[q][t][i] = sum_j P[q][t][j] a[j][q][i]
-        e = dsbt::launch_axis_apply<S, true>(F, 0, false, false, src, lf, Nr, p->d_work, lf, Nr, nf, nt, Nr, s);
+        e = azimuth(false, src, p->d_work);
         if (e == hipSuccess) e = legendre(false, p->d_work, Nr, lf, dst, lt, Nr);
     } else {
         // a[j][q][i] = sum_t P[q][t][j] c[q][t][i]; psi[j][k][i] = sum_q conj(Phi[q][k]) a[j][q][i]
         e = legendre(true, src, lt, Nr, p->d_work, Nr, lf);
-        if (e == hipSuccess)
-            e = dsbt::launch_axis_apply<S, true>(F, 0, true, true, p->d_work, lf, Nr, dst, lf, Nr, nf, nt, Nr, s);
+        if (e == hipSuccess) e = azimuth(true, p->d_work, dst);
     }
     return e;
 }
@@ -138,6 +146,27 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
                 }
         e = hipMalloc(reinterpret_cast<void**>(&p->d_pm), sizeof(float) * pm.size());
         if (e == hipSuccess) e = hipMemcpy(p->d_pm, pm.data(), sizeof(float) * pm.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && precision == DSBT_C64 && 2 * n_phi <= 64) {
+        // [[Re, -Im], [Im, Re]] per element: forward A(q, k) = Phi[q][k], inverse A(k, q) = conj(Phi[q][k])
+        const size_t f16 = (size_t)(2 * n_phi + 15) / 16 * 16, blk = f16 * f16;
+        std::vector<float> fm(2 * blk, 0.0f);
+        for (int q = 0; q < n_phi; ++q)
+            for (int k = 0; k < n_phi; ++k) {
+                const float re = (float)F[2 * ((size_t)q * n_phi + k)], im = (float)F[2 * ((size_t)q * n_phi + k) + 1];
+                float* f = fm.data() + 2 * q * f16 + 2 * k;       // forward: rows 2q + a, columns 2k + b
+                f[0] = re;
+                f[1] = -im;
+                f[f16] = im;
+                f[f16 + 1] = re;
+                float* g = fm.data() + blk + 2 * k * f16 + 2 * q;   // inverse: rows 2k + a, columns 2q + b
+                g[0] = re;
+                g[1] = im;
+                g[f16] = -im;
+                g[f16 + 1] = re;
+            }
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_fm), sizeof(float) * fm.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_fm, fm.data(), sizeof(float) * fm.size(), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         p->release();

@@ -23,8 +23,11 @@ def dev(x, dtype):
     return torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).to(dtype).cuda()
 
 
-# tolerances: FP32 arithmetic, or FP64
+# tolerances: FP32 arithmetic, or FP64.  The complex64 cases take every matrix-core
+# tile count (16, 32, 48, 64 rows) of both axis steps, and N_phi = 63 the vector
+# kernel of the azimuthal step (2 N_phi > 64).
 CASES = [(8, 9, 100, "c64", 2e-6), (16, 17, 256, "c64", 2e-6), (64, 63, 70, "c64", 2e-6), (1, 1, 64, "c64", 1e-6),
+         (33, 31, 130, "c64", 2e-6), (20, 5, 64, "c64", 2e-6),
          (8, 9, 100, "c128", 1e-12), (16, 31, 130, "c128", 1e-12), (64, 63, 65, "c128", 1e-12)]
 
 
