@@ -324,6 +324,20 @@ def main():
                "ms_step3d_velocity": step3d_velocity_ms(),
                "flops_per_direction": 8 * nt * nphi * nphi * nr + 4 * nphi * nt * nt * nr,
                "bytes_per_direction": 4 * Y.size * 8}
+        # the same grid in complex128 (vector kernels, FP64), and N_phi = 63, whose azimuthal DFT
+        # (2 N_phi > 64) takes the vector kernel in complex64 as well
+        Y2 = AngularTransform(nr, nt, nphi, "c128")
+        g2 = torch.randn(Y2.size, dtype=torch.complex128, device="cuda")
+        c2 = torch.empty_like(g2)
+        out["complex128"] = {"ms_forward": timed(lambda: Y2.forward(g2, c2), steps),
+                             "ms_inverse": timed(lambda: Y2.inverse(c2, g2), steps)}
+        del Y2, g2, c2
+        Y3 = AngularTransform(1024, nt, 63)
+        g3 = torch.randn(Y3.size, dtype=torch.complex64, device="cuda")
+        c3 = torch.empty_like(g3)
+        out["n_phi_63"] = {"workload": f"N_r=1024 N_theta={nt} N_phi=63, complex64",
+                           "ms_forward": timed(lambda: Y3.forward(g3, c3), steps),
+                           "ms_inverse": timed(lambda: Y3.inverse(c3, g3), steps)}
         print(json.dumps(out))
         return
 

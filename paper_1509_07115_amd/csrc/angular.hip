@@ -45,17 +45,43 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index (uniform)
     const bool live = i < Nr;
-    for (int q = r; q < Q4; q += 4)
-        X[q * 64 + (threadIdx.x & 63)] = (live && q < Q) ? src[o * so + q * sq + i] : V{0, 0};
-    const S* Ag = mat + o * mso;
-    for (int e = threadIdx.x; e < Q * Q4; e += 256) {
-        const int qo = e / Q4, q = e - qo * Q4;
-        const int64_t g = tr ? (int64_t)q * Q + qo : (int64_t)qo * Q + q;
-        if constexpr (CA) {
-            A[2 * e] = q < Q ? Ag[2 * g] : S(0);
-            A[2 * e + 1] = q < Q ? (cj ? -Ag[2 * g + 1] : Ag[2 * g + 1]) : S(0);
-        } else {
-            A[e] = q < Q ? Ag[g] : S(0);
+    // Staging: every lane issues its loads from addresses clamped into the rows,
+    // points and matrix elements that exist, with no branch, and zeroes the rest
+    // when it writes LDS; a load under a branch would be waited for inside it,
+    // one round trip after another.
+    {
+        const int ic = min(i, Nr - 1);
+        V xin[kShtMaxQ / 4];
+#pragma unroll
+        for (int u = 0; u < kShtMaxQ / 4; ++u) xin[u] = src[o * so + min(r + 4 * u, Q - 1) * sq + ic];
+        constexpr int kMatPerThread = kShtMaxQ * kShtMaxQ / 256;
+        const S* Ag = mat + o * mso;
+        S av[kMatPerThread][AW];
+#pragma unroll
+        for (int u = 0; u < kMatPerThread; ++u) {
+            const int e = min((int)threadIdx.x + 256 * u, Q * Q4 - 1);
+            const int qo = e / Q4, q = min(e - qo * Q4, Q - 1);
+            const int64_t g = tr ? (int64_t)q * Q + qo : (int64_t)qo * Q + q;
+#pragma unroll
+            for (int c = 0; c < AW; ++c) av[u][c] = Ag[AW * g + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kShtMaxQ / 4; ++u) {
+            const int q = r + 4 * u;
+            if (q < Q4) X[q * 64 + (threadIdx.x & 63)] = (live && q < Q) ? xin[u] : V{0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < kMatPerThread; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            if (e < Q * Q4) {
+                const int qo = e / Q4, q = e - qo * Q4;
+                if constexpr (CA) {
+                    A[2 * e] = q < Q ? av[u][0] : S(0);
+                    A[2 * e + 1] = q < Q ? (cj ? -av[u][1] : av[u][1]) : S(0);
+                } else {
+                    A[e] = q < Q ? av[u][0] : S(0);
+                }
+            }
         }
     }
     __syncthreads();
