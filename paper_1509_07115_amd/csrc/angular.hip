@@ -252,6 +252,106 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
     }
 }
 
+// The real-matrix axis step (the per-m Legendre blocks) for complex128 data on
+// the FP64 matrix cores: per block of 32 radial points, D = A X with A the
+// zero-padded Q16 x Q16 block (Q16 = 16 NR) and X the 64 real columns (2 i +
+// part), wave w taking columns 16 w .. 16 w + 15.  v_mfma_f64_16x16x4_f64 takes
+// the operands of the FP32 form (lane l: A[l%16][l/16], B[l/16][l%16]) and
+// returns row 4 v + l/16, column l%16 in result register v.  The contraction
+// index is split as k = 16 G + 4 (l/16) + s, so that each lane holds the four
+// k of its four instructions in 32 contiguous bytes of the matrix (registers,
+// loaded once) and of the transposed LDS copy Xt[column][k] (pitch Q16 + 2).
+// Workgroups loop over point blocks of one outer index with the next block's
+// loads issued, from clamped addresses with no branch, before the current one
+// is multiplied.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int NR>
+__global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict__ mat16, int64_t mso,
+                                                        const double2* __restrict__ src, int64_t so, int64_t sq,
+                                                        double2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
+                                                        int Nr) {
+    constexpr int Q16 = 16 * NR, XS = Q16 + 2, NCOL = 64, YP = NCOL + 2, PB = 32;
+    constexpr int NIT = Q16 * PB / 256;   // staging items per thread: (row, point)
+    static_assert(Q16 * YP <= NCOL * XS, "result staging must fit in the input buffer");
+    __shared__ __align__(16) double Xt[NCOL * XS];
+    const int o = blockIdx.y;
+    const int nblk = (Nr + PB - 1) / PB;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const double2* sp = src + o * so;
+    double2* dp = dst + o * dout;
+    d4v a[NR][NR];   // [G][rb]: A[16 rb + l%16][16 G + 4 (l/16) + s]
+    {
+        const double* Am = mat16 + o * mso + (lane & 15) * Q16 + 4 * (lane >> 4);
+#pragma unroll
+        for (int G = 0; G < NR; ++G)
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb) {
+                const double2 lo = *reinterpret_cast<const double2*>(Am + 16 * rb * Q16 + 16 * G);
+                const double2 hi = *reinterpret_cast<const double2*>(Am + 16 * rb * Q16 + 16 * G + 2);
+                a[G][rb] = d4v{lo.x, lo.y, hi.x, hi.y};
+            }
+#pragma unroll
+        for (int G = 0; G < NR; ++G)
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb) {
+                // two 16-byte halves: a 32-byte operand here drops the kernel's host stub
+                const d4v t = a[G][rb];
+                asm volatile("" ::"v"(t.lo), "v"(t.hi));
+            }
+    }
+    double2 pf[NIT];   // item e = threadIdx.x + 256 u: row e / PB, point e % PB
+    auto fetch = [&](int bx) {
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            pf[u] = sp[min(e / PB, Q - 1) * sq + min(bx * PB + e % PB, Nr - 1)];
+        }
+    };
+    int bx = blockIdx.x;
+    fetch(bx);
+    for (; bx < nblk; bx += gridDim.x) {
+        const int i0 = bx * PB;
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = threadIdx.x + 256 * u, q = e / PB, il = e % PB;
+            const double2 v = (q < Q && i0 + il < Nr) ? pf[u] : double2{0.0, 0.0};
+            Xt[(2 * il) * XS + q] = v.x;
+            Xt[(2 * il + 1) * XS + q] = v.y;
+        }
+        __syncthreads();
+        fetch(bx + gridDim.x);
+        d4v acc[NR];
+#pragma unroll
+        for (int rb = 0; rb < NR; ++rb) acc[rb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int G = 0; G < NR; ++G) {
+            const double* xb = Xt + (16 * w + (lane & 15)) * XS + 16 * G + 4 * (lane >> 4);
+            const double2 lo = *reinterpret_cast<const double2*>(xb);
+            const double2 hi = *reinterpret_cast<const double2*>(xb + 2);
+            const double b[4] = {lo.x, lo.y, hi.x, hi.y};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int rb = 0; rb < NR; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[G][rb][s], b[s], acc[rb], 0, 0, 0);
+        }
+        __syncthreads();
+        double* Ys = Xt;   // Ys[row][column], pitch YP
+#pragma unroll
+        for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ys[(16 * rb + 4 * v + (lane >> 4)) * YP + 16 * w + (lane & 15)] = acc[rb][v];
+        __syncthreads();
+        for (int e = threadIdx.x; e < Q * PB; e += 256) {
+            const int t = e / PB, il = e % PB;
+            if (i0 + il < Nr) dp[t * dq + i0 + il] = double2{Ys[t * YP + 2 * il], Ys[t * YP + 2 * il + 1]};
+        }
+        __syncthreads();
+    }
+}
+
 // x[i] *= exp(-i (V0[i] + F V1[i]) dt/2), the angle formed and reduced mod 2 pi
 // in FP64 (V0 or V1 may be null: zero)
 template <typename S>
@@ -381,6 +481,48 @@ static hipError_t launch_axis_mfma_t(const float* mat16, int64_t mso, const void
     return hipGetLastError();
 }
 
+// Workgroups of axis_real_mfma64<nr> resident on the device at once (queried
+// once, first from set_lds_limits_axis); -1 if the query fails.
+static int axis_real_mfma64_fit(int nr) {
+    static std::atomic<int> fit[4] = {{0}, {0}, {0}, {0}};
+    if (nr < 1 || nr > 4) return -1;
+    int f = fit[nr - 1].load(std::memory_order_relaxed);
+    if (f > 0) return f;
+    const void* k = nr == 1   ? (const void*)axis_real_mfma64<1>
+                    : nr == 2 ? (const void*)axis_real_mfma64<2>
+                    : nr == 3 ? (const void*)axis_real_mfma64<3>
+                              : (const void*)axis_real_mfma64<4>;
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 256, 0) != hipSuccess)
+        return -1;
+    f = std::max(1, occ) * std::max(1, ncu);
+    fit[nr - 1].store(f, std::memory_order_relaxed);
+    return f;
+}
+
+hipError_t launch_axis_real_mfma64(const double* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
+                                   void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
+    const int nr = (Q + 15) / 16;
+    if (Q < 1 || nr > 4 || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
+    const int fit0 = axis_real_mfma64_fit(nr);
+    if (fit0 < 0) return hipErrorInvalidValue;
+    const int nblk = (Nr + 31) / 32;
+    const int fit = std::max(1, std::min(nblk, fit0 / nouter));
+    const int per = (nblk + fit - 1) / fit;
+    const dim3 grid((unsigned)((nblk + per - 1) / per), (unsigned)nouter);
+    const double2* x = static_cast<const double2*>(src);
+    double2* y = static_cast<double2*>(dst);
+    switch (nr) {
+        case 1: hipLaunchKernelGGL(axis_real_mfma64<1>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 2: hipLaunchKernelGGL(axis_real_mfma64<2>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 3: hipLaunchKernelGGL(axis_real_mfma64<3>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        default: hipLaunchKernelGGL(axis_real_mfma64<4>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso, const void* src, int64_t so,
                             int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
                             hipStream_t s) {
@@ -390,7 +532,8 @@ hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso
 
 hipError_t set_lds_limits_axis() {
     for (int nr = 1; nr <= 4; ++nr)
-        if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0) return hipErrorInvalidDeviceFunction;
+        if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0 || axis_real_mfma64_fit(nr) < 0)
+            return hipErrorInvalidDeviceFunction;
     hipError_t e = hipFuncSetAttribute((const void*)axis_apply<float, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)axis_lds_bytes<float, true>(kShtMaxQ));

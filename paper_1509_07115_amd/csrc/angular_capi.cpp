@@ -13,17 +13,15 @@
 struct dsbt_sht_s {
     int Nr = 0, nt = 0, nphi = 0, precision = DSBT_C64;
     void* d_phi = nullptr;   // Phi[q][k] complex (interleaved), precision of the data
-    void* d_p = nullptr;     // P[q][t][j] real
     void* d_work = nullptr;  // a[j][q][i], complex
-    float* d_pm = nullptr;   // complex64 only: [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse)
+    void* d_pm = nullptr;    // [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse), data precision
     float* d_fm = nullptr;   // complex64, 2 N_phi <= 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded
     void release() {
         if (d_phi) (void)hipFree(d_phi);
-        if (d_p) (void)hipFree(d_p);
         if (d_work) (void)hipFree(d_work);
         if (d_pm) (void)hipFree(d_pm);
         if (d_fm) (void)hipFree(d_fm);
-        d_phi = d_p = d_work = nullptr;
+        d_phi = d_work = nullptr;
         d_pm = d_fm = nullptr;
     }
 };
@@ -43,17 +41,15 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
     const int nt = p->nt, nf = p->nphi, Nr = p->Nr;
     const int64_t lf = (int64_t)nf * Nr, lt = (int64_t)nt * Nr;
     const S* F = static_cast<const S*>(p->d_phi);
-    const S* P = static_cast<const S*>(p->d_p);
     const int64_t q16 = (nt + 15) / 16 * 16;
     const int64_t f16 = (2 * nf + 15) / 16 * 16;
     // matrix cores for complex64 (the DFT while 2 N_phi <= 64), the vector kernel otherwise
     auto legendre = [&](bool tr, const void* x, int64_t so, int64_t sq, void* y, int64_t dout, int64_t dq) {
+        const S* pm = static_cast<const S*>(p->d_pm) + (tr ? nf * q16 * q16 : 0);
         if constexpr (std::is_same<S, float>::value)
-            return dsbt::launch_axis_mfma(false, p->d_pm + (tr ? nf * q16 * q16 : 0), q16 * q16, x, so, sq, y, dout,
-                                          dq, nt, nf, Nr, s);
+            return dsbt::launch_axis_mfma(false, pm, q16 * q16, x, so, sq, y, dout, dq, nt, nf, Nr, s);
         else
-            return dsbt::launch_axis_apply<S, false>(P, (int64_t)nt * nt, tr, false, x, so, sq, y, dout, dq, nt, nf,
-                                                     Nr, s);
+            return dsbt::launch_axis_real_mfma64(pm, q16 * q16, x, so, sq, y, dout, dq, nt, nf, Nr, s);
     };
     auto azimuth = [&](bool inv, const void* x, void* y) {
         if (p->d_fm)
@@ -132,20 +128,18 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
     const size_t work = (size_t)n_theta * n_phi * Nr * (precision == DSBT_C128 ? 16 : 8);
     hipError_t e = dsbt::set_lds_limits_axis();
     if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(F, &p->d_phi) : upload<float>(F, &p->d_phi);
-    if (e == hipSuccess) e = precision == DSBT_C128 ? upload<double>(P, &p->d_p) : upload<float>(P, &p->d_p);
     if (e == hipSuccess) e = hipMalloc(&p->d_work, work);
-    if (e == hipSuccess && precision == DSBT_C64) {
+    if (e == hipSuccess) {
         const size_t q16 = (size_t)(n_theta + 15) / 16 * 16, blk = q16 * q16;
-        std::vector<float> pm(2 * n_phi * blk, 0.0f);
+        std::vector<double> pm(2 * n_phi * blk, 0.0);
         for (int q = 0; q < n_phi; ++q)
             for (int t = 0; t < n_theta; ++t)
                 for (int j = 0; j < n_theta; ++j) {
-                    const float v = (float)P[((size_t)q * n_theta + t) * n_theta + j];
+                    const double v = P[((size_t)q * n_theta + t) * n_theta + j];
                     pm[q * blk + t * q16 + j] = v;                     // forward: rows t, columns j
                     pm[(n_phi + q) * blk + j * q16 + t] = v;           // inverse: rows j, columns t
                 }
-        e = hipMalloc(reinterpret_cast<void**>(&p->d_pm), sizeof(float) * pm.size());
-        if (e == hipSuccess) e = hipMemcpy(p->d_pm, pm.data(), sizeof(float) * pm.size(), hipMemcpyHostToDevice);
+        e = precision == DSBT_C128 ? upload<double>(pm, &p->d_pm) : upload<float>(pm, &p->d_pm);
     }
     if (e == hipSuccess && precision == DSBT_C64 && 2 * n_phi <= 64) {
         // [[Re, -Im], [Im, Re]] per element: forward A(q, k) = Phi[q][k], inverse A(k, q) = conj(Phi[q][k])

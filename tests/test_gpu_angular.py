@@ -47,25 +47,27 @@ def test_forward_inverse_match_oracle(nt, nphi, nr, precision, tol):
     assert np.linalg.norm(got_i - refi) <= tol * np.linalg.norm(refi)
 
 
-@pytest.mark.parametrize("nt,nphi,nr", [(64, 17, 4096), (64, 63, 1024)])
-def test_timed_sizes_match_oracle(nt, nphi, nr):
-    """The complex64 sizes the angular timing runs: there each matrix-core
-    workgroup loops over several point blocks with its loads prefetched (3 and 4
-    blocks at 64 x 17 x 4096; 2 for the Legendre step at 64 x 63 x 1024), which
-    the small cases above do not reach.  Element by element against the oracle."""
+@pytest.mark.parametrize("nt,nphi,nr,precision,tol", [(64, 17, 4096, "c64", 2e-6), (64, 63, 1024, "c64", 2e-6),
+                                                      (64, 17, 4096, "c128", 1e-12)])
+def test_timed_sizes_match_oracle(nt, nphi, nr, precision, tol):
+    """The sizes the angular timing runs: there each matrix-core workgroup loops
+    over several point blocks with its loads prefetched (3 and 4 blocks at
+    64 x 17 x 4096 in complex64, 2 for the FP64 Legendre step; 2 for the
+    Legendre step at 64 x 63 x 1024), which the small cases above do not reach.
+    Element by element against the oracle."""
     from paper_1509_07115_amd import AngularTransform
     rng = np.random.default_rng(nr + nphi)
     psi = rng.standard_normal((nt, nphi, nr)) + 1j * rng.standard_normal((nt, nphi, nr))
-    Y = AngularTransform(nr, nt, nphi)
+    Y = AngularTransform(nr, nt, nphi, precision)
     ref = angular.forward(psi, nt, nphi)
     c = Y.forward(dev(psi, Y.dtype)).cpu().numpy().reshape(nphi, nt, nr)
     scale = np.abs(ref).max()
-    assert np.abs(c - ref).max() <= 2e-6 * scale * math.sqrt(nt)
-    assert np.linalg.norm(c - ref) <= 2e-6 * np.linalg.norm(ref)
+    assert np.abs(c - ref).max() <= tol * scale * math.sqrt(nt)
+    assert np.linalg.norm(c - ref) <= tol * np.linalg.norm(ref)
     refi = angular.inverse(ref, nt, nphi)
     got_i = Y.inverse(dev(ref, Y.dtype)).cpu().numpy().reshape(nt, nphi, nr)
-    assert np.abs(got_i - refi).max() <= 2e-6 * np.abs(refi).max() * math.sqrt(nt)
-    assert np.linalg.norm(got_i - refi) <= 2e-6 * np.linalg.norm(refi)
+    assert np.abs(got_i - refi).max() <= tol * np.abs(refi).max() * math.sqrt(nt)
+    assert np.linalg.norm(got_i - refi) <= tol * np.linalg.norm(refi)
 
 
 @pytest.mark.parametrize("l,m", [(0, 0), (2, -1), (5, 3), (8, -7), (8, 8)])
