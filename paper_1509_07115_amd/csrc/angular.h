@@ -47,11 +47,11 @@ hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso
                             int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
                             hipStream_t s);
 
-// The real-matrix case for complex128 data on the FP64 matrix cores:
-// A_o(q', q) = mat16[o*mso + q'*Q16 + q], Q16 = Q rounded up to 16 (<= 64),
-// zero outside q, q' < Q, 16-byte aligned.
-hipError_t launch_axis_real_mfma64(const double* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
-                                   void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s);
+// launch_axis_mfma for complex128 data on the FP64 matrix cores, the matrix as
+// an FP64 table of the same layout (Q16 <= 64).
+hipError_t launch_axis_mfma64(bool complex_matrix, const double* mat16, int64_t mso, const void* src, int64_t so,
+                              int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
+                              hipStream_t s);
 
 // x[i] *= exp(-i (V0[i] + F V1[i]) dt/2) for i < n (complex of S; V0, V1 FP64
 // device arrays or null), angles reduced mod 2 pi in FP64.

@@ -252,27 +252,28 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
     }
 }
 
-// The real-matrix axis step (the per-m Legendre blocks) for complex128 data on
-// the FP64 matrix cores: per block of 32 radial points, D = A X with A the
-// zero-padded Q16 x Q16 block (Q16 = 16 NR) and X the 64 real columns (2 i +
-// part), wave w taking columns 16 w .. 16 w + 15.  v_mfma_f64_16x16x4_f64 takes
-// the operands of the FP32 form (lane l: A[l%16][l/16], B[l/16][l%16]) and
-// returns row 4 v + l/16, column l%16 in result register v.  The contraction
-// index is split as k = 16 G + 4 (l/16) + s, so that each lane holds the four
-// k of its four instructions in 32 contiguous bytes of the matrix (registers,
-// loaded once) and of the transposed LDS copy Xt[column][k] (pitch Q16 + 2).
-// Workgroups loop over point blocks of one outer index with the next block's
-// loads issued, from clamped addresses with no branch, before the current one
-// is multiplied.
+// The axis steps for complex128 data on the FP64 matrix cores, in the forms of
+// axis_mfma: the real per-m Legendre block on 32 radial points per block (64
+// real columns 2 i + part), or the azimuthal DFT in its real form
+// [[Re, -Im], [Im, Re]] (contraction index 2 q + part) on 64 points per block;
+// either way 64 columns, wave w taking columns 16 w .. 16 w + 15.
+// v_mfma_f64_16x16x4_f64 takes the operands of the FP32 form (lane l:
+// A[l%16][l/16], B[l/16][l%16]) and returns row 4 v + l/16, column l%16 in
+// result register v.  The contraction index is split as k = 16 G + 4 (l/16) + s,
+// so that each lane holds the four k of its four instructions in 32 contiguous
+// bytes of the matrix (registers, loaded once) and of the transposed LDS copy
+// Xt[column][k] (pitch Q16 + 2).  Workgroups loop over point blocks of one
+// outer index with the next block's loads issued, from clamped addresses with
+// no branch, before the current one is multiplied.
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-template <int NR>
-__global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict__ mat16, int64_t mso,
-                                                        const double2* __restrict__ src, int64_t so, int64_t sq,
-                                                        double2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
-                                                        int Nr) {
-    constexpr int Q16 = 16 * NR, XS = Q16 + 2, NCOL = 64, YP = NCOL + 2, PB = 32;
-    constexpr int NIT = Q16 * PB / 256;   // staging items per thread: (row, point)
+template <int NR, bool CPX>
+__global__ void __launch_bounds__(256) axis_mfma64(const double* __restrict__ mat16, int64_t mso,
+                                                   const double2* __restrict__ src, int64_t so, int64_t sq,
+                                                   double2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
+                                                   int Nr) {
+    constexpr int Q16 = 16 * NR, XS = Q16 + 2, NCOL = 64, YP = NCOL + 2, PB = CPX ? 64 : 32;
+    constexpr int NIT = 2 * NR;   // staging items per thread: (input row, point)
     static_assert(Q16 * YP <= NCOL * XS, "result staging must fit in the input buffer");
     __shared__ __align__(16) double Xt[NCOL * XS];
     const int o = blockIdx.y;
@@ -292,6 +293,8 @@ __global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict
                 const double2 hi = *reinterpret_cast<const double2*>(Am + 16 * rb * Q16 + 16 * G + 2);
                 a[G][rb] = d4v{lo.x, lo.y, hi.x, hi.y};
             }
+        // have them in registers here: a first use inside the block loop would
+        // put a wait on every memory operation in flight into each iteration
 #pragma unroll
         for (int G = 0; G < NR; ++G)
 #pragma unroll
@@ -301,7 +304,7 @@ __global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict
                 asm volatile("" ::"v"(t.lo), "v"(t.hi));
             }
     }
-    double2 pf[NIT];   // item e = threadIdx.x + 256 u: row e / PB, point e % PB
+    double2 pf[NIT];   // item e = threadIdx.x + 256 u: input row e / PB, point e % PB
     auto fetch = [&](int bx) {
 #pragma unroll
         for (int u = 0; u < NIT; ++u) {
@@ -317,8 +320,12 @@ __global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict
         for (int u = 0; u < NIT; ++u) {
             const int e = threadIdx.x + 256 * u, q = e / PB, il = e % PB;
             const double2 v = (q < Q && i0 + il < Nr) ? pf[u] : double2{0.0, 0.0};
-            Xt[(2 * il) * XS + q] = v.x;
-            Xt[(2 * il + 1) * XS + q] = v.y;
+            if constexpr (CPX) {
+                *reinterpret_cast<double2*>(Xt + il * XS + 2 * q) = v;
+            } else {
+                Xt[(2 * il) * XS + q] = v.x;
+                Xt[(2 * il + 1) * XS + q] = v.y;
+            }
         }
         __syncthreads();
         fetch(bx + gridDim.x);
@@ -346,7 +353,11 @@ __global__ void __launch_bounds__(256) axis_real_mfma64(const double* __restrict
         __syncthreads();
         for (int e = threadIdx.x; e < Q * PB; e += 256) {
             const int t = e / PB, il = e % PB;
-            if (i0 + il < Nr) dp[t * dq + i0 + il] = double2{Ys[t * YP + 2 * il], Ys[t * YP + 2 * il + 1]};
+            if (i0 + il >= Nr) continue;
+            if constexpr (CPX)
+                dp[t * dq + i0 + il] = double2{Ys[(2 * t) * YP + il], Ys[(2 * t + 1) * YP + il]};
+            else
+                dp[t * dq + i0 + il] = double2{Ys[t * YP + 2 * il], Ys[t * YP + 2 * il + 1]};
         }
         __syncthreads();
     }
@@ -481,17 +492,18 @@ static hipError_t launch_axis_mfma_t(const float* mat16, int64_t mso, const void
     return hipGetLastError();
 }
 
-// Workgroups of axis_real_mfma64<nr> resident on the device at once (queried
+// Workgroups of axis_mfma64<nr, CPX> resident on the device at once (queried
 // once, first from set_lds_limits_axis); -1 if the query fails.
-static int axis_real_mfma64_fit(int nr) {
+template <bool CPX>
+static int axis_mfma64_fit(int nr) {
     static std::atomic<int> fit[4] = {{0}, {0}, {0}, {0}};
     if (nr < 1 || nr > 4) return -1;
     int f = fit[nr - 1].load(std::memory_order_relaxed);
     if (f > 0) return f;
-    const void* k = nr == 1   ? (const void*)axis_real_mfma64<1>
-                    : nr == 2 ? (const void*)axis_real_mfma64<2>
-                    : nr == 3 ? (const void*)axis_real_mfma64<3>
-                              : (const void*)axis_real_mfma64<4>;
+    const void* k = nr == 1   ? (const void*)axis_mfma64<1, CPX>
+                    : nr == 2 ? (const void*)axis_mfma64<2, CPX>
+                    : nr == 3 ? (const void*)axis_mfma64<3, CPX>
+                              : (const void*)axis_mfma64<4, CPX>;
     int dev = 0, ncu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -502,25 +514,35 @@ static int axis_real_mfma64_fit(int nr) {
     return f;
 }
 
-hipError_t launch_axis_real_mfma64(const double* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
-                                   void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
-    const int nr = (Q + 15) / 16;
+template <bool CPX>
+static hipError_t launch_axis_mfma64_t(const double* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
+                                       void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
+                                       hipStream_t s) {
+    const int nr = ((CPX ? 2 * Q : Q) + 15) / 16;
     if (Q < 1 || nr > 4 || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
-    const int fit0 = axis_real_mfma64_fit(nr);
+    const int fit0 = axis_mfma64_fit<CPX>(nr);
     if (fit0 < 0) return hipErrorInvalidValue;
-    const int nblk = (Nr + 31) / 32;
+    const int pb = CPX ? 64 : 32;
+    const int nblk = (Nr + pb - 1) / pb;
     const int fit = std::max(1, std::min(nblk, fit0 / nouter));
     const int per = (nblk + fit - 1) / fit;
     const dim3 grid((unsigned)((nblk + per - 1) / per), (unsigned)nouter);
     const double2* x = static_cast<const double2*>(src);
     double2* y = static_cast<double2*>(dst);
     switch (nr) {
-        case 1: hipLaunchKernelGGL(axis_real_mfma64<1>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
-        case 2: hipLaunchKernelGGL(axis_real_mfma64<2>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
-        case 3: hipLaunchKernelGGL(axis_real_mfma64<3>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
-        default: hipLaunchKernelGGL(axis_real_mfma64<4>, grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 1: hipLaunchKernelGGL((axis_mfma64<1, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 2: hipLaunchKernelGGL((axis_mfma64<2, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        case 3: hipLaunchKernelGGL((axis_mfma64<3, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
+        default: hipLaunchKernelGGL((axis_mfma64<4, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_axis_mfma64(bool complex_matrix, const double* mat16, int64_t mso, const void* src, int64_t so,
+                              int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
+                              hipStream_t s) {
+    return complex_matrix ? launch_axis_mfma64_t<true>(mat16, mso, src, so, sq, dst, dout, dq, Q, nouter, Nr, s)
+                          : launch_axis_mfma64_t<false>(mat16, mso, src, so, sq, dst, dout, dq, Q, nouter, Nr, s);
 }
 
 hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso, const void* src, int64_t so,
@@ -532,7 +554,8 @@ hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso
 
 hipError_t set_lds_limits_axis() {
     for (int nr = 1; nr <= 4; ++nr)
-        if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0 || axis_real_mfma64_fit(nr) < 0)
+        if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0 ||
+            axis_mfma64_fit<true>(nr) < 0 || axis_mfma64_fit<false>(nr) < 0)
             return hipErrorInvalidDeviceFunction;
     hipError_t e = hipFuncSetAttribute((const void*)axis_apply<float, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -15,7 +15,7 @@ struct dsbt_sht_s {
     void* d_phi = nullptr;   // Phi[q][k] complex (interleaved), precision of the data
     void* d_work = nullptr;  // a[j][q][i], complex
     void* d_pm = nullptr;    // [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse), data precision
-    float* d_fm = nullptr;   // complex64, 2 N_phi <= 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded
+    void* d_fm = nullptr;    // 2 N_phi <= 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded, data precision
     void release() {
         if (d_phi) (void)hipFree(d_phi);
         if (d_work) (void)hipFree(d_work);
@@ -43,18 +43,22 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
     const S* F = static_cast<const S*>(p->d_phi);
     const int64_t q16 = (nt + 15) / 16 * 16;
     const int64_t f16 = (2 * nf + 15) / 16 * 16;
-    // matrix cores for complex64 (the DFT while 2 N_phi <= 64), the vector kernel otherwise
+    // matrix cores (the DFT while 2 N_phi <= 64), the vector kernel otherwise
     auto legendre = [&](bool tr, const void* x, int64_t so, int64_t sq, void* y, int64_t dout, int64_t dq) {
         const S* pm = static_cast<const S*>(p->d_pm) + (tr ? nf * q16 * q16 : 0);
         if constexpr (std::is_same<S, float>::value)
             return dsbt::launch_axis_mfma(false, pm, q16 * q16, x, so, sq, y, dout, dq, nt, nf, Nr, s);
         else
-            return dsbt::launch_axis_real_mfma64(pm, q16 * q16, x, so, sq, y, dout, dq, nt, nf, Nr, s);
+            return dsbt::launch_axis_mfma64(false, pm, q16 * q16, x, so, sq, y, dout, dq, nt, nf, Nr, s);
     };
     auto azimuth = [&](bool inv, const void* x, void* y) {
-        if (p->d_fm)
-            return dsbt::launch_axis_mfma(true, p->d_fm + (inv ? f16 * f16 : 0), 0, x, lf, Nr, y, lf, Nr, nf, nt, Nr,
-                                          s);
+        if (p->d_fm) {
+            const S* fm = static_cast<const S*>(p->d_fm) + (inv ? f16 * f16 : 0);
+            if constexpr (std::is_same<S, float>::value)
+                return dsbt::launch_axis_mfma(true, fm, 0, x, lf, Nr, y, lf, Nr, nf, nt, Nr, s);
+            else
+                return dsbt::launch_axis_mfma64(true, fm, 0, x, lf, Nr, y, lf, Nr, nf, nt, Nr, s);
+        }
         return dsbt::launch_axis_apply<S, true>(F, 0, inv, inv, x, lf, Nr, y, lf, Nr, nf, nt, Nr, s);
     };
     hipError_t e;
@@ -141,26 +145,25 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
                 }
         e = precision == DSBT_C128 ? upload<double>(pm, &p->d_pm) : upload<float>(pm, &p->d_pm);
     }
-    if (e == hipSuccess && precision == DSBT_C64 && 2 * n_phi <= 64) {
+    if (e == hipSuccess && 2 * n_phi <= 64) {
         // [[Re, -Im], [Im, Re]] per element: forward A(q, k) = Phi[q][k], inverse A(k, q) = conj(Phi[q][k])
         const size_t f16 = (size_t)(2 * n_phi + 15) / 16 * 16, blk = f16 * f16;
-        std::vector<float> fm(2 * blk, 0.0f);
+        std::vector<double> fm(2 * blk, 0.0);
         for (int q = 0; q < n_phi; ++q)
             for (int k = 0; k < n_phi; ++k) {
-                const float re = (float)F[2 * ((size_t)q * n_phi + k)], im = (float)F[2 * ((size_t)q * n_phi + k) + 1];
-                float* f = fm.data() + 2 * q * f16 + 2 * k;       // forward: rows 2q + a, columns 2k + b
+                const double re = F[2 * ((size_t)q * n_phi + k)], im = F[2 * ((size_t)q * n_phi + k) + 1];
+                double* f = fm.data() + 2 * q * f16 + 2 * k;       // forward: rows 2q + a, columns 2k + b
                 f[0] = re;
                 f[1] = -im;
                 f[f16] = im;
                 f[f16 + 1] = re;
-                float* g = fm.data() + blk + 2 * k * f16 + 2 * q;   // inverse: rows 2k + a, columns 2q + b
+                double* g = fm.data() + blk + 2 * k * f16 + 2 * q;   // inverse: rows 2k + a, columns 2q + b
                 g[0] = re;
                 g[1] = im;
                 g[f16] = -im;
                 g[f16 + 1] = re;
             }
-        e = hipMalloc(reinterpret_cast<void**>(&p->d_fm), sizeof(float) * fm.size());
-        if (e == hipSuccess) e = hipMemcpy(p->d_fm, fm.data(), sizeof(float) * fm.size(), hipMemcpyHostToDevice);
+        e = precision == DSBT_C128 ? upload<double>(fm, &p->d_fm) : upload<float>(fm, &p->d_fm);
     }
     if (e != hipSuccess) {
         p->release();
