@@ -70,6 +70,36 @@ __global__ void __launch_bounds__(kThreads) orthonormalize(const int64_t* __rest
     using V = typename Cplx<S>::t;
     const int c0 = first[blockIdx.x], c1 = first[blockIdx.x + 1];
     __shared__ double red[2 * kWaves];
+    constexpr int kRegs = 16;   // values per thread of the one-channel path
+    if (c1 - c0 == 1 && Nc[c0] >= 1 && Nc[c0] <= kThreads * kRegs) {
+        // A set of one channel is only normalised: the channel is held in
+        // registers (one read and one write; the loads come from clamped
+        // addresses with no branch, so they are all in flight at once).  Each
+        // thread sums its values in the order of the loop below, so the result
+        // is the same.
+        V* pj = psi + off[c0];
+        const int N = Nc[c0];
+        V z[kRegs];
+#pragma unroll
+        for (int u = 0; u < kRegs; ++u) z[u] = pj[min((int)threadIdx.x + kThreads * u, N - 1)];
+        double n2[1] = {0.0};
+#pragma unroll
+        for (int u = 0; u < kRegs; ++u)
+            n2[0] += (int)threadIdx.x + kThreads * u < N ? (double)z[u].x * z[u].x + (double)z[u].y * z[u].y : 0.0;
+        block_sum<1>(n2, red);
+        const double sc = n2[0] > 0.0 ? 1.0 / sqrt(n2[0]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kRegs; ++u) {
+            const int k = threadIdx.x + kThreads * u;
+            if (k < N) {
+                V z1 = z[u];
+                z1.x = (S)(z1.x * sc);
+                z1.y = (S)(z1.y * sc);
+                pj[k] = z1;
+            }
+        }
+        return;
+    }
     for (int j = c0; j < c1; ++j) {
         V* pj = psi + off[j];
         const int N = Nc[j];

@@ -153,6 +153,28 @@ def test_orthonormalize_matches_oracle(precision):
             plan.orthonormalize(x, bad)
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_orthonormalize_single_channel_sets(precision):
+    """Sets of one channel are normalised in registers up to 4096 points and by
+    the general loop above that (8192): both against the oracle's Gram-Schmidt."""
+    sizes = [16, 256, 4096, 8192, 2048]
+    chs, off = [], 0
+    for N in sizes:
+        chs.append((N, 0, 0.1 * N, off))
+        off += N
+    psi = random_state(chs, off, 15)
+    for c, (N, _, _, o) in enumerate(chs):
+        psi[o:o + N] *= 2.5 + c
+    plan = Plan(chs, precision=precision)
+    x = dev(psi, plan.dtype)
+    ref = x.cpu().numpy().astype(np.complex128)
+    plan.orthonormalize(x, list(range(len(sizes) + 1)))
+    got = x.cpu().numpy().astype(np.complex128)
+    for N, _, _, o in chs:
+        q = tdse.orthonormalize(ref[o:o + N, None])[:, 0]
+        assert np.linalg.norm(got[o:o + N] - q) <= 10 * TOL[precision], (N, precision)
+
+
 def imag_time_energies(w, precision, dt, nsteps, every=10):
     plan = Plan(w.channels, precision=precision, kinetic="corrected")
     plan.set_potential(w.extra["V"], dt, imaginary=True)
