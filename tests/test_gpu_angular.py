@@ -28,6 +28,8 @@ def dev(x, dtype):
 # kernel of the azimuthal step (2 N_phi > 64).
 CASES = [(8, 9, 100, "c64", 2e-6), (16, 17, 256, "c64", 2e-6), (64, 63, 70, "c64", 2e-6), (1, 1, 64, "c64", 1e-6),
          (33, 31, 130, "c64", 2e-6), (20, 5, 64, "c64", 2e-6),
+         # fewer radial points than one block: every load past the last point is clamped
+         (5, 3, 3, "c64", 2e-6), (33, 31, 1, "c64", 2e-6), (5, 3, 3, "c128", 1e-12), (40, 31, 1, "c128", 1e-12),
          (8, 9, 100, "c128", 1e-12), (16, 31, 130, "c128", 1e-12), (64, 63, 65, "c128", 1e-12)]
 
 
