@@ -42,7 +42,8 @@ hipError_t launch_axis_apply(const S* mat, int64_t mso, bool tr, bool cj, const 
 // used block, 16-byte aligned.  Real matrix (complex_matrix false):
 // A_o(q', q) = mat16[o*mso + q'*Q16 + q], Q16 = Q rounded up to 16.  Complex
 // matrix: row 2 q' + a, column 2 q + b hold [[Re, -Im], [Im, Re]][a][b] of
-// A_o(q', q), Q16 = 2 Q rounded up to 16.  Q16 <= 64, else hipErrorInvalidValue.
+// A_o(q', q), Q16 = 2 Q rounded up to 16.  Q16 <= 64 (real) or 128 (complex;
+// above 64 only with mso = 0), else hipErrorInvalidValue.
 hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso, const void* src, int64_t so,
                             int64_t sq, void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr,
                             hipStream_t s);

@@ -258,6 +258,94 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
     }
 }
 
+// The complex64 azimuthal DFT for 64 < 2 N_phi <= 128 on the matrix cores: the
+// real form of axis_mfma<NR, true> with NR = 5..8 row blocks, whose matrix does
+// not fit in registers: it is staged once per workgroup in LDS (As[row][k],
+// pitch Q16 + 4 like Xt, so the 16-byte fragment reads of 16 lanes cover all
+// banks once), with the results in a third LDS buffer (Ys, pitch 68).  Dynamic
+// LDS: (64 + Q16) (Q16 + 4) + 68 Q16 floats.
+__host__ __device__ constexpr size_t axis_big_lds_bytes(int NR) {
+    return sizeof(float) * ((size_t)(64 + 16 * NR) * (16 * NR + 4) + (size_t)68 * 16 * NR);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) axis_mfma_big(const float* __restrict__ mat16,
+                                                     const float2* __restrict__ src, int64_t so, int64_t sq,
+                                                     float2* __restrict__ dst, int64_t dout, int64_t dq, int Q,
+                                                     int Nr) {
+    constexpr int Q16 = 16 * NR, XS = Q16 + 4, YP = 68;
+    extern __shared__ __align__(16) unsigned char lds_big[];
+    float* Xt = reinterpret_cast<float*>(lds_big);   // Xt[point][k], 64 x XS
+    float* As = Xt + 64 * XS;                         // As[row][k], Q16 x XS
+    float* Ys = As + Q16 * XS;                        // Ys[row][point], Q16 x YP
+    const int o = blockIdx.y;
+    const int nblk = (Nr + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float2* sp = src + o * so;
+    float2* dp = dst + o * dout;
+    for (int e = threadIdx.x; e < Q16 * Q16 / 4; e += 256) {
+        const int r = e / (Q16 / 4), k4 = e - r * (Q16 / 4);
+        *reinterpret_cast<f4v*>(As + r * XS + 4 * k4) = *reinterpret_cast<const f4v*>(mat16 + r * Q16 + 4 * k4);
+    }
+    // staging item (g, il) = threadIdx.x + 256 u: input rows 2 g, 2 g + 1 of point
+    // il; loads from clamped addresses with no branch, zeroed when staged
+    float2 pf[NR][2];
+    auto fetch = [&](int bx) {
+        const int ic = min(bx * 64 + (threadIdx.x & 63), Nr - 1);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int g = (threadIdx.x + 256 * u) >> 6;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) pf[u][c] = sp[min(2 * g + c, Q - 1) * sq + ic];
+        }
+    };
+    int bx = blockIdx.x;
+    fetch(bx);
+    for (; bx < nblk; bx += gridDim.x) {
+        const bool live = bx * 64 + (threadIdx.x & 63) < Nr;
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const int e = threadIdx.x + 256 * u, il = e & 63, g = e >> 6;
+            const float2 v0 = (live && 2 * g < Q) ? pf[u][0] : float2{0.f, 0.f};
+            const float2 v1 = (live && 2 * g + 1 < Q) ? pf[u][1] : float2{0.f, 0.f};
+            *reinterpret_cast<f4v*>(Xt + il * XS + 4 * g) = f4v{v0.x, v0.y, v1.x, v1.y};
+        }
+        __syncthreads();
+        fetch(bx + gridDim.x);
+        f4v acc[NR];
+#pragma unroll
+        for (int rb = 0; rb < NR; ++rb) acc[rb] = f4v{0.f, 0.f, 0.f, 0.f};
+        const int kl = 4 * (lane >> 4);
+#pragma unroll
+        for (int G = 0; G < NR; ++G) {
+            const f4v b = *reinterpret_cast<const f4v*>(Xt + (16 * w + (lane & 15)) * XS + 16 * G + kl);
+            f4v a[NR];
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb)
+                a[rb] = *reinterpret_cast<const f4v*>(As + (16 * rb + (lane & 15)) * XS + 16 * G + kl);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int rb = 0; rb < NR; ++rb)
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][s], b[s], acc[rb], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < NR; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Ys[(16 * rb + 4 * (lane >> 4) + v) * YP + 16 * w + (lane & 15)] = acc[rb][v];
+        __syncthreads();
+        const int i0 = bx * 64;
+        for (int e = threadIdx.x; e < Q * 64; e += 256) {
+            const int t = e >> 6, il = e & 63;
+            if (i0 + il < Nr) dp[t * dq + i0 + il] = float2{Ys[(2 * t) * YP + il], Ys[(2 * t + 1) * YP + il]};
+        }
+        __syncthreads();
+    }
+}
+
 // The axis steps for complex128 data on the FP64 matrix cores, in the forms of
 // axis_mfma: the real per-m Legendre block on 32 radial points per block (64
 // real columns 2 i + part), or the azimuthal DFT in its real form
@@ -474,12 +562,35 @@ static int axis_mfma_fit(int nr) {
     return f;
 }
 
+// Workgroups of axis_mfma_big<nr> (nr = 5..8) resident on the device at once,
+// with its dynamic LDS (queried once, first from set_lds_limits_axis); -1 if
+// the query fails.
+static int axis_big_fit(int nr) {
+    static std::atomic<int> fit[4] = {{0}, {0}, {0}, {0}};
+    if (nr < 5 || nr > 8) return -1;
+    int f = fit[nr - 5].load(std::memory_order_relaxed);
+    if (f > 0) return f;
+    const void* k = nr == 5   ? (const void*)axis_mfma_big<5>
+                    : nr == 6 ? (const void*)axis_mfma_big<6>
+                    : nr == 7 ? (const void*)axis_mfma_big<7>
+                              : (const void*)axis_mfma_big<8>;
+    int dev = 0, ncu = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, 256, axis_big_lds_bytes(nr)) != hipSuccess)
+        return -1;
+    f = std::max(1, occ) * std::max(1, ncu);
+    fit[nr - 5].store(f, std::memory_order_relaxed);
+    return f;
+}
+
 template <bool CPX>
 static hipError_t launch_axis_mfma_t(const float* mat16, int64_t mso, const void* src, int64_t so, int64_t sq,
                                      void* dst, int64_t dout, int64_t dq, int Q, int nouter, int Nr, hipStream_t s) {
     const int nr = ((CPX ? 2 * Q : Q) + 15) / 16;
-    if (Q < 1 || nr > 4 || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
-    const int fit0 = axis_mfma_fit<CPX>(nr);
+    if (Q < 1 || nr > (CPX ? 8 : 4) || nouter < 1 || Nr < 1) return hipErrorInvalidValue;
+    if (CPX && nr > 4 && mso != 0) return hipErrorInvalidValue;   // the large form takes one shared matrix
+    const int fit0 = nr > 4 ? axis_big_fit(nr) : axis_mfma_fit<CPX>(nr);
     if (fit0 < 0) return hipErrorInvalidValue;
     const int nblk = (Nr + 63) / 64;
     // as many workgroups as fit on the device at once (at least one per outer
@@ -489,6 +600,16 @@ static hipError_t launch_axis_mfma_t(const float* mat16, int64_t mso, const void
     const dim3 grid((unsigned)((nblk + per - 1) / per), (unsigned)nouter);
     const float2* x = static_cast<const float2*>(src);
     float2* y = static_cast<float2*>(dst);
+    if (nr > 4) {
+        const size_t lds = axis_big_lds_bytes(nr);
+        switch (nr) {
+            case 5: hipLaunchKernelGGL(axis_mfma_big<5>, grid, dim3(256), lds, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+            case 6: hipLaunchKernelGGL(axis_mfma_big<6>, grid, dim3(256), lds, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+            case 7: hipLaunchKernelGGL(axis_mfma_big<7>, grid, dim3(256), lds, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+            default: hipLaunchKernelGGL(axis_mfma_big<8>, grid, dim3(256), lds, s, mat16, x, so, sq, y, dout, dq, Q, Nr); break;
+        }
+        return hipGetLastError();
+    }
     switch (nr) {
         case 1: hipLaunchKernelGGL((axis_mfma<1, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
         case 2: hipLaunchKernelGGL((axis_mfma<2, CPX>), grid, dim3(256), 0, s, mat16, mso, x, so, sq, y, dout, dq, Q, Nr); break;
@@ -559,6 +680,16 @@ hipError_t launch_axis_mfma(bool complex_matrix, const float* mat16, int64_t mso
 }
 
 hipError_t set_lds_limits_axis() {
+    {
+        const void* big[4] = {(const void*)axis_mfma_big<5>, (const void*)axis_mfma_big<6>,
+                              (const void*)axis_mfma_big<7>, (const void*)axis_mfma_big<8>};
+        for (int i = 0; i < 4; ++i) {
+            const hipError_t e = hipFuncSetAttribute(big[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)axis_big_lds_bytes(5 + i));
+            if (e != hipSuccess) return e;
+            if (axis_big_fit(5 + i) < 0) return hipErrorInvalidDeviceFunction;
+        }
+    }
     for (int nr = 1; nr <= 4; ++nr)
         if (axis_mfma_fit<true>(nr) < 0 || axis_mfma_fit<false>(nr) < 0 ||
             axis_mfma64_fit<true>(nr) < 0 || axis_mfma64_fit<false>(nr) < 0)

@@ -15,7 +15,7 @@ struct dsbt_sht_s {
     void* d_phi = nullptr;   // Phi[q][k] complex (interleaved), precision of the data
     void* d_work = nullptr;  // a[j][q][i], complex
     void* d_pm = nullptr;    // [2][q][16 NR][16 NR] zero-padded P[q] (forward) and P[q]^T (inverse), data precision
-    void* d_fm = nullptr;    // 2 N_phi <= 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded, data precision
+    void* d_fm = nullptr;    // 2 N_phi <= 128 (complex64) or 64: [2][F16][F16] real forms of Phi and Phi^H, zero-padded
     void release() {
         if (d_phi) (void)hipFree(d_phi);
         if (d_work) (void)hipFree(d_work);
@@ -43,7 +43,7 @@ hipError_t run(dsbt_sht_s* p, const void* src, void* dst, bool inverse, hipStrea
     const S* F = static_cast<const S*>(p->d_phi);
     const int64_t q16 = (nt + 15) / 16 * 16;
     const int64_t f16 = (2 * nf + 15) / 16 * 16;
-    // matrix cores (the DFT while 2 N_phi <= 64), the vector kernel otherwise
+    // matrix cores (the complex128 DFT while 2 N_phi <= 64), the vector kernel otherwise
     auto legendre = [&](bool tr, const void* x, int64_t so, int64_t sq, void* y, int64_t dout, int64_t dq) {
         const S* pm = static_cast<const S*>(p->d_pm) + (tr ? nf * q16 * q16 : 0);
         if constexpr (std::is_same<S, float>::value)
@@ -145,7 +145,7 @@ dsbt_status dsbt_sht_create(dsbt_sht* out, int32_t Nr, int32_t n_theta, int32_t 
                 }
         e = precision == DSBT_C128 ? upload<double>(pm, &p->d_pm) : upload<float>(pm, &p->d_pm);
     }
-    if (e == hipSuccess && 2 * n_phi <= 64) {
+    if (e == hipSuccess && 2 * n_phi <= (precision == DSBT_C64 ? 128 : 64)) {
         // [[Re, -Im], [Im, Re]] per element: forward A(q, k) = Phi[q][k], inverse A(k, q) = conj(Phi[q][k])
         const size_t f16 = (size_t)(2 * n_phi + 15) / 16 * 16, blk = f16 * f16;
         std::vector<double> fm(2 * blk, 0.0);

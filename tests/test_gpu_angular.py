@@ -24,10 +24,12 @@ def dev(x, dtype):
 
 
 # tolerances: FP32 arithmetic, or FP64.  The complex64 cases take every matrix-core
-# tile count (16, 32, 48, 64 rows) of both axis steps, and N_phi = 63 the vector
-# kernel of the azimuthal step (2 N_phi > 64).
+# tile count of both axis steps (16 to 64 rows; the DFT up to 128), and N_phi = 63
+# in complex128 the vector kernel of the azimuthal step (2 N_phi > 64).
 CASES = [(8, 9, 100, "c64", 2e-6), (16, 17, 256, "c64", 2e-6), (64, 63, 70, "c64", 2e-6), (1, 1, 64, "c64", 1e-6),
          (33, 31, 130, "c64", 2e-6), (20, 5, 64, "c64", 2e-6),
+         # 64 < 2 N_phi <= 128: the DFT matrix in LDS, 5, 6, 7 and 8 row blocks
+         (8, 33, 100, "c64", 2e-6), (4, 45, 70, "c64", 2e-6), (3, 53, 130, "c64", 2e-6),
          # fewer radial points than one block: every load past the last point is clamped
          (5, 3, 3, "c64", 2e-6), (33, 31, 1, "c64", 2e-6), (5, 3, 3, "c128", 1e-12), (40, 31, 1, "c128", 1e-12),
          (8, 9, 100, "c128", 1e-12), (16, 31, 130, "c128", 1e-12), (64, 63, 65, "c128", 1e-12)]
