@@ -5,11 +5,13 @@
 //  * axis_mfma (complex64) and axis_mfma64 (complex128): the contraction as a
 //    real product on the matrix cores, for matrices up to 64 x 64 in real form
 //    (every Legendre block; the DFT while 2 N_phi <= 64).
-//  * axis_apply: the vector kernel for the larger DFT.  A workgroup takes one
-//    outer index and 64 consecutive radial points: their Q input vectors and
-//    the Q x Q matrix are staged in LDS, and each of the four waves accumulates
-//    every fourth output row for its 64 points, reading the matrix as LDS
-//    broadcasts (one element per row and input, the same for the whole wave).
+//  * axis_mfma_big: the complex64 DFT for 64 < 2 N_phi <= 128, matrix in LDS.
+//  * axis_apply: the vector kernel for the larger complex128 DFT.  A workgroup
+//    takes one outer index and 64 consecutive radial points: their Q input
+//    vectors and the Q x Q matrix are staged in LDS, and each of the four waves
+//    accumulates every fourth output row for its 64 points, reading the matrix
+//    as LDS broadcasts (one element per row and input, the same for the whole
+//    wave).
 // grid_phase and momentum_order are the diagonal factors and the reordering
 // of the 3D split steps.
 #include <algorithm>
