@@ -140,9 +140,10 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
 //    and the output row 2 q' + part', with A = [[Re, -Im], [Im, Re]] per element,
 //    so the 64 points are NCOL = 64 columns.
 // Workgroup (x, o) takes the point blocks x, x + gridDim.x, ... of outer index
-// o: its matrix fragments are loaded once into registers, and the inputs of the
-// next block are loaded into registers while the current one is multiplied and
-// stored, so that memory and matrix work overlap inside the workgroup.  The
+// o: its matrix is loaded once (into registers, or for the real form into LDS),
+// and the inputs of the next block are loaded into registers while the current
+// one is multiplied and stored, so that memory and matrix work overlap inside
+// the workgroup.  The
 // inputs are staged transposed in LDS (Xt[column][k], row pitch Q16 + 4 floats,
 // so that the 16-byte reads of 16 lanes cover all 64 banks once); wave w takes
 // NCOL / 4 columns and every row block.  v_mfma_f32_16x16x4_f32: lane l
@@ -150,7 +151,8 @@ __global__ void __launch_bounds__(256) axis_apply(const S* __restrict__ mat, int
 // D[4 (l/16) + v][l%16].  The contraction index is split as
 // k = 16 G + 4 (l/16) + s for instruction s of group G, so that each lane holds
 // the four k of its four instructions as one 16-byte word, of the zero-padded
-// matrix (row-major [Q16][Q16] at mat16 + o mso in global memory) and of Xt.
+// matrix (row-major [Q16][Q16] at mat16 + o mso in global memory; As, pitch XS,
+// for the real form) and of Xt.
 // Results pass through LDS (over Xt, row pitch NCOL + 4 floats: conflict-free)
 // and are written back coalesced.
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -170,13 +172,30 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const float2* sp = src + o * so;
     float2* dp = dst + o * dout;
-    f4v a[NR][NR];   // [G][rb]
-    {
+    // the matrix fragments: the complex form (at most 64 x 64, shared by every
+    // outer index) in registers for the whole workgroup; the real per-m block
+    // staged once in LDS (As[row][k], pitch XS), which leaves registers for a
+    // third workgroup per compute unit
+    f4v a[CPX ? NR : 1][NR];   // [G][rb]
+    __shared__ __align__(16) float As[CPX ? 4 : Q16 * XS];
+    if constexpr (CPX) {
         const float* Am = mat16 + o * mso + (lane & 15) * Q16 + 4 * (lane >> 4);
 #pragma unroll
         for (int G = 0; G < NR; ++G)
 #pragma unroll
             for (int rb = 0; rb < NR; ++rb) a[G][rb] = *reinterpret_cast<const f4v*>(Am + 16 * rb * Q16 + 16 * G);
+        // have them in registers here: a first use inside the block loop would
+        // put a wait on every memory operation in flight into each iteration
+#pragma unroll
+        for (int G = 0; G < NR; ++G)
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb) asm volatile("" ::"v"(a[G][rb]));
+    } else {
+        for (int e = threadIdx.x; e < Q16 * Q16 / 4; e += 256) {
+            const int r = e / (Q16 / 4), k4 = e - r * (Q16 / 4);
+            *reinterpret_cast<f4v*>(As + r * XS + 4 * k4) =
+                *reinterpret_cast<const f4v*>(mat16 + o * mso + r * Q16 + 4 * k4);
+        }
     }
     // staging item (g, il) = threadIdx.x + 256 u holds the contraction indices
     // 4 g .. 4 g + 3 of point il: input rows 2 g, 2 g + 1 (complex matrix) or
@@ -223,6 +242,14 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
             for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int G = 0; G < NR; ++G) {
+            f4v ag[NR];
+#pragma unroll
+            for (int rb = 0; rb < NR; ++rb) {
+                if constexpr (CPX)
+                    ag[rb] = a[G][rb];
+                else
+                    ag[rb] = *reinterpret_cast<const f4v*>(As + (16 * rb + (lane & 15)) * XS + 16 * G + 4 * (lane >> 4));
+            }
             f4v b[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
@@ -235,7 +262,7 @@ __global__ void __launch_bounds__(256) axis_mfma(const float* __restrict__ mat16
 #pragma unroll
                     for (int cb = 0; cb < NCB; ++cb)
                         acc[rb][cb] =
-                            __builtin_amdgcn_mfma_f32_16x16x4f32(a[G][rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(ag[rb][s], b[cb][s], acc[rb][cb], 0, 0, 0);
         }
         __syncthreads();
         float* Ys = Xt;   // Ys[row][column], pitch YP
