@@ -13,6 +13,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -39,15 +40,19 @@ def build(verbose: bool = False) -> str:
              "-I", os.path.join(HERE, "..", "include"), "-Wall", "-Wno-unused-result"]
     tmp = tempfile.mkdtemp(prefix="dsbt_build_")
     try:
-        objs = []
-        for src in SOURCES:
+        def compile_one(src: str) -> str:
             obj = os.path.join(tmp, src + ".o")
             lang = ["-x", "hip"] if src.endswith((".hip", "capi.cpp", "autotune.cpp")) else []
             cmd = [cc, *flags, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             subprocess.run(cmd, check=True)
-            objs.append(obj)
+            return obj
+
+        # translation units are independent: compile them side by side
+        jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(max_workers=jobs) as pool:
+            objs = list(pool.map(compile_one, SOURCES))
         out_tmp = LIB + ".tmp"
         cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", out_tmp, "-lpthread"]
         if verbose:

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -55,73 +56,43 @@ int ilog2(int n) {
     return l;
 }
 
-// A unit complex number (c, s) rounded to FP32 with |z| as close to one as the
-// neighbouring roundings allow.  Rounding cos and sin separately leaves
-// |z|^2 - 1 of the order of the FP32 epsilon with a fixed sign per table
-// entry, which repeated steps would accumulate into a norm drift.
-float2 unit_pair(double c, double s) {
-    const float c0 = (float)c, s0 = (float)s;
-    float best_c = c0, best_s = s0;
-    double best = 1e300;
-    for (int dc = -1; dc <= 1; ++dc) {
-        for (int ds = -1; ds <= 1; ++ds) {
-            float cc = c0, ss = s0;
-            if (dc) cc = std::nextafter(c0, dc > 0 ? 2.0f : -2.0f);
-            if (ds) ss = std::nextafter(s0, ds > 0 ? 2.0f : -2.0f);
-            // stay within one ulp of the exact value
-            if (std::fabs((double)cc - c) > 2.0 * std::fabs((double)std::nextafter(c0, 2.0f) - c0)) continue;
-            if (std::fabs((double)ss - s) > 2.0 * std::fabs((double)std::nextafter(s0, 2.0f) - s0)) continue;
-            const double m = std::fabs((double)cc * cc + (double)ss * ss - 1.0);
-            if (m < best) {
-                best = m;
-                best_c = cc;
-                best_s = ss;
-            }
-        }
-    }
-    return make_float2(best_c, best_s);
-}
-
-// Phase factor exp(-i a), the angle reduced mod 2 pi in FP64.
-float2 unit_phase(double a) {
-    const double twopi = 6.283185307179586476925286766559;
-    a -= twopi * std::nearbyint(a / twopi);
-    return unit_pair(std::cos(a), -std::sin(a));
-}
-
-
-// exp(-i a) for every angle a, reduced mod 2 pi in FP64: FP64 pairs for
-// complex128 plans, the nearest unit-modulus FP32 pairs for complex64 plans.
-std::vector<unsigned char> phase_table(const std::vector<double>& ang, bool fp64) {
-    const double twopi = 6.283185307179586476925286766559;
-    std::vector<unsigned char> out(ang.size() * (fp64 ? sizeof(double2) : sizeof(float2)));
-    for (size_t i = 0; i < ang.size(); ++i) {
+// Complex factors z_i (FP64) as a device table: FP64 pairs for plans with FP64
+// arithmetic; for FP32 arithmetic the hi parts (nearest FP32 values) of all n
+// factors followed by their lo parts (FP32 roundings of z - hi), which the
+// kernels multiply as z hi + z lo (kernels.h, FChan).
+std::vector<unsigned char> factor_table(const std::vector<double2>& z, bool fp64) {
+    const size_t n = z.size();
+    std::vector<unsigned char> out(n * (fp64 ? sizeof(double2) : 2 * sizeof(float2)));
+    for (size_t i = 0; i < n; ++i) {
         if (fp64) {
-            const double a = ang[i] - twopi * std::nearbyint(ang[i] / twopi);
-            const double2 z = make_double2(std::cos(a), -std::sin(a));
-            std::memcpy(out.data() + i * sizeof(double2), &z, sizeof(z));
+            std::memcpy(out.data() + i * sizeof(double2), &z[i], sizeof(double2));
         } else {
-            const float2 z = unit_phase(ang[i]);
-            std::memcpy(out.data() + i * sizeof(float2), &z, sizeof(z));
+            const float2 h = make_float2((float)z[i].x, (float)z[i].y);
+            const float2 l = make_float2((float)(z[i].x - (double)h.x), (float)(z[i].y - (double)h.y));
+            std::memcpy(out.data() + i * sizeof(float2), &h, sizeof(h));
+            std::memcpy(out.data() + (n + i) * sizeof(float2), &l, sizeof(l));
         }
     }
     return out;
+}
+
+// exp(-i a) for every angle a, reduced mod 2 pi in FP64.
+std::vector<unsigned char> phase_table(const std::vector<double>& ang, bool fp64) {
+    const double twopi = 6.283185307179586476925286766559;
+    std::vector<double2> z(ang.size());
+    for (size_t i = 0; i < ang.size(); ++i) {
+        const double a = ang[i] - twopi * std::nearbyint(ang[i] / twopi);
+        z[i] = make_double2(std::cos(a), -std::sin(a));
+    }
+    return factor_table(z, fp64);
 }
 
 // exp(-a) for every exponent a (imaginary time, t -> -i t): real factors stored
 // as complex values with zero imaginary part, in the layout of phase_table.
 std::vector<unsigned char> decay_table(const std::vector<double>& ex, bool fp64) {
-    std::vector<unsigned char> out(ex.size() * (fp64 ? sizeof(double2) : sizeof(float2)));
-    for (size_t i = 0; i < ex.size(); ++i) {
-        if (fp64) {
-            const double2 z = make_double2(std::exp(-ex[i]), 0.0);
-            std::memcpy(out.data() + i * sizeof(double2), &z, sizeof(z));
-        } else {
-            const float2 z = make_float2((float)std::exp(-ex[i]), 0.0f);
-            std::memcpy(out.data() + i * sizeof(float2), &z, sizeof(z));
-        }
-    }
-    return out;
+    std::vector<double2> z(ex.size());
+    for (size_t i = 0; i < ex.size(); ++i) z[i] = make_double2(std::exp(-ex[i]), 0.0);
+    return factor_table(z, fp64);
 }
 
 }  // namespace
@@ -240,23 +211,19 @@ struct dsbt_plan_s {
 
 namespace {
 
-// Complex table (re, im pairs) of unit numbers in the data precision.
+// Complex table (re, im pairs, FP64 values v) of unit numbers in the arithmetic
+// precision: FP64 as is; FP32 as the hi table followed by the lo table
+// (factor_table).  Returns the hi table; *lo receives the lo table (FP32) or
+// nullptr.
 template <typename T>
-void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s) {
-    std::vector<T> h(v.size());
-    for (size_t i = 0; i + 1 < v.size(); i += 2) {
-        if constexpr (sizeof(T) == sizeof(float)) {
-            const float2 z = unit_pair(v[i], v[i + 1]);
-            h[i] = z.x;
-            h[i + 1] = z.y;
-        } else {
-            h[i] = v[i];
-            h[i + 1] = v[i + 1];
-        }
-    }
-    void* d = P->dalloc(h.size() * sizeof(T));
-    hip_check(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_t s, const void** lo) {
+    std::vector<double2> z(v.size() / 2);
+    for (size_t i = 0; i < z.size(); ++i) z[i] = make_double2(v[2 * i], v[2 * i + 1]);
+    const std::vector<unsigned char> h = factor_table(z, sizeof(T) == sizeof(double));
+    void* d = P->dalloc(h.size());
+    hip_check(hipMemcpyAsync(d, h.data(), h.size(), hipMemcpyHostToDevice, s), "upload");
     hip_check(hipStreamSynchronize(s), "upload sync");
+    *lo = sizeof(T) == sizeof(float) ? static_cast<const unsigned char*>(d) + z.size() * sizeof(float2) : nullptr;
     return d;
 }
 
@@ -439,13 +406,16 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         }
         tabs[ell] = t;
     }
-    // twiddles per N
-    std::map<int, std::pair<const void*, const void*>> twd;
+    // twiddles per N: pass tables, post-twiddles and their lo parts
+    std::map<int, std::array<const void*, 4>> twd;
     for (auto& g : P->groups) {
         if (twd.count(g.N)) continue;
         std::vector<double> tw, post;
         dsbt::fft_twiddles(g.N, tw, post);
-        twd[g.N] = {upload_unit_table<T>(P, tw, s), upload_unit_table<T>(P, post, s)};
+        std::array<const void*, 4> a{};
+        a[0] = upload_unit_table<T>(P, tw, s, &a[1]);
+        a[2] = upload_unit_table<T>(P, post, s, &a[3]);
+        twd[g.N] = a;
     }
     // channel descriptors
     P->h_fchans.resize(nch);
@@ -459,8 +429,10 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         f.p = dsbt::parity_p(x.ell);
         const int sg = (((x.ell + 1) / 2) % 2) ? -1 : 1;
         f.sign = (P->opts.sign == DSBT_SIGN_PRINTED_F) ? 1.0f : (float)sg;
-        f.tw = twd[x.N].first;
-        f.post = twd[x.N].second;
+        f.tw = twd[x.N][0];
+        f.tw_lo = twd[x.N][1];
+        f.post = twd[x.N][2];
+        f.post_lo = twd[x.N][3];
         P->h_fchans[c] = f;
         P->maxN = std::max(P->maxN, x.N);
     }
@@ -956,24 +928,31 @@ dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32
             hip_check(hipMemcpy(p->d_echans, ec.data(), sizeof(dsbt::EChan) * ec.size(), hipMemcpyHostToDevice),
                       "echans");
         }
-        // refresh descriptors with the phase pointers
+        // refresh descriptors with the phase pointers (FP32 plans: the lo parts
+        // follow the hi parts of all n points)
         for (size_t c = 0; c < p->ch.size(); ++c) {
-            p->h_fchans[c].vphase = static_cast<const unsigned char*>(p->d_vphase) + p->cmp_bytes * p->ch[c].offset;
+            const auto* base = static_cast<const unsigned char*>(p->d_vphase);
+            p->h_fchans[c].vphase = base + p->cmp_bytes * p->ch[c].offset;
+            p->h_fchans[c].vphase_lo = fp64 ? nullptr : base + p->cmp_bytes * (n + p->ch[c].offset);
             p->h_fchans[c].vangle = p->d_vangle + p->ch[c].offset;
         }
         hip_check(hipMemcpy(p->d_fchans, p->h_fchans.data(), sizeof(dsbt::FChan) * p->ch.size(),
                             hipMemcpyHostToDevice), "fchans");
         upload_fchans_n(p);
-        std::map<int64_t, void*> by_off;
+        std::map<int64_t, const dsbt_plan_s::Group*> by_off;
         for (auto& g : p->groups)
-            for (int c : g.chans) by_off[p->ch[c].offset] = g.d_kphase;
+            for (int c : g.chans) by_off[p->ch[c].offset] = &g;
         auto refresh = [&](std::vector<dsbt::MItem>& v, dsbt::MItem* d) {
-            for (auto& it : v)
-                if (it.nch > 0) it.kphase = by_off[it.off[0]];
+            for (auto& it : v) {
+                if (it.nch <= 0) continue;
+                const auto* g = by_off[it.off[0]];
+                it.kphase = g->d_kphase;
+                it.kphase_lo = fp64 ? nullptr : static_cast<const unsigned char*>(g->d_kphase) + sizeof(float2) * g->N;
+            }
             if (d) hip_check(hipMemcpy(d, v.data(), sizeof(dsbt::MItem) * v.size(), hipMemcpyHostToDevice), "items");
         };
         if (p->d_lchans) {
-            for (auto& x : p->h_lchans) x.kphase = by_off[x.off];
+            for (auto& x : p->h_lchans) x.kphase = by_off[x.off]->d_kphase;
             hip_check(hipMemcpy(p->d_lchans, p->h_lchans.data(), sizeof(dsbt::LChan) * p->h_lchans.size(),
                                 hipMemcpyHostToDevice), "monomial channels");
         }

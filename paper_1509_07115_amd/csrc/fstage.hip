@@ -13,8 +13,10 @@
 // thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
 // pass for the remaining factor), data stay in LDS with one pad slot per 32
 // complex values.  Twiddles: per pass a table of every power a butterfly
-// needs, one 16-byte aligned row per butterfly class, built in FP64 (the
-// FP32 entries are the unit-modulus roundings).
+// needs, one 16-byte aligned row per butterfly class, built in FP64; FP32
+// plans carry every twiddle and phase factor as hi + lo parts (kernels.h), so
+// that no product by a fixed unit number or constant changes the modulus of
+// the data systematically.
 #include "kernels.h"
 
 namespace dsbt {
@@ -31,10 +33,9 @@ template <typename V> __device__ __forceinline__ V f_mul(V a, V b) {
 template <typename V, typename S> __device__ __forceinline__ V f_scale(V a, S s) { return {a.x * s, a.y * s}; }
 
 // Multiplication by a constant c = hi + lo that is not representable in FP32
-// (sqrt(1/2), sqrt(2/N) for even log2 N): a x hi + x lo.  A product with the
-// rounded constant alone scales every value by the same relative error, which
-// repeated transforms would accumulate into a norm drift; the split product
-// leaves only the final rounding.  FP64 data use hi alone (lo = 0).
+// (sqrt(1/2), sqrt(2/N) for even log2 N): mul_const (kernels.h), so that the
+// rounding of the constant does not scale every value by the same factor.
+// FP64 arithmetic uses hi alone (lo = 0).
 template <typename T> struct Split {
     T hi, lo;
 };
@@ -45,8 +46,23 @@ __device__ __forceinline__ Split<T> split_const(double c) {
 }
 template <typename T>
 __device__ __forceinline__ T s_mul(T x, Split<T> c) {
-    if constexpr (sizeof(T) == sizeof(float)) return __builtin_fmaf(x, c.lo, x * c.hi);
+    if constexpr (sizeof(T) == sizeof(float)) return mul_const(x, c.hi, c.lo);
     else return x * c.hi;
+}
+
+// A unit number w = h + l (l = 0 for FP64 arithmetic) and a product by it.
+template <typename V> struct Unit {
+    V h, l;
+};
+template <typename V>
+__device__ __forceinline__ V u_mul(V a, const Unit<V>& w) {
+    if constexpr (sizeof(V) == sizeof(float2)) return mul_unit(a, w.h, w.l);
+    else return f_mul(a, w.h);
+}
+template <typename V>
+__device__ __forceinline__ Unit<V> unit_at(const V* hi, const V* lo, int i) {
+    if constexpr (sizeof(V) == sizeof(float2)) return {hi[i], lo[i]};
+    else return {hi[i], V{0, 0}};
 }
 template <typename V, typename T>
 __device__ __forceinline__ V f_scale(V a, Split<T> c) { return {s_mul(a.x, c), s_mul(a.y, c)}; }
@@ -112,7 +128,8 @@ __device__ __forceinline__ void load_row(const typename CV<T>::t* row, typename 
 // One Stockham pass of radix R on the channel at buf (padded indexing);
 // thread t of the channel owns butterflies j = t + u N/8, u < 8/R.
 template <typename T, int N, int R>
-__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const typename CV<T>::t* tw, int t) {
+__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const typename CV<T>::t* tw,
+                                         const typename CV<T>::t* twl, int t) {
     using V = typename CV<T>::t;
     constexpr int NR = N / R, U = 8 / R;
     V v[U][R];
@@ -129,8 +146,15 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
             // butterfly of a pass with few distinct w
             V wv[R];
             load_row<T, R>(tw + jm * R, wv);
+            if constexpr (sizeof(T) == sizeof(float)) {
+                V wl[R];
+                load_row<T, R>(twl + jm * R, wl);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], wv[r]);
+                for (int r = 1; r < R; ++r) v[u][r] = mul_unit(v[u][r], wv[r], wl[r]);
+            } else {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], wv[r]);
+            }
         }
         if constexpr (R == 8) dft8<T>(v[u]);
         else if constexpr (R == 4) dft4<T>(v[u]);
@@ -148,54 +172,46 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
     lds_barrier();
 }
 
-// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R.
+// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R
+// (twl: their lo parts, FP32 only).
 template <typename T, int N>
-__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<T>::t* tw, int t) {
+__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<T>::t* tw,
+                                      const typename CV<T>::t* twl, int t) {
     constexpr int L = __builtin_ctz(N);
     int Ns = 1, off = 0;
 #pragma unroll
     for (int s = 0; s < L / 3; ++s) {
-        fft_pass<T, N, 8>(buf, Ns, tw + off, t);
+        fft_pass<T, N, 8>(buf, Ns, tw + off, twl + off, t);
         if (Ns > 1) off += Ns * 8;
         Ns *= 8;
     }
-    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw + off, t);
-    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw + off, t);
+    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw + off, twl + off, t);
+    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw + off, twl + off, t);
 }
 
+// The potential factor exp(-i s V tau/2) of point i: from the plan's table
+// when every strength is one, else from the FP64 angle s V tau/2 reduced mod
+// 2 pi (FP64 sine and cosine, split into hi + lo for FP32 arithmetic).
 template <typename V>
-__device__ __forceinline__ V phase_factor(const FChan& c, int i, const PhaseArgs& ph);
-
-template <>
-__device__ __forceinline__ float2 phase_factor<float2>(const FChan& c, int i, const PhaseArgs& ph) {
-    float2 z;
+__device__ __forceinline__ Unit<V> phase_factor(const FChan& c, int i, const PhaseArgs& ph) {
+    Unit<V> z;
     if (ph.scale == nullptr) {
-        z = static_cast<const float2*>(c.vphase)[i];
-    } else {
-        double a = (double)ph.scale[ph.step] * c.vangle[i];
-        const double twopi = 6.283185307179586476925286766559;
-        a -= twopi * rint(a / twopi);
-        float sn, cs;
-        sincosf((float)a, &sn, &cs);
-        z = make_float2(cs, -sn);
-    }
-    if (ph.conj) z.y = -z.y;
-    return z;
-}
-template <>
-__device__ __forceinline__ double2 phase_factor<double2>(const FChan& c, int i, const PhaseArgs& ph) {
-    double2 z;
-    if (ph.scale == nullptr) {
-        z = static_cast<const double2*>(c.vphase)[i];
+        z = unit_at(static_cast<const V*>(c.vphase), static_cast<const V*>(c.vphase_lo), i);
     } else {
         double a = (double)ph.scale[ph.step] * c.vangle[i];
         const double twopi = 6.283185307179586476925286766559;
         a -= twopi * rint(a / twopi);
         double sn, cs;
         sincos(a, &sn, &cs);
-        z = make_double2(cs, -sn);
+        using T = decltype(V{}.x);
+        const T hc = (T)cs, hs = (T)(-sn);
+        z.h = V{hc, hs};
+        z.l = V{(T)(cs - (double)hc), (T)(-sn - (double)hs)};
     }
-    if (ph.conj) z.y = -z.y;
+    if (ph.conj) {
+        z.h.y = -z.h.y;
+        z.l.y = -z.l.y;
+    }
     return z;
 }
 
@@ -229,7 +245,9 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     const bool live = cidx < nch;
     const FChan c = chans[live ? cidx : nch - 1];
     const V* tw = reinterpret_cast<const V*>(c.tw);
+    const V* twl = reinterpret_cast<const V*>(c.tw_lo);
     const V* post = reinterpret_cast<const V*>(c.post);
+    const V* postl = reinterpret_cast<const V*>(c.post_lo);
     // orthonormal scales sqrt(1/N) (k = 0) and sqrt(2/N), with the sign, in FP64
     const double d0 = (double)c.sign * sqrt(1.0 / N), d1 = (double)c.sign * sqrt(2.0 / N);
     const Split<T> sc0 = split_const<T>(INV ? d0 : 0.5 * d0), sc1 = split_const<T>(INV ? d1 : 0.5 * d1);
@@ -243,8 +261,8 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 const typename Pair<S>::t w = *reinterpret_cast<const typename Pair<S>::t*>(x + 2 * j);
                 V a = to_prec<V>(SV{w[0], w[1]}), b = to_prec<V>(SV{w[2], w[3]});
                 if (ph.use) {
-                    a = f_mul(a, phase_factor<V>(c, 2 * j, ph));
-                    b = f_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                    a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
+                    b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
                 }
                 if (c.p) b = {-b.x, -b.y};
                 buf[pidx(j)] = a;
@@ -252,7 +270,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
             }
         }
         lds_barrier();
-        fft_n<T, N>(buf, tw, t);
+        fft_n<T, N>(buf, tw, twl, t);
         if (live) {
             // X_k for k = 2m, 2m + 1, stored as one 16-byte pair (reversed for the sine form)
             SV* y = dst + c.off;
@@ -263,10 +281,17 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int k = 2 * m + e;
-                    const V w = post[k];
+                    const Unit<V> w = unit_at(post, postl, k);
                     const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
-                    // w a + conj(w) b
-                    V X = {w.x * a.x - w.y * a.y + w.x * b.x + w.y * b.y, w.x * a.y + w.y * a.x + w.x * b.y - w.y * b.x};
+                    // w a + conj(w) b = (w.x (a.x + b.x) + w.y (b.y - a.y), w.x (a.y + b.y) + w.y (a.x - b.x))
+                    const T sx = a.x + b.x, dy = b.y - a.y, sy = a.y + b.y, dx = a.x - b.x;
+                    V X;
+                    if constexpr (sizeof(T) == sizeof(float)) {
+                        X = {__builtin_fmaf(w.h.x, sx, __builtin_fmaf(w.h.y, dy, w.l.x * sx + w.l.y * dy)),
+                             __builtin_fmaf(w.h.x, sy, __builtin_fmaf(w.h.y, dx, w.l.x * sy + w.l.y * dx))};
+                    } else {
+                        X = {w.h.x * sx + w.h.y * dy, w.h.x * sy + w.h.y * dx};
+                    }
                     o[e] = to_prec<SV>(f_scale(X, k == 0 ? sc0 : sc1));
                 }
                 if (c.p)
@@ -302,14 +327,14 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 u8[u] = buf[0];
             } else {
                 const V s = f_add(buf[pidx(j)], f_posi(buf[pidx(N - j)]));
-                u8[u] = f_scale(f_mul(post[j], s), (T)0.5);
+                u8[u] = f_scale(u_mul(s, unit_at(post, postl, j)), (T)0.5);
             }
         }
         lds_barrier();
 #pragma unroll
         for (int u = 0; u < 8; ++u) buf[pidx(t + u * TPC)] = u8[u];
         lds_barrier();
-        fft_n<T, N>(buf, tw, t);
+        fft_n<T, N>(buf, tw, twl, t);
         if (live) {
             // v_j and v_{N-1-j} go out as the pair x_{2j}, x_{2j+1} (one 16-byte store)
             SV* x = dst + c.off;
@@ -319,8 +344,8 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 V a = buf[pidx(j)], b = buf[pidx(N - 1 - j)];
                 if (c.p) b = {-b.x, -b.y};
                 if (ph.use) {
-                    a = f_mul(a, phase_factor<V>(c, 2 * j, ph));
-                    b = f_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                    a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
+                    b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
                 }
                 const SV sa = to_prec<SV>(a), sb = to_prec<SV>(b);
                 *reinterpret_cast<typename Pair<S>::t*>(x + 2 * j) = typename Pair<S>::t{sa.x, sa.y, sb.x, sb.y};

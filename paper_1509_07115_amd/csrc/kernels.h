@@ -9,14 +9,24 @@ constexpr int kBlock = 256;          // threads per workgroup of every transform
 constexpr int kMaxChanPerItem = 16;  // channels sharing one moment-table pass
 
 // One channel of the sine/cosine stage (Sec. 2.2, eq. csFourierBasis).
+//
+// Unit numbers (twiddles, phase factors) of FP32 plans are carried as two FP32
+// complex tables of the same layout, hi = the nearest FP32 value and lo = the
+// FP32 rounding of the rest, and multiplied as z hi + z lo: the FP32 value
+// alone has a modulus 1 + O(eps) with a fixed sign per entry, and repeated
+// transforms of the same data would turn that into a norm drift.  FP64 plans
+// have no lo tables (nullptr).
 struct FChan {
     int64_t off;          // element offset of the channel in every data buffer
     int N, log2N;
     int p;                // 1: even l (DST-II), 0: odd l (DCT-II)
     float sign;           // (-1)^ceil(l/2), or +1 for the printed F
-    const void* tw;       // FFT pass tables (fft_twiddles), complex of the data precision
+    const void* tw;       // FFT pass tables (fft_twiddles), complex of the arithmetic precision
+    const void* tw_lo;    // FP32 plans: the lo parts of tw
     const void* post;     // exp(-i pi t/(2N)), t < N
-    const void* vphase;   // unit-modulus exp(-i V tau/2) per point (complex of the data precision), or nullptr
+    const void* post_lo;  // FP32 plans: the lo parts of post
+    const void* vphase;   // exp(-i V tau/2) per point (complex of the arithmetic precision), or nullptr
+    const void* vphase_lo;// FP32 plans: the lo parts of vphase
     const double* vangle; // V tau/2 per point (FP64), or nullptr
 };
 
@@ -28,7 +38,8 @@ struct MItem {
     const void* mf_f;      // MFMA operand layout of the forward blocks (FP32, or FP64 for FP64
                            // arithmetic on complex64 data), or nullptr
     const void* mf_i;      // MFMA operand layout of the inverse blocks
-    const void* kphase;    // unit-modulus exp(-i K_n tau) per slot (complex of the data precision), or nullptr
+    const void* kphase;    // exp(-i K_n tau) per slot (complex of the arithmetic precision), or nullptr
+    const void* kphase_lo; // FP32 plans: the lo parts of kphase (see FChan)
     int B, k, R, NT, p, nch;
     int NB;                // 16-row blocks of the padded block size R16 = 16 NB (1, 2, 4 or 8)
     int NCB;               // 8-channel column blocks of the item (mfma_ncb on the matrix-core path)
@@ -78,6 +89,27 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// x c for a constant c = hi + lo (hi its FP32 rounding).  The product with hi
+// alone scales every value by the same relative error hi/c - 1, which repeated
+// transforms turn into a norm drift; so the rounding error of p = x hi is
+// recovered exactly (e = fma(x, hi, -p)) and added back with x lo, leaving a
+// result within about one rounding of x c.
+__device__ __forceinline__ float mul_const(float x, float hi, float lo) {
+#pragma clang fp contract(off)   // p must be the rounded product, and p + (...) a plain sum
+    const float p = x * hi;
+    const float e = __builtin_fmaf(x, hi, -p);
+    return p + __builtin_fmaf(x, lo, e);
+}
+
+// z w for a unit number w = h + l carried as FP32 hi and lo parts (FChan):
+// the small product z l first, then the two main products, each fused.
+__device__ __forceinline__ float2 mul_unit(float2 z, float2 h, float2 l) {
+    const float cx = __builtin_fmaf(z.x, l.x, -(z.y * l.y));
+    const float cy = __builtin_fmaf(z.x, l.y, z.y * l.x);
+    return make_float2(__builtin_fmaf(z.x, h.x, __builtin_fmaf(-z.y, h.y, cx)),
+                       __builtin_fmaf(z.x, h.y, __builtin_fmaf(z.y, h.x, cy)));
 }
 
 // Launchers.  T = float (complex64 data) or double (complex128 data).

@@ -40,6 +40,21 @@ template <typename V, typename W> __device__ __forceinline__ V cvt(W w) {
     return {(decltype(V{}.x))w.x, (decltype(V{}.x))w.y};
 }
 
+// v times the kinetic factor of slot i of an item (conjugated for the adjoint
+// step); FP32 factors carry hi + lo parts (kernels.h).
+template <typename V>
+__device__ __forceinline__ V kin_factor(const MItem& it, V v, int i, bool cj) {
+    V z = static_cast<const V*>(it.kphase)[i];
+    if (cj) z.y = -z.y;
+    if constexpr (sizeof(V) == sizeof(float2)) {
+        V l = static_cast<const V*>(it.kphase_lo)[i];
+        if (cj) l.y = -l.y;
+        return mul_unit(v, z, l);
+    } else {
+        return cmul(v, z);
+    }
+}
+
 // T: arithmetic (and table) precision; S: data precision in memory.
 template <typename T, typename S, int RP>
 __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items,
@@ -58,7 +73,17 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
     const int r = tid % RP, cs = tid / RP;
     const T* tab = reinterpret_cast<const T*>(inverse ? it.tab_i : it.tab_f);
     const T sgn = p ? (T)-1 : (T)1;      // completion rows = (-1)^p mu_NT
-    const T w0 = p ? (T)1 : (T)0.70710678118654752440;  // w_m at m = 0 (odd l)
+    // w_m at m = 0 (odd l): sqrt(1/2), as a compensated FP32 product (kernels.h)
+    auto w0_scale = [&](V v) -> V {
+        if (p) return v;
+        constexpr double h = 0.70710678118654752440;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            constexpr float hi = (float)h, lo = (float)(h - (double)(float)h);
+            return {mul_const(v.x, hi, lo), mul_const(v.y, hi, lo)};
+        } else {
+            return cscale(v, (T)h);
+        }
+    };
 
     // initial moments: forward mu_0 = 0; inverse lam_NT = (-1)^p b[0..k)
     for (int e = tid; e < nch * k; e += kBlock) {
@@ -66,11 +91,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
         V v = {(T)0, (T)0};
         if (inverse) {
             v = cvt<V>(src[it.off[ch] + kk]);
-            if (ph.use && it.kphase) {
-                V z = static_cast<const V*>(it.kphase)[kk];
-                if (ph.conj) z.y = -z.y;
-                v = cmul(v, z);
-            }
+            if (ph.use && it.kphase) v = kin_factor(it, v, kk, ph.conj != 0);
             v = cscale(v, sgn);
         }
         X[ch * R + B + kk] = v;
@@ -83,11 +104,9 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
             const int slot = J * B + s;
             V v = cvt<V>(src[it.off[ch] + slot]);
             if (!inverse) {
-                if (slot == 0) v = cscale(v, w0);
+                if (slot == 0) v = w0_scale(v);
             } else if (ph.use && it.kphase) {
-                V z = static_cast<const V*>(it.kphase)[slot];
-                if (ph.conj) z.y = -z.y;
-                v = cmul(v, z);
+                v = kin_factor(it, v, slot, ph.conj != 0);
             }
             X[ch * R + s] = v;
         }
@@ -123,13 +142,9 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
                     V v = acc[u];
                     if (!inverse) {
                         if (J == 0 && r < k) continue;   // completion rows written last
-                        if (ph.use && it.kphase) {
-                            V z = static_cast<const V*>(it.kphase)[slot];
-                            if (ph.conj) z.y = -z.y;
-                            v = cmul(v, z);
-                        }
+                        if (ph.use && it.kphase) v = kin_factor(it, v, slot, ph.conj != 0);
                     } else if (slot == 0) {
-                        v = cscale(v, w0);
+                        v = w0_scale(v);
                     }
                     dst[it.off[ch] + slot] = cvt<SV>(v);
                 }
@@ -141,11 +156,7 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
         for (int e = tid; e < nch * k; e += kBlock) {
             const int ch = e / k, kk = e % k;
             V v = cscale(X[ch * R + B + kk], sgn);
-            if (ph.use && it.kphase) {
-                V z = static_cast<const V*>(it.kphase)[kk];
-                if (ph.conj) z.y = -z.y;
-                v = cmul(v, z);
-            }
+            if (ph.use && it.kphase) v = kin_factor(it, v, kk, ph.conj != 0);
             dst[it.off[ch] + kk] = cvt<SV>(v);
         }
     }

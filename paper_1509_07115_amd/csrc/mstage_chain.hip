@@ -158,6 +158,7 @@ struct Pipe {
     D DSBT_GLOBAL* dst;
     const T DSBT_GLOBAL* tab;
     const V2 DSBT_GLOBAL* kphase;   // complex of the arithmetic precision
+    const V2 DSBT_GLOBAL* kphase_lo;   // FP32: lo parts of the kinetic factors (kernels.h)
     T* xring;
     T* qring;
     T* mring;
@@ -184,6 +185,7 @@ struct Pipe {
         conj = ph.conj != 0;
         tab = as_global(static_cast<const T*>(INV ? it.mf_i : it.mf_f));
         kphase = as_global(reinterpret_cast<const V2*>(it.kphase));
+        kphase_lo = as_global(reinterpret_cast<const V2*>(it.kphase_lo));
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             e0[cb] = 2 * it.off[8 * cb + (col >> 1)] + (col & 1);
@@ -227,11 +229,18 @@ struct Pipe {
             }
         }
     }
-    // x (w.x + i w.y) on the lane pair (re, im) of one complex value
-    static __device__ T phase(T x, V2 w, bool im, bool cj) {
+    // x (w.x + i w.y) on the lane pair (re, im) of one complex value; FP32
+    // factors carry hi (w) and lo (wl) parts (kernels.h)
+    static __device__ T phase(T x, V2 w, V2 wl, bool im, bool cj) {
         const T y = __shfl_xor(x, 1, 64);
-        const T s = cj ? -w.y : w.y;
-        return im ? x * w.x + y * s : x * w.x - y * s;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            const float2 z = im ? make_float2(y, x) : make_float2(x, y);
+            const float2 r = mul_unit(z, make_float2(w.x, cj ? -w.y : w.y), make_float2(wl.x, cj ? -wl.y : wl.y));
+            return im ? r.y : r.x;
+        } else {
+            const T s = cj ? -w.y : w.y;
+            return im ? x * w.x + y * s : x * w.x - y * s;
+        }
     }
     static __device__ V4 ld4(const T* p) { return *reinterpret_cast<const V4*>(p); }
     static __device__ void st4(T* p, V4 v) { *reinterpret_cast<V4*>(p) = v; }
@@ -463,7 +472,10 @@ struct Pipe {
             for (int j = 0; j < 4 * KB; ++j) {
                 const int row = 4 * j + q;
                 T x = sgn * bm[4 * KB * cb + j];
-                if constexpr (KPH) x = phase(x, kphase[row], col & 1, conj);
+                if constexpr (KPH) {
+                    const V2 wl = sizeof(T) == sizeof(float) ? kphase_lo[row] : V2{0, 0};
+                    x = phase(x, kphase[row], wl, col & 1, conj);
+                }
                 if (row < k) dst[e0[cb] + 2 * row] = (D)x;
             }
     }
@@ -479,10 +491,12 @@ struct Pipe {
         static constexpr int ND = (HI - LO) / 4;
         V4 a[kSets][ND + KB];
         V4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
+        V4 wl[kSets];                 // FP32: their lo parts
         T x[kPhase][NCB * 8];         // block cb: data chunk kc in x[.][8 cb + kc]
         T mu[kPhase][NCB * 4 * KB];
         V4 c0[2][NCB], c1[2][NCB];    // accumulators of tile t in [t % 2]
         V4 wq[2];                     // kinetic phases of tile t in [t % 2]
+        V4 wql[2];
     };
     template <int RB, int S>
     __device__ void out_load(Out<RB>& r, int t) const {
@@ -490,8 +504,11 @@ struct Pipe {
         const int J = tile(t);
         seg<Out<RB>::ND>(r.a[S], J, RB, Out<RB>::LO / 4);
         seg<KB>(r.a[S] + Out<RB>::ND, J, RB, 2);
-        if constexpr (KPH)
+        if constexpr (KPH) {
             r.w[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
+            if constexpr (sizeof(T) == sizeof(float))
+                r.wl[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase_lo + J * 32 + 16 * RB + 2 * (lane & 7));
+        }
     }
     // read-out of tile t from accumulators [P]: result layout -> (channel
     // 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through LDS, phase, 16-byte store
@@ -517,7 +534,15 @@ struct Pipe {
             if constexpr (KPH) {
                 const V4 w = r.wq[P];
                 const T s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
-                v = V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+                if constexpr (sizeof(T) == sizeof(float)) {
+                    const V4 l = r.wql[P];
+                    const T l1 = conj ? -l.y : l.y, l2 = conj ? -l.w : l.w;
+                    const float2 a = mul_unit(make_float2(v.x, v.y), make_float2(w.x, s1), make_float2(l.x, l1));
+                    const float2 b = mul_unit(make_float2(v.z, v.w), make_float2(w.z, s2), make_float2(l.z, l2));
+                    v = V4{a.x, a.y, b.x, b.y};
+                } else {
+                    v = V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+                }
             }
             // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
             *reinterpret_cast<DV4 DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) =
@@ -540,7 +565,10 @@ struct Pipe {
         for (int cb = 0; cb < NCB; ++cb) r.c0[P][cb] = r.c1[P][cb] = zero4();
         mac<LO, HI, 8>(r.c0[P], r.c1[P], r.a[S], r.x[S % kPhase] + LO);
         mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
-        if constexpr (KPH) r.wq[P] = r.w[S];
+        if constexpr (KPH) {
+            r.wq[P] = r.w[S];
+            if constexpr (sizeof(T) == sizeof(float)) r.wql[P] = r.wl[S];
+        }
     }
     template <int RB, int I0, bool FIRST, int I = 0>
     __device__ void out_phase(Out<RB>& r, int t0) const {

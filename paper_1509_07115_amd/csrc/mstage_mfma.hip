@@ -51,6 +51,7 @@ struct MfmaTile {
     float* Yt;   // [2][NCB][B][16]: tile results
     const float DSBT_GLOBAL* tab;
     const f2 DSBT_GLOBAL* kphase;
+    const f2 DSBT_GLOBAL* kphase_lo;
     int k, NT, tid, lane, rb;
     int cbs[UMAX];
     bool conj;
@@ -77,6 +78,7 @@ struct MfmaTile {
         Yt = lds + 2 * NCB * R16 * 16;
         tab = as_global(static_cast<const float*>(INV ? it.mf_i : it.mf_f));
         kphase = as_global(reinterpret_cast<const f2*>(it.kphase));
+        kphase_lo = as_global(reinterpret_cast<const f2*>(it.kphase_lo));
         conj = ph.conj != 0;
         // element e = (channel, slot): 4 consecutive slots of one channel per
         // 4 lanes (32-byte global segments), channels across lanes, so the LDS
@@ -95,7 +97,16 @@ struct MfmaTile {
     __device__ int tile_of(int step) const { return INV ? NT - 1 - step : step; }
     __device__ float* xt(int par, int cb, int row) const { return Xt + ((par * NCB + cb) * R16 + row) * 16; }
     __device__ float* yt(int par, int cb, int row) const { return Yt + ((par * NCB + cb) * B + row) * 16; }
-    static __device__ f2 cm(f2 x, f2 y) { return f2{x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x}; }
+    // x times the kinetic factor of slot i (hi + lo parts, kernels.h)
+    __device__ f2 kph(f2 x, int i) const {
+        f2 h = kphase[i], l = kphase_lo[i];
+        if (conj) {
+            h.y = -h.y;
+            l.y = -l.y;
+        }
+        const float2 r = mul_unit(make_float2(x.x, x.y), make_float2(h.x, h.y), make_float2(l.x, l.y));
+        return f2{r.x, r.y};
+    }
 
     template <int S>
     __device__ void load(int step) {   // issue the loads of one tile (clamped to the last) into set S
@@ -164,11 +175,7 @@ struct MfmaTile {
 #pragma unroll
         for (int i = 0; i < GM; ++i) {
             f2 v = *reinterpret_cast<const f2*>(Y + yofs[i]);
-            if constexpr (KPH) {
-                f2 z = kphase[J * B + sidx[i]];
-                if (conj) z.y = -z.y;
-                v = cm(v, z);
-            }
+            if constexpr (KPH) v = kph(v, J * B + sidx[i]);
             dst[gofs[i] + J * B] = v;   // forward: tile-0 completion slots are rewritten at the end
         }
     }
@@ -223,11 +230,7 @@ struct MfmaTile {
                 const int o = lofs[i] + B * 16;   // moment row B + s of the same column
                 f2 v = *reinterpret_cast<const f2*>(X + o);
                 v = f2{sgn * v.x, sgn * v.y};
-                if constexpr (KPH) {
-                    f2 z = kphase[sidx[i]];
-                    if (conj) z.y = -z.y;
-                    v = cm(v, z);
-                }
+                if constexpr (KPH) v = kph(v, sidx[i]);
                 dst[gofs[i]] = v;
             }
         }
