@@ -64,6 +64,7 @@ enum {
     DSBT_ERR_OOM = -3,           /* device or host allocation failed */
     DSBT_ERR_HIP = -4,           /* a HIP runtime call or kernel launch failed */
     DSBT_ERR_PLAN_MISMATCH = -5, /* call does not fit the plan (e.g. no potential set) */
+    DSBT_ERR_NONFINITE = -6,     /* checked plan: a NaN or infinity in the data (dsbt_plan_opts.check_finite) */
     DSBT_ERR_NO_DEVICE = -7      /* no HIP device is visible */
 };
 
@@ -101,7 +102,27 @@ typedef struct {
     int32_t tile;         /* moment tile B (power of two >= ceil((l+1)/2)); 0 = automatic */
     int32_t chans_per_block; /* channels per workgroup in the transform stage; 0 = automatic */
     int32_t algorithm;    /* DSBT_ALG_TILED (default) or DSBT_ALG_MONOMIAL, see below */
-    int32_t reserved[8];
+    int32_t check_finite; /* 0 (default) or 1: dsbt_forward, dsbt_inverse and dsbt_kinetic_step first
+                             scan every channel of their input for NaN and infinities, synchronise
+                             the stream and return DSBT_ERR_NONFINITE without touching the output if
+                             one is found; dsbt_kinetic_step also scans psi after its steps and
+                             returns DSBT_ERR_NONFINITE (psi then holds the result).  Checked calls
+                             synchronise, so they cannot be captured in a graph. */
+    int32_t reserved0;    /* 0 */
+    /* Device allocator of the plan (both or neither; NULL: hipMalloc / hipFree).
+     * Every device table, descriptor and plan-time scratch buffer of the plan is
+     * obtained from dev_alloc(bytes, alloc_ctx) -- 256-byte aligned device memory
+     * usable on any stream, or NULL on failure (then dsbt_plan_create returns
+     * DSBT_ERR_OOM after handing back what it got) -- and handed back through
+     * dev_free(ptr, alloc_ctx) by dsbt_plan_destroy or a failing create.  The
+     * callbacks are called from the thread that makes the plan call, never from
+     * a stream callback.  dsbt_plan_destroy does not synchronise: the caller
+     * ensures no enqueued work still reads the plan (a caching allocator that
+     * reuses freed blocks on other streams relies on that). */
+    void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+    void (*dev_free)(void* ptr, void* alloc_ctx);
+    void* alloc_ctx;
+    int32_t reserved[4];
 } dsbt_plan_opts;
 
 /* Moment-stage algorithm.  DSBT_ALG_TILED: the numerically stable tiled moment
@@ -277,6 +298,19 @@ dsbt_status dsbt_sht_potential_phase(dsbt_sht s, void* grid, const double* V0, c
  * it (i^l).  src and dst must not overlap (DSBT_ERR_INVALID_ARG). */
 dsbt_status dsbt_sht_momentum_order(dsbt_sht s, const void* src, void* dst, int32_t inverse, void* stream);
 
+/* Diagonal tables of the 3D split step, FP64, computed on the host and copied
+ * to the caller's device array (synchronises `stream`):
+ *   dsbt_sht_kinetic:     K[c Nr + i] = k_i^2 / 2 for coefficient channel c = q N_theta + t
+ *                         (l = |q - M| + t) and slot i, the kinetic diagonal of eq. KinMat with
+ *                         the momenta of dsbt_kinetic_momenta(Nr, l, rmax, kinetic);
+ *   dsbt_sht_momentum_pz: Pz[(j N_phi + k) Nr + n - 1] = -2 k~_n eta_j, n = 1..Nr, on the
+ *                         unified momentum grid k~_n = n pi / rmax (eq. tilde_k_grid), so that
+ *                         dsbt_sht_potential_phase(V1 = Pz, F = A) multiplies by
+ *                         exp(i A k~_n eta_j dt), the A.P factor of eq. H_DVR for A along z.
+ * Both arrays hold Nr N_theta N_phi doubles; rmax > 0 (else DSBT_ERR_INVALID_ARG). */
+dsbt_status dsbt_sht_kinetic(dsbt_sht y, double rmax, int32_t kinetic, double* K, void* stream);
+dsbt_status dsbt_sht_momentum_pz(dsbt_sht y, double rmax, double* Pz, void* stream);
+
 /* One 3D split step (Sec. 4.1) in place on a grid buffer, enqueued on `stream`.
  * p: a plan over the transform's channels (channel q N_theta + t: N = Nr, l = |m| + t,
  * offset (q N_theta + t) Nr) with the potential set to zero for this dt; work (and
@@ -285,8 +319,9 @@ dsbt_status dsbt_sht_momentum_order(dsbt_sht s, const void* src, void* dst, int3
  * U = V0 + F V1 (device FP64 grid arrays, either may be NULL).
  * Velocity gauge (A along z): the printed sequence through the momentum grid,
  * with K the kinetic energies per channel slot (device FP64, coefficient
- * layout) and Pz = -2 k~_n eta_j on the momentum grid (device FP64), so that
- * the A.P factor is exp(i A k~_n eta_j dt).  The first failing call's status
+ * layout, from dsbt_sht_kinetic) and Pz = -2 k~_n eta_j on the momentum grid
+ * (device FP64, from dsbt_sht_momentum_pz), so that the A.P factor is
+ * exp(i A k~_n eta_j dt).  The first failing call's status
  * is returned (later calls are not enqueued). */
 dsbt_status dsbt_step3d(dsbt_sht y, dsbt_plan p, void* grid, void* work, const double* V0, const double* V1, double F,
                         double dt, void* stream);

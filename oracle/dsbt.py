@@ -147,7 +147,6 @@ def dlop(ell: int, M: int, xmax: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 @functools.lru_cache(maxsize=64)
-@functools.lru_cache(maxsize=16)
 def fourier_matrix(N: int, ell: int, sign: bool = True) -> np.ndarray:
     """F[j, i], row j = n - p_l (n = p_l..N_l), column i = 0..N-1 (r_{i+1}).
 

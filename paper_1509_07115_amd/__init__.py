@@ -46,11 +46,16 @@ class Plan:
     kinetic: "plain" (k_n = n dk) or "corrected" (roots of eq. kcorr) momenta of the step.
     algorithm: "tiled" (default, the stable tiled moment form) or "monomial" (the paper's own
         monomial-moment fast multiplication of Sec. 2.6, FP64, complex128 plans only).
+    check_finite: scan transform and step inputs for NaN / infinities (``DSBT_ERR_NONFINITE``;
+        checked calls synchronise).
+    allocator: None (the library's hipMalloc), "torch" (PyTorch's caching allocator on the
+        current device and stream), or a pair (alloc(nbytes) -> int pointer or 0, free(ptr)) of
+        Python callables, passed as the plan's ``dev_alloc`` / ``dev_free``.
     """
 
     def __init__(self, channels: Sequence, precision: str = "c64", mode: str = "batched", tile: int = 0,
                  chans_per_block: int = 0, sign: bool = True, plan_where: str = "device", kinetic: str = "plain",
-                 algorithm: str = "tiled", stream=None, _create=True):
+                 algorithm: str = "tiled", check_finite: bool = False, allocator=None, stream=None, _create=True):
         self._lib = _lib.load()
         self._h = ctypes.c_void_p()
         self.precision = precision
@@ -61,9 +66,42 @@ class Plan:
         for i, (N, ell, rmax, off) in enumerate(self.channels):
             arr[i] = _lib.Channel(int(N), int(ell), float(rmax), int(off))
         opts = self._opts(precision, mode, tile, chans_per_block, sign, plan_where, kinetic, algorithm)
+        opts.check_finite = 1 if check_finite else 0
+        self._alloc_cbs = self._allocator(allocator, stream)
+        if self._alloc_cbs is not None:
+            opts.dev_alloc, opts.dev_free = self._alloc_cbs
         _lib.check(self._lib.dsbt_plan_create(ctypes.byref(self._h), arr, len(self.channels), ctypes.byref(opts),
                                               _stream_handle(stream)), "dsbt_plan_create")
         self._info()
+
+    @staticmethod
+    def _allocator(allocator, stream):
+        """ctypes callbacks for dsbt_plan_opts.dev_alloc / dev_free (kept alive by the plan)."""
+        if allocator is None:
+            return None
+        if allocator == "torch":
+            import torch
+            dev = torch.cuda.current_device()
+            st = torch.cuda.current_stream() if stream is None else stream
+
+            def alloc(nbytes):
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=st)
+
+            def free(ptr):
+                torch.cuda.caching_allocator_delete(ptr)
+        else:
+            alloc, free = allocator
+
+        def c_alloc(nbytes, _ctx):
+            try:
+                return int(alloc(nbytes)) or None
+            except Exception:   # reported to the library as a failed allocation (DSBT_ERR_OOM)
+                return None
+
+        def c_free(ptr, _ctx):
+            if ptr:
+                free(int(ptr))
+        return _lib.ALLOC_FN(c_alloc), _lib.FREE_FN(c_free)
 
     @staticmethod
     def _opts(precision, mode, tile, chans_per_block, sign, plan_where="device", kinetic="plain", algorithm="tiled"):
@@ -332,22 +370,23 @@ class AngularTransform:
                    "dsbt_sht_momentum_order")
         return dst
 
-    def kinetic(self, rmax: float, kinetic: str = "plain"):
-        """K_n = k_n^2/2 per channel slot (cuda float64, coefficient layout)."""
+    def kinetic(self, rmax: float, kinetic: str = "plain", stream=None):
+        """K_n = k_n^2/2 per channel slot (cuda float64, coefficient layout; ``dsbt_sht_kinetic``)."""
         import torch
-        out = np.zeros((len(self.lm()), self.Nr))
-        for c, (l, _) in enumerate(self.lm()):
-            out[c] = 0.5 * kinetic_momenta(self.Nr, l, rmax, kinetic) ** 2
-        return torch.from_numpy(out.reshape(-1)).cuda()
+        out = torch.empty(self.size, dtype=torch.float64, device="cuda")
+        kin = {"plain": _lib.DSBT_K_PLAIN, "corrected": _lib.DSBT_K_CORRECTED}[kinetic]
+        _lib.check(self._lib.dsbt_sht_kinetic(self._h, float(rmax), kin, ctypes.c_void_p(out.data_ptr()),
+                                              _stream_handle(stream)), "dsbt_sht_kinetic")
+        return out
 
-    def momentum_pz(self, rmax: float):
-        """-2 k~_n eta_j on the momentum grid [j][k][n] (cuda float64): with it as V1 and F = A,
-        ``potential_phase`` multiplies by exp(i A k~_n eta_j dt)."""
+    def momentum_pz(self, rmax: float, stream=None):
+        """-2 k~_n eta_j on the momentum grid [j][k][n] (cuda float64; ``dsbt_sht_momentum_pz``): with it
+        as V1 and F = A, ``potential_phase`` multiplies by exp(i A k~_n eta_j dt)."""
         import torch
-        eta = sht_grid(self.n_theta, self.n_phi)[0]
-        k = np.arange(1, self.Nr + 1) * (np.pi / rmax)
-        v = -2.0 * eta[:, None, None] * k[None, None, :] * np.ones((1, self.n_phi, 1))
-        return torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).cuda()
+        out = torch.empty(self.size, dtype=torch.float64, device="cuda")
+        _lib.check(self._lib.dsbt_sht_momentum_pz(self._h, float(rmax), ctypes.c_void_p(out.data_ptr()),
+                                                  _stream_handle(stream)), "dsbt_sht_momentum_pz")
+        return out
 
     def close(self):
         if self._h:

@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsbt.so")
 
 DSBT_OK = 0
+DSBT_ERR_OOM, DSBT_ERR_NONFINITE = -3, -6
 DSBT_C64, DSBT_C128, DSBT_C64_FP64 = 0, 1, 2
 DSBT_K_PLAIN, DSBT_K_CORRECTED = 0, 1
 DSBT_SIGN_C, DSBT_SIGN_PRINTED_F = 0, 1
@@ -19,7 +20,7 @@ DSBT_ALG_TILED, DSBT_ALG_MONOMIAL = 0, 1
 
 STATUS_NAMES = {
     0: "DSBT_OK", -1: "DSBT_ERR_INVALID_ARG", -2: "DSBT_ERR_UNSUPPORTED", -3: "DSBT_ERR_OOM",
-    -4: "DSBT_ERR_HIP", -5: "DSBT_ERR_PLAN_MISMATCH", -7: "DSBT_ERR_NO_DEVICE",
+    -4: "DSBT_ERR_HIP", -5: "DSBT_ERR_PLAN_MISMATCH", -6: "DSBT_ERR_NONFINITE", -7: "DSBT_ERR_NO_DEVICE",
 }
 
 # every symbol include/dsbt.h declares
@@ -30,7 +31,7 @@ EXPORTED = [
     "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
     "dsbt_kinetic_momenta", "dsbt_autotune", "dsbt_sht_grid", "dsbt_sht_host_tables", "dsbt_sht_create",
     "dsbt_sht_destroy", "dsbt_sht_forward", "dsbt_sht_inverse", "dsbt_sht_potential_phase",
-    "dsbt_sht_momentum_order", "dsbt_step3d", "dsbt_step3d_velocity",
+    "dsbt_sht_momentum_order", "dsbt_sht_kinetic", "dsbt_sht_momentum_pz", "dsbt_step3d", "dsbt_step3d_velocity",
     "dsbt_status_string", "dsbt_last_error",
 ]
 
@@ -40,11 +41,18 @@ class Channel(ctypes.Structure):
                 ("offset", ctypes.c_int64)]
 
 
+# dsbt_plan_opts.dev_alloc / dev_free
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("kinetic", ctypes.c_int32), ("sign", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("plan_where", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("chans_per_block", ctypes.c_int32), ("algorithm", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("check_finite", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class DsbtError(RuntimeError):
@@ -99,6 +107,8 @@ def load() -> ctypes.CDLL:
         "dsbt_sht_inverse": (i32, [P, P, P, P]),
         "dsbt_sht_potential_phase": (i32, [P, P, P, P, dbl, dbl, P]),
         "dsbt_sht_momentum_order": (i32, [P, P, P, i32, P]),
+        "dsbt_sht_kinetic": (i32, [P, dbl, i32, P, P]),
+        "dsbt_sht_momentum_pz": (i32, [P, dbl, P, P]),
         "dsbt_step3d": (i32, [P, P, P, P, P, P, dbl, dbl, P]),
         "dsbt_step3d_velocity": (i32, [P, P, P, P, P, P, P, P, dbl, dbl, P]),
         "dsbt_status_string": (ctypes.c_char_p, [i32]),

@@ -54,7 +54,9 @@ def build(verbose: bool = False) -> str:
         with ThreadPoolExecutor(max_workers=jobs) as pool:
             objs = list(pool.map(compile_one, SOURCES))
         out_tmp = LIB + ".tmp"
-        cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", out_tmp, "-lpthread"]
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", out_tmp, "-lpthread",
+               "-L", os.path.join(rocm, "lib"), "-lrocprofiler-sdk-roctx"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

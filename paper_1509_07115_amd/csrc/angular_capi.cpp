@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -232,6 +233,49 @@ dsbt_status dsbt_step3d(dsbt_sht y, dsbt_plan p, void* grid, void* work, const d
     if (st == DSBT_OK) st = dsbt_sht_inverse(y, work, grid, stream);
     if (st == DSBT_OK) st = dsbt_sht_potential_phase(y, grid, V0, V1, F, dt, stream);
     return st;
+}
+
+dsbt_status dsbt_sht_kinetic(dsbt_sht y, double rmax, int32_t kinetic, double* K, void* stream) {
+    if (!y || !K) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!(rmax > 0.0) || !std::isfinite(rmax)) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "rmax must be positive");
+    if (kinetic != DSBT_K_PLAIN && kinetic != DSBT_K_CORRECTED)
+        return dsbt::set_error(DSBT_ERR_INVALID_ARG, "unknown kinetic option");
+    const int nt = y->nt, nphi = y->nphi, Nr = y->Nr, M = (nphi - 1) / 2;
+    std::vector<double> h((size_t)nt * nphi * Nr), k(Nr);
+    for (int q = 0; q < nphi; ++q) {
+        for (int t = 0; t < nt; ++t) {
+            const int ell = std::abs(q - M) + t;
+            const dsbt_status st = dsbt_kinetic_momenta(Nr, ell, rmax, kinetic, k.data());
+            if (st != DSBT_OK) return st;
+            double* row = h.data() + ((size_t)q * nt + t) * Nr;
+            for (int i = 0; i < Nr; ++i) row[i] = 0.5 * k[i] * k[i];   // eq. KinMat
+        }
+    }
+    const hipError_t e = hipMemcpyAsync(K, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize((hipStream_t)stream) : e;
+    if (e2 != hipSuccess) return dsbt::set_error(DSBT_ERR_HIP, (std::string("dsbt_sht_kinetic: ") + hipGetErrorString(e2)).c_str());
+    return DSBT_OK;
+}
+
+dsbt_status dsbt_sht_momentum_pz(dsbt_sht y, double rmax, double* Pz, void* stream) {
+    if (!y || !Pz) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!(rmax > 0.0) || !std::isfinite(rmax)) return dsbt::set_error(DSBT_ERR_INVALID_ARG, "rmax must be positive");
+    const int nt = y->nt, nphi = y->nphi, Nr = y->Nr;
+    std::vector<double> eta(nt);
+    dsbt_status st = dsbt_sht_grid(nt, nphi, eta.data(), nullptr, nullptr);
+    if (st != DSBT_OK) return st;
+    const double dk = 3.14159265358979323846 / rmax;
+    std::vector<double> h((size_t)nt * nphi * Nr);
+    for (int j = 0; j < nt; ++j)
+        for (int q = 0; q < nphi; ++q) {
+            double* row = h.data() + ((size_t)j * nphi + q) * Nr;
+            for (int i = 0; i < Nr; ++i) row[i] = -2.0 * eta[j] * (double)(i + 1) * dk;   // k~_n = n dk, n = i + 1
+        }
+    const hipError_t e = hipMemcpyAsync(Pz, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+    const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize((hipStream_t)stream) : e;
+    if (e2 != hipSuccess)
+        return dsbt::set_error(DSBT_ERR_HIP, (std::string("dsbt_sht_momentum_pz: ") + hipGetErrorString(e2)).c_str());
+    return DSBT_OK;
 }
 
 dsbt_status dsbt_step3d_velocity(dsbt_sht y, dsbt_plan p, void* grid, void* work1, void* work2, const double* V0,

@@ -16,6 +16,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kernels.h"
 #include "plan_device.h"
 #include "plan_host.h"
@@ -183,13 +185,34 @@ struct dsbt_plan_s {
     float* d_sgraph = nullptr;    // strengths staged for graph replays
     int sgraph_cap = 0;
 
-    void* dalloc(size_t bytes) {
+    // checked plans (opts.check_finite): device flag and its pinned host copy
+    int* d_flag = nullptr;
+    int* h_flag = nullptr;
+
+    // device memory through the caller's allocator (opts.dev_alloc) or hipMalloc
+    void* dalloc_raw(size_t bytes) {
         void* p = nullptr;
         if (bytes == 0) bytes = 16;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) throw StatusError(DSBT_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        if (opts.dev_alloc) {
+            p = opts.dev_alloc(bytes, opts.alloc_ctx);
+            if (!p) throw StatusError(DSBT_ERR_OOM, "dev_alloc returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess)
+                throw StatusError(DSBT_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        return p;
+    }
+    void dfree(void* p) {
+        if (!p) return;
+        if (opts.dev_free) opts.dev_free(p, opts.alloc_ctx);
+        else (void)hipFree(p);
+    }
+    // a device buffer owned by the plan (freed by release)
+    void* dalloc(size_t bytes) {
+        void* p = dalloc_raw(bytes);
         allocs.push_back(p);
-        table_bytes += (int64_t)bytes;
+        table_bytes += (int64_t)(bytes == 0 ? 16 : bytes);
         return p;
     }
     void release() {
@@ -197,8 +220,10 @@ struct dsbt_plan_s {
         if (graph) (void)hipGraphDestroy(graph);
         graph_exec = nullptr;
         graph = nullptr;
-        for (void* p : allocs) (void)hipFree(p);
+        for (void* p : allocs) dfree(p);
         allocs.clear();
+        if (h_flag) (void)hipHostFree(h_flag);
+        h_flag = nullptr;
         for (auto& t : prof_events) {
             (void)hipEventDestroy(std::get<1>(t));
             (void)hipEventDestroy(std::get<2>(t));
@@ -227,11 +252,18 @@ void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_
     return d;
 }
 
-// Temporary device buffer for the plan generator, freed on scope exit.
+// Temporary device buffer for the plan generator, freed on scope exit (through
+// the plan's allocator when P is given; the generator synchronises before it
+// returns, so nothing reads the buffer when it is handed back).
 struct DeviceScratch {
+    dsbt_plan_s* P = nullptr;
     double* ptr = nullptr;
     void alloc(size_t doubles) {
         if (doubles == 0) return;
+        if (P) {
+            ptr = static_cast<double*>(P->dalloc_raw(sizeof(double) * doubles));
+            return;
+        }
         hipError_t e = hipMalloc(&ptr, sizeof(double) * doubles);
         if (e != hipSuccess) {
             ptr = nullptr;
@@ -239,8 +271,16 @@ struct DeviceScratch {
         }
     }
     ~DeviceScratch() {
-        if (ptr) (void)hipFree(ptr);
+        if (!ptr) return;
+        if (P) P->dfree(ptr);
+        else (void)hipFree(ptr);
     }
+};
+
+// A named range for rocprofv3 --marker-trace around an entry point.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
 };
 
 void device_blocks(int ell, int B, int NT, double* scratch, std::vector<double>& blk, hipStream_t s) {
@@ -361,6 +401,7 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     const bool fp64mf = P->precision == DSBT_C64_FP64 || P->precision == DSBT_C128;   // FP64 arithmetic
     // FP64 blocks generated on the device (default) or by host threads
     DeviceScratch scratch;
+    scratch.P = P;
     if (P->opts.plan_where == DSBT_PLAN_ON_DEVICE) {
         size_t most = 0;
         for (auto& kv : tileB)
@@ -724,6 +765,19 @@ void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool 
     }
 }
 
+// Checked plans: scan the channels of `data` for NaN and infinities on s and
+// wait for the answer.
+void check_finite_data(dsbt_plan_s* P, const void* data, hipStream_t s, const char* what) {
+    const int nch = (int)P->ch.size();
+    if (P->precision == DSBT_C128)
+        hip_check(dsbt::launch_scan_nonfinite<double>(P->d_fchans, nch, data, P->d_flag, s), "scan");
+    else
+        hip_check(dsbt::launch_scan_nonfinite<float>(P->d_fchans, nch, data, P->d_flag, s), "scan");
+    hip_check(hipMemcpyAsync(P->h_flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, s), "scan flag");
+    hip_check(hipStreamSynchronize(s), "scan sync");
+    if (*P->h_flag) throw StatusError(DSBT_ERR_NONFINITE, std::string(what) + ": NaN or infinity in the data");
+}
+
 template <typename F>
 dsbt_status guarded(F&& f) {
     try {
@@ -749,6 +803,7 @@ void dsbt_plan_opts_default(dsbt_plan_opts* o) {
 
 dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch, const dsbt_plan_opts* o,
                              void* stream) {
+    Range range("dsbt_plan_create");
     if (!out) return fail(DSBT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     return guarded([&]() -> dsbt_status {
@@ -764,6 +819,9 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
             return fail(DSBT_ERR_INVALID_ARG, "unknown plan_where");
         if (opts.algorithm != DSBT_ALG_TILED && opts.algorithm != DSBT_ALG_MONOMIAL)
             return fail(DSBT_ERR_INVALID_ARG, "unknown algorithm");
+        if (opts.check_finite != 0 && opts.check_finite != 1) return fail(DSBT_ERR_INVALID_ARG, "check_finite must be 0 or 1");
+        if ((opts.dev_alloc == nullptr) != (opts.dev_free == nullptr))
+            return fail(DSBT_ERR_INVALID_ARG, "dev_alloc and dev_free must be given together");
         if (opts.algorithm == DSBT_ALG_MONOMIAL) {
             if (opts.precision != DSBT_C128 || opts.mode != DSBT_MODE_BATCHED)
                 return fail(DSBT_ERR_UNSUPPORTED, "the monomial variant needs DSBT_C128 and DSBT_MODE_BATCHED");
@@ -797,6 +855,10 @@ dsbt_status dsbt_plan_create(dsbt_plan* out, const dsbt_channel* ch, int32_t nch
                 build_plan<float>(P, s);
             else
                 build_plan<double>(P, s);   // complex128, or complex64 data with FP64 arithmetic
+            if (P->opts.check_finite) {
+                P->d_flag = static_cast<int*>(P->dalloc(sizeof(int)));
+                hip_check(hipHostMalloc((void**)&P->h_flag, sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+            }
             hip_check(hipStreamSynchronize(s), "plan sync");
         } catch (...) {
             P->release();
@@ -843,8 +905,10 @@ dsbt_status dsbt_plan_info(dsbt_plan p, int32_t* nch, int64_t* elems, int32_t* p
 }
 
 dsbt_status dsbt_forward(dsbt_plan p, const void* psi, void* b, void* stream) {
+    Range range("dsbt_forward");
     if (!p || !psi || !b) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     return guarded([&]() -> dsbt_status {
+        if (p->opts.check_finite) check_finite_data(p, psi, (hipStream_t)stream, "dsbt_forward input");
         dsbt::PhaseArgs none{};
         if (p->precision == DSBT_C128)
             enqueue_forward<double, double>(p, psi, b, (hipStream_t)stream, none, none);
@@ -857,8 +921,10 @@ dsbt_status dsbt_forward(dsbt_plan p, const void* psi, void* b, void* stream) {
 }
 
 dsbt_status dsbt_inverse(dsbt_plan p, const void* b, void* psi, void* stream) {
+    Range range("dsbt_inverse");
     if (!p || !psi || !b) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     return guarded([&]() -> dsbt_status {
+        if (p->opts.check_finite) check_finite_data(p, b, (hipStream_t)stream, "dsbt_inverse input");
         dsbt::PhaseArgs none{};
         if (p->precision == DSBT_C128)
             enqueue_inverse<double, double>(p, b, psi, (hipStream_t)stream, none);
@@ -875,6 +941,7 @@ dsbt_status dsbt_set_potential(dsbt_plan p, const double* V, double dt) {
 }
 
 dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32_t flags) {
+    Range range("dsbt_set_potential");
     if (!p || !V) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DSBT_ERR_INVALID_ARG, "dt must be positive");
     if (flags & ~DSBT_TIME_IMAGINARY) return fail(DSBT_ERR_INVALID_ARG, "unknown potential flag");
@@ -973,6 +1040,7 @@ dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32
 }
 
 dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const float* s, int32_t flags, void* stream) {
+    Range range("dsbt_kinetic_step");
     if (!p || !psi) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (nsteps < 0) return fail(DSBT_ERR_INVALID_ARG, "negative step count");
     if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
@@ -984,6 +1052,10 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
     return guarded([&]() -> dsbt_status {
         hipStream_t st = (hipStream_t)stream;
         const bool adj = (flags & DSBT_STEP_ADJOINT) != 0;
+        if (p->opts.check_finite) {
+            check_finite_data(p, psi, st, "dsbt_kinetic_step input");
+            flags &= ~DSBT_STEP_GRAPH;   // a checked call synchronises; it is not worth a graph
+        }
         auto enqueue = [&](hipStream_t q) {
             if (p->precision == DSBT_C128)
                 enqueue_steps<double, double>(p, psi, nsteps, s, adj, q);
@@ -994,6 +1066,7 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
         };
         if (!(flags & DSBT_STEP_GRAPH)) {
             enqueue(st);
+            if (p->opts.check_finite) check_finite_data(p, psi, st, "dsbt_kinetic_step result");
             return DSBT_OK;
         }
         // The strengths are staged into a plan buffer that the graph reads, so a
@@ -1042,6 +1115,7 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
 
 dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1, const void* lam_t,
                              const void* lam_t1, double* out, void* stream) {
+    Range range("dsbt_step_grad_s");
     if (!p || !psi_t || !psi_t1 || !lam_t || !lam_t1 || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
     if (p->imaginary) return fail(DSBT_ERR_PLAN_MISMATCH, "the potential was set for imaginary time");
@@ -1059,6 +1133,7 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
 }
 
 dsbt_status dsbt_energy(dsbt_plan p, const void* psi, void* work, double* out, void* stream) {
+    Range range("dsbt_energy");
     if (!p || !psi || !work || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
     if (psi == work) return fail(DSBT_ERR_INVALID_ARG, "work must not alias psi");
     if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
@@ -1243,6 +1318,7 @@ const char* dsbt_status_string(dsbt_status s) {
         case DSBT_ERR_OOM: return "out of memory";
         case DSBT_ERR_HIP: return "HIP error";
         case DSBT_ERR_PLAN_MISMATCH: return "call does not fit the plan";
+        case DSBT_ERR_NONFINITE: return "NaN or infinity in the data";
         case DSBT_ERR_NO_DEVICE: return "no HIP device";
         default: return "unknown status";
     }

@@ -161,6 +161,12 @@ hipError_t set_lds_limits_chain();
 template <typename T>
 size_t chain_lds_bytes(int ncb);
 
+// *flag = 1 if any value of the channels' data is a NaN or an infinity
+// (checked plans); the flag is cleared first by the same launcher.  One
+// workgroup per channel; plain stores of 1, no atomics.  S: data scalar.
+template <typename S>
+hipError_t launch_scan_nonfinite(const FChan* d_chans, int nch, const void* data, int* flag, hipStream_t s);
+
 // Partial sums of sum_i vangle_i Im(conj(l1) p1 + conj(l0) p0) per channel into
 // scratch[nch], then out[0] = their sum (FP64).
 template <typename T>

@@ -163,6 +163,32 @@ __global__ void __launch_bounds__(kBlock) mstage(const MItem* __restrict__ items
 }
 
 // ---------------------------------------------------------------------------
+// Scan for non-finite values (checked plans).
+// ---------------------------------------------------------------------------
+
+__global__ void clear_flag(int* flag) { flag[threadIdx.x] = 0; }
+
+template <typename S>
+__global__ void __launch_bounds__(kBlock) scan_nonfinite(const FChan* __restrict__ chans, const S* data, int* flag) {
+    const FChan c = chans[blockIdx.x];
+    const S* x = data + 2 * c.off;
+    bool bad = false;
+    for (int i = threadIdx.x; i < 2 * c.N; i += kBlock) bad |= !isfinite(x[i]);
+    if (bad) flag[0] = 1;
+}
+
+template <typename S>
+hipError_t launch_scan_nonfinite(const FChan* d_chans, int nch, const void* data, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, s, flag);
+    if (nch > 0)
+        hipLaunchKernelGGL(scan_nonfinite<S>, dim3(nch), dim3(kBlock), 0, s, d_chans, static_cast<const S*>(data), flag);
+    return hipGetLastError();
+}
+
+template hipError_t launch_scan_nonfinite<float>(const FChan*, int, const void*, int*, hipStream_t);
+template hipError_t launch_scan_nonfinite<double>(const FChan*, int, const void*, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Reduction for the strength gradient of a step.
 // ---------------------------------------------------------------------------
 

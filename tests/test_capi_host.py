@@ -109,3 +109,42 @@ def test_corrected_momenta_match_oracle_roots(built_lib, N, ell, rmax):
     plain = kinetic_momenta(N, ell, rmax, "plain")
     p = odsbt.parity_p(ell)
     assert np.allclose(plain[kx:], np.arange(kx + p, N + p) * odsbt.delta_k(rmax), rtol=1e-15, atol=0)
+
+
+def test_plan_opts_layout_matches_the_header(tmp_path):
+    # the ctypes mirror of dsbt_plan_opts against the C compiler's layout of
+    # the header (sizes and field offsets)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in _lib.PlanOpts._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'    printf("{f} %zu\\n", offsetof(dsbt_plan_opts, {f}));\n' for f in fields)
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "dsbt.h"\nint main(void) {\n'
+                   '    printf("size %zu\\n", sizeof(dsbt_plan_opts));\n' + body + "    return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", "include", str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(_lib.PlanOpts)
+    for f in fields:
+        assert int(out[f]) == getattr(_lib.PlanOpts, f).offset, f
+
+
+def test_plan_opts_validation_without_a_device(built_lib):
+    # option checks come before the device lookup: they fail the same way with
+    # or without a GPU
+    lib = _lib.load()
+    ch = (_lib.Channel * 1)(_lib.Channel(64, 3, 6.4, 0))
+    h = ctypes.c_void_p()
+    o = _lib.PlanOpts()
+    o.check_finite = 2
+    assert lib.dsbt_plan_create(ctypes.byref(h), ch, 1, ctypes.byref(o), None) == -1
+    assert b"check_finite" in lib.dsbt_last_error()
+    o = _lib.PlanOpts()
+    o.dev_alloc = _lib.ALLOC_FN(lambda n, c: None)    # dev_free missing
+    assert lib.dsbt_plan_create(ctypes.byref(h), ch, 1, ctypes.byref(o), None) == -1
+    assert b"together" in lib.dsbt_last_error()
+    assert lib.dsbt_status_string(_lib.DSBT_ERR_NONFINITE) == b"NaN or infinity in the data"

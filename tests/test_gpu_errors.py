@@ -67,3 +67,100 @@ def test_step_and_buffer_errors_leave_the_plan_usable():
     torch.cuda.synchronize()
     assert abs(torch.linalg.vector_norm(b).item() - 1.0) < 1e-6
     assert torch.allclose(back, x, atol=1e-6)
+
+
+def test_check_finite_reports_nonfinite_data():
+    # checked plans scan the input of a transform or step for NaN and
+    # infinities; the output is not touched when one is found
+    from paper_1509_07115_amd import DsbtError
+    chans = [(256, 3, 25.6, 0), (512, 20, 51.2, 256), (256, 0, 25.6, 768)]
+    for precision, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        plan = Plan(chans, precision=precision, check_finite=True)
+        x = torch.randn(1024, dtype=dtype, device="cuda")
+        b = plan.forward(x)                     # finite: transforms as an unchecked plan
+        ref = Plan(chans, precision=precision).forward(x)
+        torch.cuda.synchronize()
+        assert torch.equal(b, ref)
+        for pos, bad in ((300, float("nan")), (1023, float("inf")), (0, float("-inf"))):
+            y = x.clone()
+            y[pos] = bad
+            out = torch.full_like(x, 7.0)
+            with pytest.raises(DsbtError, match="NONFINITE"):
+                plan.forward(y, out=out)
+            with pytest.raises(DsbtError, match="NONFINITE"):
+                plan.inverse(y, out=out)
+            assert torch.all(out == 7.0)
+        plan.set_potential(np.zeros(1024), 0.01)
+        y = x.clone()
+        y[700] = float("nan")
+        with pytest.raises(DsbtError, match="NONFINITE"):
+            plan.kinetic_step(y, 2, graph=True)
+        z = x.clone()
+        plan.kinetic_step(z, 2, graph=True)     # finite input and result
+        torch.cuda.synchronize()
+
+
+def test_plan_memory_through_the_caller_allocator():
+    # dev_alloc / dev_free: every device buffer of the plan comes from the
+    # caller's allocator and goes back to it; a failing allocation (injected
+    # after k successes) gives DSBT_ERR_OOM and hands back what was obtained
+    from paper_1509_07115_amd import DsbtError
+    chans = [(256, 5, 25.6, 0), (256, 6, 25.6, 256), (512, 33, 51.2, 512)]
+    live = {}
+
+    def alloc(n):
+        t = torch.empty(int(n), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr):
+        del live[ptr]
+
+    x = torch.randn(1024, dtype=torch.complex64, device="cuda")
+    ref = Plan(chans).forward(x)
+    plan = Plan(chans, allocator=(alloc, free))
+    n_plan = len(live)
+    assert n_plan > 5
+    assert sum(t.numel() for t in live.values()) >= plan.table_bytes
+    b = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(b, ref)
+    plan.set_potential(np.zeros(1024), 0.01)     # potential tables come from the allocator too
+    assert len(live) > n_plan
+    plan.close()
+    assert not live
+    for k in (0, 3, n_plan - 1):
+        count = [0]
+
+        def failing(n):
+            count[0] += 1
+            return 0 if count[0] > k else alloc(n)
+        with pytest.raises(DsbtError, match="OOM"):
+            Plan(chans, allocator=(failing, free))
+        assert not live, k
+    # PyTorch's caching allocator
+    plan = Plan(chans, allocator="torch")
+    b = plan.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(b, ref)
+    plan.close()
+
+
+def test_angular_diagonal_tables_from_the_library():
+    # K = k_n^2/2 per coefficient slot (eq. KinMat) and -2 k~_n eta_j on the
+    # momentum grid, built behind the C ABI, against their definitions
+    from paper_1509_07115_amd import AngularTransform, kinetic_momenta, sht_grid
+    Nr, nt, nphi, rmax = 64, 6, 5, 12.8
+    Y = AngularTransform(Nr, nt, nphi)
+    for kin in ("plain", "corrected"):
+        K = Y.kinetic(rmax, kin).cpu().numpy().reshape(nphi, nt, Nr)
+        M = (nphi - 1) // 2
+        for q in range(nphi):
+            for t in range(nt):
+                ell = abs(q - M) + t
+                k = kinetic_momenta(Nr, ell, rmax, kin)
+                assert np.array_equal(K[q, t], 0.5 * k * k), (kin, q, t)
+    P = Y.momentum_pz(rmax).cpu().numpy().reshape(nt, nphi, Nr)
+    eta = sht_grid(nt, nphi)[0]
+    kt = np.arange(1, Nr + 1) * (np.pi / rmax)
+    assert np.allclose(P, -2.0 * eta[:, None, None] * kt[None, None, :], rtol=1e-15, atol=0)

@@ -75,13 +75,26 @@ def test_uneven_batch_device_plan():
         worst_rt = max(worst_rt, np.linalg.norm(yh[off:off + N] - w.psi[off:off + N]) / nx)
     print(f"round trip: max per-channel relative error {worst_rt:.2e}")
     assert worst_rt < 1e-5
+    # forward and inverse against the FP64 oracle: the smallest and the largest
+    # l of every N, and one channel (the smallest N) of every distinct l, so
+    # that every l's tables are checked
     pick = {}
     for N, ell, _, off in w.channels:
         lo, hi = pick.get(N, ((999, 0), (-1, 0)))
         pick[N] = (min(lo, (ell, off)), max(hi, (ell, off)))
-    for N, sel in sorted(pick.items()):
-        for ell, off in sel:
-            ref = odsbt.forward(w.psi[off:off + N], ell)
-            err = np.linalg.norm(bh[off:off + N] - ref) / np.linalg.norm(ref)
-            print(f"N={N} l={ell}: forward relative error {err:.2e}")
-            assert err < 1e-5, (N, ell, err)
+    sel = {(N, ell, off) for N, s in pick.items() for ell, off in s}
+    per_l = {}
+    for N, ell, _, off in w.channels:
+        if ell not in per_l or N < per_l[ell][0]:
+            per_l[ell] = (N, off)
+    sel |= {(N, ell, off) for ell, (N, off) in per_l.items()}
+    worst_f = worst_i = 0.0
+    for N, ell, off in sorted(sel):
+        ref = odsbt.forward(w.psi[off:off + N], ell)
+        err = np.linalg.norm(bh[off:off + N] - ref) / np.linalg.norm(ref)
+        ref_i = odsbt.inverse(bh[off:off + N], ell)
+        err_i = np.linalg.norm(yh[off:off + N] - ref_i) / np.linalg.norm(ref_i)
+        worst_f, worst_i = max(worst_f, err), max(worst_i, err_i)
+        assert err < 1e-5 and err_i < 1e-5, (N, ell, err, err_i)
+    print(f"{len(sel)} channels ({len(per_l)} distinct l): forward max rel {worst_f:.2e}, "
+          f"inverse max rel {worst_i:.2e}")
