@@ -212,6 +212,21 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
 dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
                              const void* lam_t, const void* lam_t1, double* out, void* stream);
 
+/* dsbt_step_grad_s for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, with the per-channel FP64 partial sums in a
+ * fixed device array of DSBT_NOALLOC_MAX_CHANNELS doubles (512 KiB) that the
+ * library holds on each GPU it runs on until the process ends, instead of the
+ * plan's buffer.  The call itself allocates nothing (its first call on a
+ * device only looks up that array's address).  Every call on one GPU shares
+ * the array: calls that overlap on a GPU (several streams or host threads)
+ * race and must be serialised by the caller.  A plan with more than
+ * DSBT_NOALLOC_MAX_CHANNELS channels: DSBT_ERR_UNSUPPORTED.  Other errors as
+ * dsbt_step_grad_s. */
+#define DSBT_NOALLOC_MAX_CHANNELS 65536
+dsbt_status dsbt_step_grad_s_noalloc(dsbt_plan p, const void* psi_t, const void* psi_t1,
+                                     const void* lam_t, const void* lam_t1, double* out, void* stream);
+
 /* Energy terms of eq. H_DVR per channel (Sec. 4.1, used for the bound-state
  * energies of Sec. 4.3): with b = T F psi,
  *     out[3c + 0] = sum_i |psi_i|^2,

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -102,6 +103,36 @@ std::vector<unsigned char> decay_table(const std::vector<double>& ex, bool fp64)
 namespace dsbt {
 dsbt_status set_error(dsbt_status s, const char* msg) { return fail(s, msg); }
 }  // namespace dsbt
+
+// Scratch of dsbt_step_grad_s_noalloc: one FP64 partial sum per channel, in a
+// fixed device array (each GPU the library runs on holds its own copy until
+// the process ends).  Host code never passes the array's name to a kernel: it
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device on the entry point's first call there.
+static __device__ __align__(256) double noalloc_scratch[DSBT_NOALLOC_MAX_CHANNELS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of noalloc_scratch on the current device.
+double* noalloc_scratch_ptr() {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) throw StatusError(DSBT_ERR_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)), "hipGetSymbolAddress");
+        if (!ptr) throw HipError(hipErrorInvalidSymbol, "hipGetSymbolAddress returned NULL");
+        g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_noalloc_ptr[dev];
+}
+
+}  // namespace
 
 struct dsbt_plan_s {
     int device = 0;
@@ -1128,6 +1159,30 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
         else
             hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
                                                  st), "grad_s");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_step_grad_s_noalloc(dsbt_plan p, const void* psi_t, const void* psi_t1, const void* lam_t,
+                                     const void* lam_t1, double* out, void* stream) {
+    if (!p || !psi_t || !psi_t1 || !lam_t || !lam_t1 || !out) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    if (p->imaginary) return fail(DSBT_ERR_PLAN_MISMATCH, "the potential was set for imaginary time");
+    const int nch = (int)p->ch.size();
+    if (nch > DSBT_NOALLOC_MAX_CHANNELS)
+        return fail(DSBT_ERR_UNSUPPORTED, "dsbt_step_grad_s_noalloc: the plan has " + std::to_string(nch) +
+                                              " channels, more than DSBT_NOALLOC_MAX_CHANNELS = " +
+                                              std::to_string(DSBT_NOALLOC_MAX_CHANNELS));
+    return guarded([&]() -> dsbt_status {
+        double* part = noalloc_scratch_ptr();
+        hipStream_t st = (hipStream_t)stream;
+        // the partial sums are written (not accumulated) for every channel before they are read
+        if (p->precision == DSBT_C128)
+            hip_check(dsbt::launch_grad_s<double>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, part, out, st),
+                      "grad_s");
+        else
+            hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, part, out, st),
+                      "grad_s");
         return DSBT_OK;
     });
 }
