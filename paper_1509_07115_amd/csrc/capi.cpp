@@ -267,7 +267,7 @@ struct dsbt_plan_s {
 
 namespace {
 
-// Complex table (re, im pairs, FP64 values v) of unit numbers in the arithmetic
+// Complex table (re, im pairs, FP64 values v) of factors in the arithmetic
 // precision: FP64 as is; FP32 as the hi table followed by the lo table
 // (factor_table).  Returns the hi table; *lo receives the lo table (FP32) or
 // nullptr.
@@ -478,7 +478,8 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         }
         tabs[ell] = t;
     }
-    // twiddles per N: pass tables, post-twiddles and their lo parts
+    // per N: pass twiddles, and the post-twiddles times the orthonormal scale,
+    // 0.5 sqrt(2/N) w^k (k >= 1) and 0.5 sqrt(1/N) (k = 0), with their lo parts
     std::map<int, std::array<const void*, 4>> twd;
     for (auto& g : P->groups) {
         if (twd.count(g.N)) continue;
@@ -486,6 +487,12 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         dsbt::fft_twiddles(g.N, tw, post);
         std::array<const void*, 4> a{};
         a[0] = upload_unit_table<T>(P, tw, s, &a[1]);
+        const double sc1 = 0.5 * std::sqrt(2.0 / g.N), sc0 = 0.5 * std::sqrt(1.0 / g.N);
+        for (int k = 0; k < g.N; ++k) {
+            const double f = k == 0 ? sc0 : sc1;
+            post[2 * k] *= f;
+            post[2 * k + 1] *= f;
+        }
         a[2] = upload_unit_table<T>(P, post, s, &a[3]);
         twd[g.N] = a;
     }

@@ -13,10 +13,11 @@
 // thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
 // pass for the remaining factor), data stay in LDS with one pad slot per 32
 // complex values.  Twiddles: per pass a table of every power a butterfly
-// needs, one 16-byte aligned row per butterfly class, built in FP64; FP32
-// plans carry every twiddle and phase factor as hi + lo parts (kernels.h), so
-// that no product by a fixed unit number or constant changes the modulus of
-// the data systematically.
+// needs, one 16-byte aligned row per butterfly class, built in FP64.  In FP32
+// no product by a fixed unit number or constant may change the modulus of the
+// data systematically (kernels.h, FChan): the pass twiddles are applied as
+// shears, the post-twiddles and phase factors as hi + lo parts, and products by
+// constants are compensated.
 #include "kernels.h"
 
 namespace dsbt {
@@ -50,6 +51,22 @@ __device__ __forceinline__ T s_mul(T x, Split<T> c) {
     else return x * c.hi;
 }
 
+// One complex table value through the global address space (the HIP vector
+// types have no constructors from address-space qualified values).
+typedef float nf2 __attribute__((ext_vector_type(2)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ __forceinline__ V ld_c(const V DSBT_GLOBAL* p, int i) {
+    if constexpr (sizeof(V) == sizeof(float2)) {
+        const nf2 v = reinterpret_cast<const nf2 DSBT_GLOBAL*>(p)[i];
+        return V{v.x, v.y};
+    } else {
+        const nd2 v = reinterpret_cast<const nd2 DSBT_GLOBAL*>(p)[i];
+        return V{v.x, v.y};
+    }
+}
+
 // A unit number w = h + l (l = 0 for FP64 arithmetic) and a product by it.
 template <typename V> struct Unit {
     V h, l;
@@ -60,9 +77,9 @@ __device__ __forceinline__ V u_mul(V a, const Unit<V>& w) {
     else return f_mul(a, w.h);
 }
 template <typename V>
-__device__ __forceinline__ Unit<V> unit_at(const V* hi, const V* lo, int i) {
-    if constexpr (sizeof(V) == sizeof(float2)) return {hi[i], lo[i]};
-    else return {hi[i], V{0, 0}};
+__device__ __forceinline__ Unit<V> unit_at(const V DSBT_GLOBAL* hi, const V DSBT_GLOBAL* lo, int i) {
+    if constexpr (sizeof(V) == sizeof(float2)) return {ld_c(hi, i), ld_c(lo, i)};
+    else return {ld_c(hi, i), V{0, 0}};
 }
 template <typename V, typename T>
 __device__ __forceinline__ V f_scale(V a, Split<T> c) { return {s_mul(a.x, c), s_mul(a.y, c)}; }
@@ -93,11 +110,27 @@ __device__ __forceinline__ void dft8(V* v) {
     V e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
     dft4<T>(e);
     dft4<T>(o);
-    constexpr double hd = 0.70710678118654752440;
-    constexpr Split<T> h{(T)hd, (T)(hd - (double)(T)hd)};
-    const V o1 = {s_mul(o[1].x + o[1].y, h), s_mul(o[1].y - o[1].x, h)};   // o1 * exp(-i pi/4)
-    const V o2 = f_negi(o[2]);                                             // o2 * exp(-i pi/2)
-    const V o3 = {s_mul(o[3].y - o[3].x, h), -s_mul(o[3].x + o[3].y, h)};  // o3 * exp(-3 i pi/4)
+    V o1, o3;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        // rotations by -pi/4 as three shears (t = tan(pi/8), s = -sin(pi/4)):
+        // determinant one whatever the rounding of t and s, so no systematic
+        // change of the modulus (the rounded constant sqrt(1/2) alone would
+        // scale every value by the same factor)
+        constexpr float tq = 0.41421356237309504880f, sq = -0.70710678118654752440f;
+        auto rot = [](V a) {
+            a.x = __builtin_fmaf(tq, a.y, a.x);
+            a.y = __builtin_fmaf(sq, a.x, a.y);
+            a.x = __builtin_fmaf(tq, a.y, a.x);
+            return a;
+        };
+        o1 = rot(o[1]);                // o1 exp(-i pi/4)
+        o3 = f_negi(rot(o[3]));        // o3 exp(-3 i pi/4)
+    } else {
+        constexpr T h = (T)0.70710678118654752440;
+        o1 = {(o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h};
+        o3 = {(o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h};
+    }
+    const V o2 = f_negi(o[2]);         // o2 exp(-i pi/2)
     v[0] = f_add(e[0], o[0]);
     v[4] = f_sub(e[0], o[0]);
     v[1] = f_add(e[1], o1);
@@ -108,28 +141,32 @@ __device__ __forceinline__ void dft8(V* v) {
     v[7] = f_sub(e[3], o3);
 }
 
+// Table pointers are cast to the global address space (as_global): generic
+// (flat) loads would also count against the LDS counter, so each LDS wait of
+// the passes would wait for them too.
+template <typename T> using TabPtr = const typename CV<T>::t DSBT_GLOBAL*;
+
 // R consecutive complex values from a 16-byte aligned row.
 template <typename T, int R>
-__device__ __forceinline__ void load_row(const typename CV<T>::t* row, typename CV<T>::t* out) {
+__device__ __forceinline__ void load_row(TabPtr<T> row, typename CV<T>::t* out) {
     if constexpr (sizeof(T) == sizeof(float)) {
-        const float4* q = reinterpret_cast<const float4*>(row);
+        const nf4 DSBT_GLOBAL* q = reinterpret_cast<const nf4 DSBT_GLOBAL*>(row);
 #pragma unroll
         for (int i = 0; i < R / 2; ++i) {
-            const float4 a = q[i];
+            const nf4 a = q[i];
             out[2 * i] = make_float2(a.x, a.y);
             out[2 * i + 1] = make_float2(a.z, a.w);
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < R; ++i) out[i] = row[i];
+        for (int i = 0; i < R; ++i) out[i] = ld_c(row, i);
     }
 }
 
 // One Stockham pass of radix R on the channel at buf (padded indexing);
 // thread t of the channel owns butterflies j = t + u N/8, u < 8/R.
 template <typename T, int N, int R>
-__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const typename CV<T>::t* tw,
-                                         const typename CV<T>::t* twl, int t) {
+__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, TabPtr<T> tw, TabPtr<T> twl, int t) {
     using V = typename CV<T>::t;
     constexpr int NR = N / R, U = 8 / R;
     V v[U][R];
@@ -172,11 +209,9 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const t
     lds_barrier();
 }
 
-// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R
-// (twl: their lo parts, FP32 only).
+// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R.
 template <typename T, int N>
-__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<T>::t* tw,
-                                      const typename CV<T>::t* twl, int t) {
+__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, TabPtr<T> tw, TabPtr<T> twl, int t) {
     constexpr int L = __builtin_ctz(N);
     int Ns = 1, off = 0;
 #pragma unroll
@@ -191,22 +226,27 @@ __device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename CV<
 
 // The potential factor exp(-i s V tau/2) of point i: from the plan's table
 // when every strength is one, else from the FP64 angle s V tau/2 reduced mod
-// 2 pi (FP64 sine and cosine, split into hi + lo for FP32 arithmetic).
+// 2 pi, then sine and cosine in the arithmetic precision (lo = 0: the factors
+// change from step to step, so their rounding does not add up to a drift).
 template <typename V>
 __device__ __forceinline__ Unit<V> phase_factor(const FChan& c, int i, const PhaseArgs& ph) {
     Unit<V> z;
     if (ph.scale == nullptr) {
-        z = unit_at(static_cast<const V*>(c.vphase), static_cast<const V*>(c.vphase_lo), i);
+        z = unit_at(as_global(static_cast<const V*>(c.vphase)), as_global(static_cast<const V*>(c.vphase_lo)), i);
     } else {
-        double a = (double)ph.scale[ph.step] * c.vangle[i];
+        double a = (double)ph.scale[ph.step] * as_global(c.vangle)[i];
         const double twopi = 6.283185307179586476925286766559;
         a -= twopi * rint(a / twopi);
-        double sn, cs;
-        sincos(a, &sn, &cs);
-        using T = decltype(V{}.x);
-        const T hc = (T)cs, hs = (T)(-sn);
-        z.h = V{hc, hs};
-        z.l = V{(T)(cs - (double)hc), (T)(-sn - (double)hs)};
+        if constexpr (sizeof(V) == sizeof(float2)) {
+            float sn, cs;
+            sincosf((float)a, &sn, &cs);
+            z.h = V{cs, -sn};
+        } else {
+            double sn, cs;
+            sincos(a, &sn, &cs);
+            z.h = V{cs, -sn};
+        }
+        z.l = V{0, 0};
     }
     if (ph.conj) {
         z.h.y = -z.h.y;
@@ -244,13 +284,12 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     // barriers on a copy of the last descriptor (valid tables) and store nothing
     const bool live = cidx < nch;
     const FChan c = chans[live ? cidx : nch - 1];
-    const V* tw = reinterpret_cast<const V*>(c.tw);
-    const V* twl = reinterpret_cast<const V*>(c.tw_lo);
-    const V* post = reinterpret_cast<const V*>(c.post);
-    const V* postl = reinterpret_cast<const V*>(c.post_lo);
-    // orthonormal scales sqrt(1/N) (k = 0) and sqrt(2/N), with the sign, in FP64
-    const double d0 = (double)c.sign * sqrt(1.0 / N), d1 = (double)c.sign * sqrt(2.0 / N);
-    const Split<T> sc0 = split_const<T>(INV ? d0 : 0.5 * d0), sc1 = split_const<T>(INV ? d1 : 0.5 * d1);
+    const TabPtr<T> tw = as_global(reinterpret_cast<const V*>(c.tw));
+    const TabPtr<T> twl = as_global(reinterpret_cast<const V*>(c.tw_lo));
+    const TabPtr<T> post = as_global(reinterpret_cast<const V*>(c.post));
+    const TabPtr<T> postl = as_global(reinterpret_cast<const V*>(c.post_lo));
+    // the sign (-1)^ceil(l/2) (an exact product); the orthonormal scales are in the post table
+    const T sg = (T)c.sign;
     if constexpr (!INV) {
         if (live) {
             // pairs x_{2j}, x_{2j+1} (one 16-byte load) go to v_j and v_{N-1-j}
@@ -281,6 +320,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int k = 2 * m + e;
+                    // c w^k with the orthonormal scale c folded into the table
                     const Unit<V> w = unit_at(post, postl, k);
                     const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
                     // w a + conj(w) b = (w.x (a.x + b.x) + w.y (b.y - a.y), w.x (a.y + b.y) + w.y (a.x - b.x))
@@ -292,7 +332,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                     } else {
                         X = {w.h.x * sx + w.h.y * dy, w.h.x * sy + w.h.y * dx};
                     }
-                    o[e] = to_prec<SV>(f_scale(X, k == 0 ? sc0 : sc1));
+                    o[e] = to_prec<SV>(f_scale(X, sg));
                 }
                 if (c.p)
                     *reinterpret_cast<typename Pair<S>::t*>(y + (N - 2 - 2 * m)) =
@@ -313,21 +353,25 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
                 for (int e = 0; e < 2; ++e) {
                     const int j = 2 * m + e;
                     const int k = c.p ? (N - 1 - j) : j;
-                    buf[pidx(k)] = f_scale(to_prec<V>(SV{v[2 * e], v[2 * e + 1]}), k == 0 ? sc0 : sc1);
+                    buf[pidx(k)] = f_scale(to_prec<V>(SV{v[2 * e], v[2 * e + 1]}), sg);
                 }
             }
         }
         lds_barrier();
-        // U = A^T X: U_0 = X_0, U_j = (w^j/2)(X_j + i X_{N-j})
+        // U = A^T S X (S the orthonormal scales): U_0 = sqrt(1/N) X_0 = 2 c_0 X_0,
+        // U_j = (w^j/2) sqrt(2/N) (X_j + i X_{N-j}) = c w^j (X_j + i X_{N-j})
         V u8[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int j = t + u * TPC;
             if (j == 0) {
-                u8[u] = buf[0];
+                Unit<V> w0 = unit_at(post, postl, 0);
+                w0.h = f_scale(w0.h, (T)2);
+                w0.l = f_scale(w0.l, (T)2);
+                u8[u] = u_mul(buf[0], w0);
             } else {
                 const V s = f_add(buf[pidx(j)], f_posi(buf[pidx(N - j)]));
-                u8[u] = f_scale(u_mul(s, unit_at(post, postl, j)), (T)0.5);
+                u8[u] = u_mul(s, unit_at(post, postl, j));
             }
         }
         lds_barrier();

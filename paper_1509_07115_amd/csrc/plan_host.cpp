@@ -1,6 +1,7 @@
 // Host FP64 plan generation for the orthogonal DSBT.  See plan_host.h for the
 // tiled moment form; the formulas cited here are those of Sec. 2.3-2.5.
 #include "plan_host.h"
+#include <cstring>
 
 #include <algorithm>
 #include <atomic>
@@ -326,6 +327,37 @@ void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
         post[2 * t] = std::cos(b);
         post[2 * t + 1] = std::sin(b);
     }
+}
+
+void fft_lift_twiddles(int N, std::vector<float>& ts) {
+    const double pi = 3.14159265358979323846;
+    int L = 0;
+    while ((1 << L) < N) ++L;
+    std::vector<std::pair<int, int>> passes;   // (Ns, R), as fft_twiddles
+    int Ns = 1;
+    for (int s = 0; s < L / 3; ++s, Ns *= 8) passes.emplace_back(Ns, 8);
+    if (L % 3) passes.emplace_back(Ns, L % 3 == 1 ? 2 : 4);
+    ts.clear();
+    for (auto [ns, R] : passes) {
+        if (ns == 1) continue;
+        const int64_t RN = (int64_t)R * ns;
+        for (int jm = 0; jm < ns; ++jm)
+            for (int r = 0; r < R; ++r) {
+                const int64_t a = 2 * (int64_t)r * jm;         // theta = -pi a / RN
+                const int64_t h = (2 * a + RN) / (2 * RN);     // nearest number of half turns
+                // theta' = theta + h pi = pi (h RN - a) / RN, an exact rational
+                const double th = pi * (double)(h * RN - a) / (double)RN;
+                const float t = (float)(-std::tan(0.5 * th));
+                float s = (float)std::sin(th);
+                uint32_t bits;
+                std::memcpy(&bits, &s, sizeof(bits));
+                bits = (bits & ~1u) | (uint32_t)(h & 1);
+                std::memcpy(&s, &bits, sizeof(bits));
+                ts.push_back(t);
+                ts.push_back(s);
+            }
+    }
+    if (ts.empty()) ts.assign(2, 0.0f);
 }
 
 }  // namespace dsbt

@@ -60,4 +60,13 @@ void corrected_momenta(int N, int ell, double rmax, double* k);
 // one radix-2 or radix-4 pass), and post, exp(-i pi k/(2N)), k < N.
 void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post);
 
+// The pass twiddles of fft_twiddles in the form the FP32 kernels multiply by:
+// w = exp(i theta) = (-1)^h exp(i theta'), h = floor((4 r jm + R Ns) / (2 R Ns))
+// (half turns), |theta'| <= pi/2, and the rotation by theta' taken as the three
+// shears x += t y, y += s x, x += t y with t = -tan(theta'/2), s = sin(theta').
+// Same layout as tw: (t, s) pairs of FP32 values; the lowest bit of s holds
+// h mod 2 (the kernel negates the input when it is set; a change of s by one
+// unit in the last place leaves every shear of determinant one).
+void fft_lift_twiddles(int N, std::vector<float>& ts);
+
 }  // namespace dsbt
