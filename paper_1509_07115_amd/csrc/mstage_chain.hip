@@ -149,7 +149,9 @@ struct Pipe {
     static constexpr int C2LO = 8, C2HI = INV ? MHI : 12;   // moment rows 0..15, moment chunks
     static constexpr int C3LO = INV ? 12 : 8, C3HI = MHI;   // moment rows 16..31 (KB = 2)
     static constexpr int NC2 = (C2HI - C2LO) / 4, NC3 = KB == 2 ? (C3HI - C3LO) / 4 : 0;
-    static constexpr int SLOT = 64 * 8 * NCB;               // values per Q x / moment slot
+    // values per Q x / moment slot: 4 values of moment rows 16 h + 4 (l/16) .. of
+    // block cb for lane l at 256 (2 cb + h) + 4 l (lane-contiguous 16-byte accesses)
+    static constexpr int SLOT = 64 * 8 * NCB;
     static constexpr int XSLOT = 8 * NCB * kXCh;            // values per data slot
     static constexpr int YWAVE = NCB * 16 * kYCol;          // result staging per result wave
     static constexpr int LPC = 8 / NCB, FPL = 8 * NCB;      // pre-wave loads: lanes per channel, floats per lane
@@ -294,11 +296,11 @@ struct Pipe {
     }
     template <int I>
     __device__ void pre_readout(const Pre& r, int t) const {
-        T* qs = qring + (t % kQRing) * SLOT + lane * 8 * NCB;
+        T* qs = qring + (t % kQRing) * SLOT + 4 * lane;
 #pragma unroll
         for (int h = 0; h < KB; ++h)
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) st4(qs + 8 * cb + 4 * h, r.c0[I][h][cb] + r.c1[I][h][cb]);
+            for (int cb = 0; cb < NCB; ++cb) st4(qs + (2 * cb + h) * 256, r.c0[I][h][cb] + r.c1[I][h][cb]);
     }
     template <int S>
     __device__ void pre_step(Pre& r, int t) const {
@@ -367,12 +369,12 @@ struct Pipe {
         if constexpr (KB == 2) seg<NC3>(r.a[S] + NC2, J, 3, C3LO / 4);
     }
     __device__ void store_mu(const Chain& r, int t) const {
-        T* ms = mring + (t % kMRing) * SLOT + lane * 8 * NCB;
+        T* ms = mring + (t % kMRing) * SLOT + 4 * lane;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const T* b = r.bm + 4 * KB * cb;
-            st4(ms + 8 * cb, V4{b[0], b[1], b[2], b[3]});
-            if constexpr (KB == 2) st4(ms + 8 * cb + 4, V4{b[4], b[5], b[6], b[7]});
+            st4(ms + 2 * cb * 256, V4{b[0], b[1], b[2], b[3]});
+            if constexpr (KB == 2) st4(ms + (2 * cb + 1) * 256, V4{b[4], b[5], b[6], b[7]});
         }
     }
     template <int S>
@@ -419,11 +421,11 @@ struct Pipe {
     __device__ void chain_phase_body(Chain& r, int t0) const {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
-            const T* qs = qring + ((t0 + i) % kQRing) * SLOT + lane * 8 * NCB;
+            const T* qs = qring + ((t0 + i) % kQRing) * SLOT + 4 * lane;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
-                r.qg[i][cb][0] = ld4(qs + 8 * cb);
-                if constexpr (KB == 2) r.qg[i][cb][1] = ld4(qs + 8 * cb + 4);
+                r.qg[i][cb][0] = ld4(qs + 2 * cb * 256);
+                if constexpr (KB == 2) r.qg[i][cb][1] = ld4(qs + (2 * cb + 1) * 256);
             }
         }
         chain_phase<I0>(r, t0);
@@ -582,16 +584,16 @@ struct Pipe {
 #pragma unroll
         for (int i = 0; i < kPhase; ++i) {
             const T* xs = xring + ((t0 + i) % kXRing) * XSLOT;
-            const T* ms = mring + ((t0 + i) % kMRing) * SLOT + lane * 8 * NCB;
+            const T* ms = mring + ((t0 + i) % kMRing) * SLOT + 4 * lane;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
                 for (int kc = 0; kc < 8; ++kc) r.x[i][8 * cb + kc] = xs[xop[cb] + 8 * kc];
-                const V4 m0 = ld4(ms + 8 * cb);
+                const V4 m0 = ld4(ms + 2 * cb * 256);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + j] = m0[j];
                 if constexpr (KB == 2) {
-                    const V4 m1 = ld4(ms + 8 * cb + 4);
+                    const V4 m1 = ld4(ms + (2 * cb + 1) * 256);
 #pragma unroll
                     for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + 4 + j] = m1[j];
                 }
@@ -662,7 +664,7 @@ __device__ void run_item(const MItem& it, const void* src, void* dst, const Phas
 }
 
 template <typename T, typename D, bool INV, bool KPH>
-__global__ void __launch_bounds__(256) mstage_chain(const MItem* __restrict__ items, const void* src, void* dst,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? 2 : 1))) mstage_chain(const MItem* __restrict__ items, const void* src, void* dst,
                                                     PhaseArgs ph) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
