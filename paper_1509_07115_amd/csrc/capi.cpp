@@ -283,6 +283,31 @@ void* upload_unit_table(dsbt_plan_s* P, const std::vector<double>& v, hipStream_
     return d;
 }
 
+// The quarter-circle roots (cos, sin) pairs of fft_quarter_roots, 16 bytes per
+// entry: FP64 (c, s), or FP32 (c hi, s hi, c lo, s lo) with hi the nearest
+// FP32 value and lo the FP32 rounding of the rest (kernels.h, FChan).
+template <typename T>
+void* upload_roots(dsbt_plan_s* P, const std::vector<double>& cs, hipStream_t s) {
+    const size_t n = cs.size() / 2;
+    std::vector<unsigned char> h(16 * n);
+    for (size_t e = 0; e < n; ++e) {
+        if (sizeof(T) == sizeof(double)) {
+            std::memcpy(h.data() + 16 * e, &cs[2 * e], 16);
+        } else {
+            float v[4];
+            for (int j = 0; j < 2; ++j) {
+                v[j] = (float)cs[2 * e + j];
+                v[2 + j] = (float)(cs[2 * e + j] - (double)v[j]);
+            }
+            std::memcpy(h.data() + 16 * e, v, 16);
+        }
+    }
+    void* d = P->dalloc(h.size());
+    hip_check(hipMemcpyAsync(d, h.data(), h.size(), hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+    return d;
+}
+
 // Temporary device buffer for the plan generator, freed on scope exit (through
 // the plan's allocator when P is given; the generator synchronises before it
 // returns, so nothing reads the buffer when it is handed back).
@@ -478,22 +503,24 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         }
         tabs[ell] = t;
     }
-    // per N: pass twiddles, and the post-twiddles times the orthonormal scale,
-    // 0.5 sqrt(2/N) w^k (k >= 1) and 0.5 sqrt(1/N) (k = 0), with their lo parts
-    std::map<int, std::array<const void*, 4>> twd;
+    // per N: the quarter-circle roots the FFT passes form their twiddles from,
+    // and the post-twiddles times the orthonormal scale, 0.5 sqrt(2/N) w^k
+    // (k >= 1) and 0.5 sqrt(1/N) (k = 0), with their lo parts
+    std::map<int, std::array<const void*, 3>> twd;
     for (auto& g : P->groups) {
         if (twd.count(g.N)) continue;
-        std::vector<double> tw, post;
-        dsbt::fft_twiddles(g.N, tw, post);
-        std::array<const void*, 4> a{};
-        a[0] = upload_unit_table<T>(P, tw, s, &a[1]);
+        std::vector<double> cs, post;
+        dsbt::fft_quarter_roots(g.N, cs);
+        dsbt::fft_post_twiddles(g.N, post);
+        std::array<const void*, 3> a{};
+        a[0] = upload_roots<T>(P, cs, s);
         const double sc1 = 0.5 * std::sqrt(2.0 / g.N), sc0 = 0.5 * std::sqrt(1.0 / g.N);
         for (int k = 0; k < g.N; ++k) {
             const double f = k == 0 ? sc0 : sc1;
             post[2 * k] *= f;
             post[2 * k + 1] *= f;
         }
-        a[2] = upload_unit_table<T>(P, post, s, &a[3]);
+        a[1] = upload_unit_table<T>(P, post, s, &a[2]);
         twd[g.N] = a;
     }
     // channel descriptors
@@ -508,10 +535,9 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         f.p = dsbt::parity_p(x.ell);
         const int sg = (((x.ell + 1) / 2) % 2) ? -1 : 1;
         f.sign = (P->opts.sign == DSBT_SIGN_PRINTED_F) ? 1.0f : (float)sg;
-        f.tw = twd[x.N][0];
-        f.tw_lo = twd[x.N][1];
-        f.post = twd[x.N][2];
-        f.post_lo = twd[x.N][3];
+        f.roots = twd[x.N][0];
+        f.post = twd[x.N][1];
+        f.post_lo = twd[x.N][2];
         P->h_fchans[c] = f;
         P->maxN = std::max(P->maxN, x.N);
     }

@@ -12,12 +12,15 @@
 // Layout: a block handles CPB channels of N points with N/8 threads each; each
 // thread owns 8 points per Stockham pass (radix 8, then one radix-2 or radix-4
 // pass for the remaining factor), data stay in LDS with one pad slot per 32
-// complex values.  Twiddles: per pass a table of every power a butterfly
-// needs, one 16-byte aligned row per butterfly class, built in FP64.  In FP32
-// no product by a fixed unit number or constant may change the modulus of the
-// data systematically (kernels.h, FChan): the pass twiddles are applied as
-// shears, the post-twiddles and phase factors as hi + lo parts, and products by
-// constants are compensated.
+// complex values.  Twiddles: the block copies the plan's quarter-circle roots
+// exp(2 pi i e/N), e < N/4 (16 bytes each) into LDS once, and a pass twiddle
+// exp(-2 pi i m/N) is the product by the conjugate root of e = m mod N/4
+// followed by the exact quarter turn (-i)^(m div N/4); so the passes read no
+// table from global memory.  In FP32 no product by a fixed unit number or
+// constant may change the modulus of the data systematically (kernels.h,
+// FChan): roots, post-twiddles and phase factors are hi + lo pairs, the
+// radix-8 rotations by -pi/4 are shears, and products by constants are
+// compensated.
 #include "kernels.h"
 
 namespace dsbt {
@@ -146,27 +149,72 @@ __device__ __forceinline__ void dft8(V* v) {
 // the passes would wait for them too.
 template <typename T> using TabPtr = const typename CV<T>::t DSBT_GLOBAL*;
 
-// R consecutive complex values from a 16-byte aligned row.
-template <typename T, int R>
-__device__ __forceinline__ void load_row(TabPtr<T> row, typename CV<T>::t* out) {
-    if constexpr (sizeof(T) == sizeof(float)) {
-        const nf4 DSBT_GLOBAL* q = reinterpret_cast<const nf4 DSBT_GLOBAL*>(row);
-#pragma unroll
-        for (int i = 0; i < R / 2; ++i) {
-            const nf4 a = q[i];
-            out[2 * i] = make_float2(a.x, a.y);
-            out[2 * i + 1] = make_float2(a.z, a.w);
+// One quarter-circle root in LDS: FP64 (c, s), FP32 (c hi, s hi, c lo, s lo).
+template <typename T> struct Root;
+template <> struct Root<float> { typedef float t __attribute__((ext_vector_type(4))); };
+template <> struct Root<double> { typedef double t __attribute__((ext_vector_type(2))); };
+
+// Roots in LDS: e < N/4, or e <= N/8 (octant) where the quarter does not fit
+// beside the data (FP64 arithmetic at N = 8192).
+constexpr size_t kLdsMax = 160 * 1024;
+// channels per block: N/8 threads each, at least 256 threads per block
+constexpr int fstage_cpb(int N) { return N / 8 >= 256 ? 1 : 256 / (N / 8); }
+template <typename T>
+constexpr size_t fstage_root_offset(int N, int cpb) {
+    return (sizeof(typename CV<T>::t) * (size_t)cpb * (N + N / 32) + 15) / 16 * 16;
+}
+template <typename T>
+constexpr bool root_octant(int N) { return fstage_root_offset<T>(N, fstage_cpb(N)) + 16 * (size_t)(N / 4) > kLdsMax; }
+template <typename T>
+constexpr int root_count(int N) { return root_octant<T>(N) ? N / 8 + 1 : N / 4; }
+template <typename T>
+constexpr size_t fstage_lds_bytes(int N, int cpb) { return fstage_root_offset<T>(N, cpb) + 16 * (size_t)root_count<T>(N); }
+
+// z exp(-2 pi i m/N) for 0 <= m < Q N/4: z (c - i s) with the root of
+// e = m mod N/4 (octant tables: the root of N/4 - e with c and s exchanged
+// when e > N/8), then (-i)^q, q = m div N/4 < Q (exact swaps and sign changes).
+template <typename T, int N, int Q>
+__device__ __forceinline__ typename CV<T>::t root_mul(typename CV<T>::t z, const typename Root<T>::t* qt, int m) {
+    using V = typename CV<T>::t;
+    const int e = m & (N / 4 - 1);
+    typename Root<T>::t w;
+    if constexpr (root_octant<T>(N)) {
+        const bool sw = e > N / 8;
+        w = qt[sw ? N / 4 - e : e];
+        if (sw) {
+            if constexpr (sizeof(T) == sizeof(float)) w = w.yxwz;
+            else w = w.yx;
         }
     } else {
-#pragma unroll
-        for (int i = 0; i < R; ++i) out[i] = ld_c(row, i);
+        w = qt[e];
+    }
+    V y;
+    if constexpr (sizeof(T) == sizeof(float)) y = mul_unit(z, V{w.x, -w.y}, V{w.z, -w.w});
+    else y = f_mul(z, V{w.x, -w.y});
+    if constexpr (Q > 1) {
+        const int q = m / (N / 4);
+        if (q & 1) y = f_negi(y);
+        if constexpr (Q > 2) {
+            if (q & 2) y = V{-y.x, -y.y};
+        }
+    }
+    return y;
+}
+
+// v[r] *= w^r for r = R0 .. R - 1, w = exp(-2 pi i m1/N), m1 < N/R: r m1 spans
+// ceil(4 r/R) quarter turns.
+template <typename T, int N, int R, int R0 = 1>
+__device__ __forceinline__ void twiddle_row(typename CV<T>::t* v, const typename Root<T>::t* qt, int m1) {
+    if constexpr (R0 < R) {
+        v[R0] = root_mul<T, N, (4 * R0 + R - 1) / R>(v[R0], qt, R0 * m1);
+        twiddle_row<T, N, R, R0 + 1>(v, qt, m1);
     }
 }
 
 // One Stockham pass of radix R on the channel at buf (padded indexing);
 // thread t of the channel owns butterflies j = t + u N/8, u < 8/R.
 template <typename T, int N, int R>
-__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, TabPtr<T> tw, TabPtr<T> twl, int t) {
+__device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, const typename Root<T>::t* qt, int t) {
     using V = typename CV<T>::t;
     constexpr int NR = N / R, U = 8 / R;
     V v[U][R];
@@ -176,23 +224,8 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, TabPtr<
 #pragma unroll
         for (int r = 0; r < R; ++r) v[u][r] = buf[pidx(j + r * NR)];
         const int jm = j & (Ns - 1);
-        if (Ns > 1) {
-            // row jm of the pass table holds w^r, r < R, w = exp(-2 pi i jm/(Ns R));
-            // powers formed by repeated FP32 products would carry a magnitude
-            // bias of the order of the FP32 epsilon, the same for every
-            // butterfly of a pass with few distinct w
-            V wv[R];
-            load_row<T, R>(tw + jm * R, wv);
-            if constexpr (sizeof(T) == sizeof(float)) {
-                V wl[R];
-                load_row<T, R>(twl + jm * R, wl);
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[u][r] = mul_unit(v[u][r], wv[r], wl[r]);
-            } else {
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[u][r] = f_mul(v[u][r], wv[r]);
-            }
-        }
+        // w^r, w = exp(-2 pi i jm/(Ns R)) = exp(-2 pi i m1/N)
+        if (Ns > 1) twiddle_row<T, N, R>(v[u], qt, jm * (N / (Ns * R)));
         if constexpr (R == 8) dft8<T>(v[u]);
         else if constexpr (R == 4) dft4<T>(v[u]);
         else dft2<T>(v[u][0], v[u][1]);
@@ -209,19 +242,17 @@ __device__ __forceinline__ void fft_pass(typename CV<T>::t* buf, int Ns, TabPtr<
     lds_barrier();
 }
 
-// tw: the pass tables of every pass with Ns > 1, in pass order, each Ns rows of R.
 template <typename T, int N>
-__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, TabPtr<T> tw, TabPtr<T> twl, int t) {
+__device__ __forceinline__ void fft_n(typename CV<T>::t* buf, const typename Root<T>::t* qt, int t) {
     constexpr int L = __builtin_ctz(N);
-    int Ns = 1, off = 0;
+    int Ns = 1;
 #pragma unroll
     for (int s = 0; s < L / 3; ++s) {
-        fft_pass<T, N, 8>(buf, Ns, tw + off, twl + off, t);
-        if (Ns > 1) off += Ns * 8;
+        fft_pass<T, N, 8>(buf, Ns, qt, t);
         Ns *= 8;
     }
-    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, tw + off, twl + off, t);
-    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, tw + off, twl + off, t);
+    if constexpr (L % 3 == 1) fft_pass<T, N, 2>(buf, Ns, qt, t);
+    if constexpr (L % 3 == 2) fft_pass<T, N, 4>(buf, Ns, qt, t);
 }
 
 // The potential factor exp(-i s V tau/2) of point i: from the plan's table
@@ -284,8 +315,13 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     // barriers on a copy of the last descriptor (valid tables) and store nothing
     const bool live = cidx < nch;
     const FChan c = chans[live ? cidx : nch - 1];
-    const TabPtr<T> tw = as_global(reinterpret_cast<const V*>(c.tw));
-    const TabPtr<T> twl = as_global(reinterpret_cast<const V*>(c.tw_lo));
+    // the quarter-circle roots (all channels of a block have the same N) after the data
+    using RT = typename Root<T>::t;
+    RT* qt = reinterpret_cast<RT*>(smem_raw + fstage_root_offset<T>(N, cpb));
+    {
+        const RT DSBT_GLOBAL* g = as_global(static_cast<const RT*>(c.roots));
+        for (int i = threadIdx.x; i < root_count<T>(N); i += blockDim.x) qt[i] = g[i];
+    }
     const TabPtr<T> post = as_global(reinterpret_cast<const V*>(c.post));
     const TabPtr<T> postl = as_global(reinterpret_cast<const V*>(c.post_lo));
     // the sign (-1)^ceil(l/2) (an exact product); the orthonormal scales are in the post table
@@ -309,7 +345,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
             }
         }
         lds_barrier();
-        fft_n<T, N>(buf, tw, twl, t);
+        fft_n<T, N>(buf, qt, t);
         if (live) {
             // X_k for k = 2m, 2m + 1, stored as one 16-byte pair (reversed for the sine form)
             SV* y = dst + c.off;
@@ -378,7 +414,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
 #pragma unroll
         for (int u = 0; u < 8; ++u) buf[pidx(t + u * TPC)] = u8[u];
         lds_barrier();
-        fft_n<T, N>(buf, tw, twl, t);
+        fft_n<T, N>(buf, qt, t);
         if (live) {
             // v_j and v_{N-1-j} go out as the pair x_{2j}, x_{2j+1} (one 16-byte store)
             SV* x = dst + c.off;
@@ -401,7 +437,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
 // Threads per block for size N and channels per block.
 static inline void fstage_shape(int N, int& cpb, int& threads) {
     const int tpc = N / 8;
-    cpb = tpc >= 256 ? 1 : 256 / tpc;
+    cpb = fstage_cpb(N);
     threads = tpc * cpb;
 }
 
@@ -412,7 +448,7 @@ static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void
     int cpb, threads;
     fstage_shape(N, cpb, threads);
     const int blocks = (nch + cpb - 1) / cpb;
-    const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
+    const size_t lds = fstage_lds_bytes<T>(N, cpb);
 #define DSBT_FN(NN)                                                                                     \
     case NN:                                                                                            \
         hipLaunchKernelGGL((fstage_n<T, S, NN, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb, \
@@ -442,7 +478,7 @@ static hipError_t lds_attr_all() {
     auto set = [&](const void* f, int N) {
         int cpb, threads;
         fstage_shape(N, cpb, threads);
-        const size_t lds = sizeof(V) * (size_t)cpb * (N + N / 32);
+        const size_t lds = fstage_lds_bytes<T>(N, cpb);
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
     set((const void*)fstage_n<T, S, 16, INV>, 16);

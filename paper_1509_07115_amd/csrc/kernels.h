@@ -12,19 +12,17 @@ constexpr int kMaxChanPerItem = 16;  // channels sharing one moment-table pass
 //
 // An FP32 unit number has a modulus 1 + O(eps) with a fixed sign per entry,
 // and repeated transforms of the same data would turn products by it into a
-// norm drift.  So FP32 plans multiply by the FFT pass twiddles as three shears
-// (determinant one whatever their rounding; fft_lift_twiddles), and carry the
-// post-twiddles and phase factors as two FP32 complex tables of the same
-// layout, hi = the nearest FP32 value and lo = the FP32 rounding of the rest,
-// multiplied as z hi + z lo.  FP64 plans use (cos, sin) tables and have no lo
-// tables (nullptr).
+// norm drift.  So FP32 plans carry every unit factor (FFT roots, post-twiddles,
+// phase factors) as hi = the nearest FP32 value and lo = the FP32 rounding of
+// the rest, multiplied as z hi + z lo (mul_unit).  FP64 plans have no lo
+// parts (the lo pointers are nullptr).
 struct FChan {
     int64_t off;          // element offset of the channel in every data buffer
     int N, log2N;
     int p;                // 1: even l (DST-II), 0: odd l (DCT-II)
     float sign;           // (-1)^ceil(l/2), or +1 for the printed F
-    const void* tw;       // FFT pass tables (cos, sin) (fft_twiddles), arithmetic precision
-    const void* tw_lo;    // FP32 plans: the lo parts of tw
+    const void* roots;    // (cos, sin) of 2 pi e/N, e < N/4, 16 bytes per entry: FP64 (c, s) or
+                          // FP32 (c hi, s hi, c lo, s lo); the FFT passes form their twiddles from it
     const void* post;     // exp(-i pi t/(2N)), t < N
     const void* post_lo;  // FP32 plans: the lo parts of post
     const void* vphase;   // exp(-i V tau/2) per point (complex of the arithmetic precision), or nullptr
@@ -103,18 +101,6 @@ __device__ __forceinline__ float mul_const(float x, float hi, float lo) {
     const float p = x * hi;
     const float e = __builtin_fmaf(x, hi, -p);
     return p + __builtin_fmaf(x, lo, e);
-}
-
-// z (-1)^h exp(i theta') for an FFT twiddle given as shear coefficients
-// ts = (-tan(theta'/2), sin(theta')) whose lowest bit of s is h mod 2
-// (fft_lift_twiddles): the exact sign change, then x += t y, y += s x, x += t y.
-__device__ __forceinline__ float2 mul_shear(float2 z, float2 ts) {
-    const unsigned neg = __float_as_uint(ts.y) << 31;
-    float x = __uint_as_float(__float_as_uint(z.x) ^ neg), y = __uint_as_float(__float_as_uint(z.y) ^ neg);
-    x = __builtin_fmaf(ts.x, y, x);
-    y = __builtin_fmaf(ts.y, x, y);
-    x = __builtin_fmaf(ts.x, y, x);
-    return make_float2(x, y);
 }
 
 // z w for a unit number w = h + l carried as FP32 hi and lo parts (FChan):

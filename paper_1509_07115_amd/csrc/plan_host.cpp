@@ -300,64 +300,24 @@ void corrected_momenta(int N, int ell, double rmax, double* k) {
     }
 }
 
-void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post) {
+void fft_quarter_roots(int N, std::vector<double>& cs) {
     const double pi = 3.14159265358979323846;
-    // Stockham passes of radix 8, then one of radix 2 or 4; the pass with
-    // span Ns (> 1) and radix R has Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R))
-    int L = 0;
-    while ((1 << L) < N) ++L;
-    std::vector<std::pair<int, int>> passes;   // (Ns, R)
-    int Ns = 1;
-    for (int s = 0; s < L / 3; ++s, Ns *= 8) passes.emplace_back(Ns, 8);
-    if (L % 3) passes.emplace_back(Ns, L % 3 == 1 ? 2 : 4);
-    tw.clear();
-    for (auto [ns, R] : passes) {
-        if (ns == 1) continue;
-        for (int jm = 0; jm < ns; ++jm)
-            for (int r = 0; r < R; ++r) {
-                const double a = -2.0 * pi * (double)((int64_t)r * jm) / (double)(ns * R);
-                tw.push_back(std::cos(a));
-                tw.push_back(std::sin(a));
-            }
+    cs.resize(2 * (size_t)(N / 4));
+    for (int e = 0; e < N / 4; ++e) {
+        const double a = 2.0 * pi * e / (double)N;
+        cs[2 * e] = std::cos(a);
+        cs[2 * e + 1] = std::sin(a);
     }
-    if (tw.empty()) tw.assign(2, 1.0), tw[1] = 0.0;
+}
+
+void fft_post_twiddles(int N, std::vector<double>& post) {
+    const double pi = 3.14159265358979323846;
     post.resize(2 * (size_t)N);
     for (int t = 0; t < N; ++t) {
         const double b = -pi * t / (2.0 * N);
         post[2 * t] = std::cos(b);
         post[2 * t + 1] = std::sin(b);
     }
-}
-
-void fft_lift_twiddles(int N, std::vector<float>& ts) {
-    const double pi = 3.14159265358979323846;
-    int L = 0;
-    while ((1 << L) < N) ++L;
-    std::vector<std::pair<int, int>> passes;   // (Ns, R), as fft_twiddles
-    int Ns = 1;
-    for (int s = 0; s < L / 3; ++s, Ns *= 8) passes.emplace_back(Ns, 8);
-    if (L % 3) passes.emplace_back(Ns, L % 3 == 1 ? 2 : 4);
-    ts.clear();
-    for (auto [ns, R] : passes) {
-        if (ns == 1) continue;
-        const int64_t RN = (int64_t)R * ns;
-        for (int jm = 0; jm < ns; ++jm)
-            for (int r = 0; r < R; ++r) {
-                const int64_t a = 2 * (int64_t)r * jm;         // theta = -pi a / RN
-                const int64_t h = (2 * a + RN) / (2 * RN);     // nearest number of half turns
-                // theta' = theta + h pi = pi (h RN - a) / RN, an exact rational
-                const double th = pi * (double)(h * RN - a) / (double)RN;
-                const float t = (float)(-std::tan(0.5 * th));
-                float s = (float)std::sin(th);
-                uint32_t bits;
-                std::memcpy(&bits, &s, sizeof(bits));
-                bits = (bits & ~1u) | (uint32_t)(h & 1);
-                std::memcpy(&s, &bits, sizeof(bits));
-                ts.push_back(t);
-                ts.push_back(s);
-            }
-    }
-    if (ts.empty()) ts.assign(2, 0.0f);
 }
 
 }  // namespace dsbt

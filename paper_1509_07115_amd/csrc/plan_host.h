@@ -54,19 +54,12 @@ void arrange_mfma_blocks(const std::vector<double>& blocks, int B, int k, int p,
 // odd l (Sec. 3, eq. kcorr), FP64, bracketed on a scan from x = 0 and bisected.
 void corrected_momenta(int N, int ell, double rmax, double* k);
 
-// FP64 tables of the size-N transform as interleaved (re, im): tw, the pass
-// tables of the FFT (for each Stockham pass with span Ns > 1 and radix R, in
-// pass order, Ns rows of w^r, r < R, w = exp(-2 pi i jm/(Ns R)); radix 8 then
-// one radix-2 or radix-4 pass), and post, exp(-i pi k/(2N)), k < N.
-void fft_twiddles(int N, std::vector<double>& tw, std::vector<double>& post);
-
-// The pass twiddles of fft_twiddles in the form the FP32 kernels multiply by:
-// w = exp(i theta) = (-1)^h exp(i theta'), h = floor((4 r jm + R Ns) / (2 R Ns))
-// (half turns), |theta'| <= pi/2, and the rotation by theta' taken as the three
-// shears x += t y, y += s x, x += t y with t = -tan(theta'/2), s = sin(theta').
-// Same layout as tw: (t, s) pairs of FP32 values; the lowest bit of s holds
-// h mod 2 (the kernel negates the input when it is set; a change of s by one
-// unit in the last place leaves every shear of determinant one).
-void fft_lift_twiddles(int N, std::vector<float>& ts);
+// FP64 tables of the size-N sine/cosine stage as interleaved pairs:
+// fft_quarter_roots, (cos, sin) of 2 pi e/N for e < N/4, from which the FFT
+// kernels form every pass twiddle exp(-2 pi i m/N) (m = e + q N/4: the
+// product by exp(-2 pi i e/N), then by (-i)^q); fft_post_twiddles,
+// exp(-i pi k/(2N)) for k < N.
+void fft_quarter_roots(int N, std::vector<double>& cs);
+void fft_post_twiddles(int N, std::vector<double>& post);
 
 }  // namespace dsbt
