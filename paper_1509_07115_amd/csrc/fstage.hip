@@ -167,8 +167,17 @@ template <typename T>
 constexpr bool root_octant(int N) { return fstage_root_offset<T>(N, fstage_cpb(N)) + 16 * (size_t)(N / 4) > kLdsMax; }
 template <typename T>
 constexpr int root_count(int N) { return root_octant<T>(N) ? N / 8 + 1 : N / 4; }
+// LDS slots of the roots: root e sits at slot root_slot(e), a permutation
+// within each aligned group of 16 (so the table takes root_count rounded up to
+// 16 slots) that spreads the power-of-two strides of the passes' reads over
+// the LDS banks.
+__device__ __forceinline__ int root_slot(int e) {
+    return __builtin_amdgcn_ubfe(e ^ (e >> 4) ^ (e >> 8), 0, 4) | (e & ~15);
+}
 template <typename T>
-constexpr size_t fstage_lds_bytes(int N, int cpb) { return fstage_root_offset<T>(N, cpb) + 16 * (size_t)root_count<T>(N); }
+constexpr size_t fstage_lds_bytes(int N, int cpb) {
+    return fstage_root_offset<T>(N, cpb) + 16 * (size_t)((root_count<T>(N) + 15) / 16 * 16);
+}
 
 // z exp(-2 pi i m/N) for 0 <= m < Q N/4: z (c - i s) with the root of
 // e = m mod N/4 (octant tables: the root of N/4 - e with c and s exchanged
@@ -180,13 +189,13 @@ __device__ __forceinline__ typename CV<T>::t root_mul(typename CV<T>::t z, const
     typename Root<T>::t w;
     if constexpr (root_octant<T>(N)) {
         const bool sw = e > N / 8;
-        w = qt[sw ? N / 4 - e : e];
+        w = qt[root_slot(sw ? N / 4 - e : e)];
         if (sw) {
             if constexpr (sizeof(T) == sizeof(float)) w = w.yxwz;
             else w = w.yx;
         }
     } else {
-        w = qt[e];
+        w = qt[root_slot(e)];
     }
     V y;
     if constexpr (sizeof(T) == sizeof(float)) y = mul_unit(z, V{w.x, -w.y}, V{w.z, -w.w});
@@ -320,7 +329,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     RT* qt = reinterpret_cast<RT*>(smem_raw + fstage_root_offset<T>(N, cpb));
     {
         const RT DSBT_GLOBAL* g = as_global(static_cast<const RT*>(c.roots));
-        for (int i = threadIdx.x; i < root_count<T>(N); i += blockDim.x) qt[i] = g[i];
+        for (int i = threadIdx.x; i < root_count<T>(N); i += blockDim.x) qt[root_slot(i)] = g[i];
     }
     const TabPtr<T> post = as_global(reinterpret_cast<const V*>(c.post));
     const TabPtr<T> postl = as_global(reinterpret_cast<const V*>(c.post_lo));
