@@ -192,7 +192,7 @@ def other_workloads(progress):
     def grad_pass(pl):
         p0 = torch.from_numpy(w.psi).to(torch.complex64).cuda().requires_grad_(True)
         st = s.clone().requires_grad_(True)
-        z = torch.vdot(phi, propagate(pl, p0, st, checkpoint_every=20))
+        z = torch.vdot(phi, propagate(pl, p0, st, checkpoint_every=20, graph=True))
         ((z * z.conj()).real).backward()
     grad_pass(plan)
     ms = _timed(lambda: grad_pass(plan), 2)

@@ -212,6 +212,26 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
 dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
                              const void* lam_t, const void* lam_t1, double* out, void* stream);
 
+/* Backward pass of one checkpoint segment of the adjoint method (Sec. 4.1:
+ * U_t^H = U_t^-1, so lam_t = U_t^H lam_{t+1} is a split step with conjugated
+ * phases).  Inputs: psi_a, the state before step a; s, the n strengths
+ * s_a .. s_{a+n-1} (device FP32); lam = lam_{a+n} (device, data layout).
+ * The call recomputes psi_{a+1} .. psi_{a+n} from psi_a, then for
+ * t = a+n-1 .. a forms lam_t and gs[t-a] = dL/ds_t exactly as
+ * dsbt_step_grad_s does, and leaves lam_a in lam (psi_a is not written).
+ * gs: device FP64 array of n values, written.  All work runs on plan-owned
+ * buffers (n + 3 states, grown through the plan's allocator to the largest n
+ * seen; a call that grows them synchronises `stream`): the inputs are copied
+ * in and the results out on `stream`.  flags: 0, or DSBT_STEP_GRAPH: the
+ * segment's launches (n steps, n adjoint steps, n reductions) are captured
+ * once in a hipGraph on those buffers and replayed, so every later call with
+ * the same n replays it.  Checked plans scan psi_a and lam before and lam
+ * after, synchronising, and do not use the graph.  Needs dsbt_set_potential
+ * in real time (else DSBT_ERR_PLAN_MISMATCH); n < 1 or other flag bits:
+ * DSBT_ERR_INVALID_ARG. */
+dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps, const float* s, void* lam,
+                                 double* gs, int32_t flags, void* stream);
+
 /* dsbt_step_grad_s for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same kernels and result, with the per-channel FP64 partial sums in a

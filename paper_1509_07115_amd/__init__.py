@@ -250,6 +250,24 @@ class Plan:
                                               _stream_handle(stream)), "dsbt_step_grad_s")
         return out
 
+    def adjoint_segment(self, psi_a, nsteps: int, s, lam, gs, graph: bool = False, stream=None):
+        """Backward pass of one checkpoint segment (``dsbt_adjoint_segment``): lam_{a+n} -> lam_a in
+        place in lam, gs[t-a] = dL/ds_t; psi_a is the state before the segment; s and gs: cuda float32 and
+        float64 tensors of nsteps values."""
+        import torch
+        if not (isinstance(s, torch.Tensor) and s.is_cuda and s.dtype == torch.float32 and s.is_contiguous()
+                and s.numel() >= nsteps):
+            raise TypeError("s must be a contiguous cuda float32 tensor with nsteps entries")
+        if not (isinstance(gs, torch.Tensor) and gs.is_cuda and gs.dtype == torch.float64 and gs.is_contiguous()
+                and gs.numel() >= nsteps):
+            raise TypeError("gs must be a contiguous cuda float64 tensor with nsteps entries")
+        _lib.check(self._lib.dsbt_adjoint_segment(self._h, self._check_buf(psi_a, "psi_a"), int(nsteps),
+                                                  ctypes.c_void_p(s.data_ptr()), self._check_buf(lam, "lam"),
+                                                  ctypes.c_void_p(gs.data_ptr()),
+                                                  _lib.DSBT_STEP_GRAPH if graph else 0, _stream_handle(stream)),
+                   "dsbt_adjoint_segment")
+        return lam
+
     def profile(self, enable: bool = True, clear: bool = True):
         """Start or stop per-stage HIP-event timing (``dsbt_profile_enable``);
         ``clear=False`` resumes without clearing what was recorded."""

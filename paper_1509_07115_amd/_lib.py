@@ -27,7 +27,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "dsbt_plan_opts_default", "dsbt_plan_create", "dsbt_plan_create_uniform", "dsbt_plan_destroy",
     "dsbt_plan_info", "dsbt_forward", "dsbt_inverse", "dsbt_set_potential", "dsbt_set_potential_ex",
-    "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_step_grad_s_noalloc", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
+    "dsbt_kinetic_step", "dsbt_step_grad_s", "dsbt_step_grad_s_noalloc", "dsbt_adjoint_segment", "dsbt_energy", "dsbt_orthonormalize", "dsbt_profile_enable",
     "dsbt_profile_read", "dsbt_host_ftb_tables", "dsbt_host_monomial_tables", "dsbt_device_ftb_tables",
     "dsbt_kinetic_momenta", "dsbt_autotune", "dsbt_sht_grid", "dsbt_sht_host_tables", "dsbt_sht_create",
     "dsbt_sht_destroy", "dsbt_sht_forward", "dsbt_sht_inverse", "dsbt_sht_potential_phase",
@@ -91,6 +91,7 @@ def load() -> ctypes.CDLL:
         "dsbt_kinetic_step": (i32, [P, P, i32, P, i32, P]),
         "dsbt_step_grad_s": (i32, [P, P, P, P, P, P, P]),
         "dsbt_step_grad_s_noalloc": (i32, [P, P, P, P, P, P, P]),
+        "dsbt_adjoint_segment": (i32, [P, P, i32, P, P, P, i32, P]),
         "dsbt_profile_enable": (i32, [P, i32]),
         "dsbt_profile_read": (i32, [P, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "dsbt_host_ftb_tables": (i32, [i32, i32, i32, ctypes.POINTER(dbl), i64, ctypes.POINTER(i64)]),

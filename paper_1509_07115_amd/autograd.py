@@ -14,10 +14,12 @@ strengths s_t and returns psi_n; its backward pass is the adjoint method:
     dL/ds_t = (tau/2) sum_i V_i Im(conj(lam_{t+1,i}) psi_{t+1,i} + conj(lam_{t,i}) psi_{t,i}),
 
 and dL/dpsi_0 = lam_0.  The states psi_t are not kept: the forward pass stores
-psi at every ``checkpoint_every``-th step, and the backward pass recomputes the
-states of one segment at a time from its checkpoint.  Every step, adjoint step
-and reduction runs in the library's kernels (``Plan.kinetic_step``,
-``Plan.step_grad_s``); this module only orders the calls and holds tensors.
+psi at every ``checkpoint_every``-th step, and the backward pass hands one
+segment at a time to the library (``Plan.adjoint_segment``), which recomputes
+the segment's states from its checkpoint and runs its adjoint steps and
+reductions, from one captured graph per segment length when ``graph`` is set.
+Every step runs in the library's kernels (``Plan.kinetic_step`` forward); this
+module only orders the calls and holds tensors.
 """
 from __future__ import annotations
 
@@ -37,31 +39,24 @@ class _Propagate(torch.autograd.Function):
             n = min(every, nsteps - a)
             ckpts.append(psi.clone())
             plan.kinetic_step(psi, n, s32[a:a + n], graph=graph)
-        ctx.plan, ctx.every, ctx.s_dtype = plan, every, s.dtype
+        ctx.plan, ctx.every, ctx.graph, ctx.s_dtype = plan, every, graph, s.dtype
         ctx.save_for_backward(s32, *ckpts)
         return psi
 
     @staticmethod
     def backward(ctx, grad_out):
         s32, *ckpts = ctx.saved_tensors
-        plan, every = ctx.plan, ctx.every
+        plan, every, graph = ctx.plan, ctx.every, ctx.graph
         nsteps = int(s32.numel())
         lam = grad_out.detach().clone(memory_format=torch.contiguous_format)
-        gs = torch.zeros(nsteps, dtype=torch.float64, device=s32.device)
+        gs = torch.empty(nsteps, dtype=torch.float64, device=s32.device)
+        # per segment, last first: recompute psi_a .. psi_{a+n} from the
+        # checkpoint and run the n adjoint steps and strength gradients, all
+        # in the library (one graph replay per segment when graph is set)
         for seg in range(len(ckpts) - 1, -1, -1):
             a = seg * every
             n = min(every, nsteps - a)
-            # psi_a .. psi_{a+n}, recomputed from the checkpoint by the same kernels
-            states = [ckpts[seg]]
-            for t in range(a, a + n):
-                x = states[-1].clone()
-                plan.kinetic_step(x, 1, s32[t:t + 1])
-                states.append(x)
-            for t in range(a + n - 1, a - 1, -1):
-                lam_next = lam
-                lam = lam_next.clone()
-                plan.kinetic_step(lam, 1, s32[t:t + 1], adjoint=True)
-                plan.step_grad_s(states[t - a], states[t - a + 1], lam, lam_next, gs[t:t + 1])
+            plan.adjoint_segment(ckpts[seg], n, s32[a:a + n], lam, gs[a:a + n], graph=graph)
         g_s = gs.to(ctx.s_dtype) if ctx.needs_input_grad[1] else None
         g_psi = lam if ctx.needs_input_grad[0] else None
         return g_psi, g_s, None, None, None
@@ -73,9 +68,10 @@ def propagate(plan, psi0: torch.Tensor, s: torch.Tensor, checkpoint_every: int =
 
     plan: a Plan with a potential set (``Plan.set_potential``); psi0: a device
     tensor in the plan's data layout and dtype; s: a real device tensor of n
-    strengths; checkpoint_every: steps between stored states (memory is
-    len/checkpoint_every + checkpoint_every + 2 state buffers in the backward
-    pass); graph: capture each forward segment in a hipGraph.
+    strengths; checkpoint_every: steps between stored states (memory: the
+    len/checkpoint_every checkpoints, plus checkpoint_every + 3 state buffers
+    that the plan holds for the backward pass); graph: capture each forward segment, and each backward segment, in a
+    hipGraph.
     """
     if checkpoint_every < 1:
         raise ValueError("checkpoint_every must be >= 1")

@@ -216,6 +216,18 @@ struct dsbt_plan_s {
     float* d_sgraph = nullptr;    // strengths staged for graph replays
     int sgraph_cap = 0;
 
+    // dsbt_adjoint_segment: states psi_a .. psi_a+n, two adjoint states, the
+    // segment's strengths and gradients (plan buffers, grown to the largest n),
+    // and the graph of one segment's launches on them
+    void* seg_states = nullptr;
+    void* seg_lam = nullptr;
+    float* seg_s = nullptr;
+    double* seg_gs = nullptr;
+    int seg_cap = 0;
+    hipGraphExec_t seg_exec = nullptr;
+    hipGraph_t seg_graph = nullptr;
+    int seg_graph_n = 0;
+
     // checked plans (opts.check_finite): device flag and its pinned host copy
     int* d_flag = nullptr;
     int* h_flag = nullptr;
@@ -246,11 +258,30 @@ struct dsbt_plan_s {
         table_bytes += (int64_t)(bytes == 0 ? 16 : bytes);
         return p;
     }
-    void release() {
+    void drop_graphs() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         graph_exec = nullptr;
         graph = nullptr;
+        if (seg_exec) (void)hipGraphExecDestroy(seg_exec);
+        if (seg_graph) (void)hipGraphDestroy(seg_graph);
+        seg_exec = nullptr;
+        seg_graph = nullptr;
+        seg_graph_n = 0;
+    }
+    void free_segment() {
+        dfree(seg_states);
+        dfree(seg_lam);
+        dfree(seg_s);
+        dfree(seg_gs);
+        seg_states = seg_lam = nullptr;
+        seg_s = nullptr;
+        seg_gs = nullptr;
+        seg_cap = 0;
+    }
+    void release() {
+        drop_graphs();
+        free_segment();
         for (void* p : allocs) dfree(p);
         allocs.clear();
         if (h_flag) (void)hipHostFree(h_flag);
@@ -829,6 +860,55 @@ void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool 
     }
 }
 
+// Captures what `enqueue` launches (on a capture stream) as a graph and instantiates it.
+template <typename F>
+void capture_graph(F&& enqueue, hipGraph_t* graph, hipGraphExec_t* exec) {
+    hipStream_t cap;
+    hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        try {
+            enqueue(cap);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cap, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cap);
+            throw;
+        }
+        e = hipStreamEndCapture(cap, graph);
+    }
+    (void)hipStreamDestroy(cap);
+    hip_check(e, "graph capture");
+    hip_check(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0), "graph instantiate");
+}
+
+// One checkpoint segment of the adjoint method on the plan's segment buffers
+// (dsbt_adjoint_segment): states 1..n from state 0, then the n adjoint steps
+// and strength gradients, lam_{t+1} -> lam_t alternating between the two
+// adjoint buffers (lam_a ends in buffer n mod 2).
+template <typename T, typename S>
+void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
+    const size_t sb = (size_t)P->elems * P->elem_bytes;
+    auto state = [&](int t) { return static_cast<unsigned char*>(P->seg_states) + sb * (size_t)t; };
+    unsigned char* lam[2] = {static_cast<unsigned char*>(P->seg_lam), static_cast<unsigned char*>(P->seg_lam) + sb};
+    const int nch = (int)P->ch.size();
+    for (int t = 0; t < n; ++t) {
+        const dsbt::PhaseArgs pv{1, 0, P->seg_s, t}, pk{1, 0, nullptr, 0};
+        enqueue_forward<T, S>(P, state(t), state(t + 1), q, pv, pk);
+        enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv);
+    }
+    int cur = 0;   // lam[cur] holds lam_{t+1}
+    for (int t = n - 1; t >= 0; --t) {
+        const dsbt::PhaseArgs pv{1, 1, P->seg_s, t}, pk{1, 1, nullptr, 0};
+        enqueue_forward<T, S>(P, lam[cur], lam[cur ^ 1], q, pv, pk);
+        enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv);
+        hip_check(dsbt::launch_grad_s<S>(P->d_fchans, nch, state(t), state(t + 1), lam[cur ^ 1], lam[cur],
+                                         P->d_scratch, P->seg_gs + t, q), "grad_s");
+        cur ^= 1;
+    }
+}
+
 // Checked plans: scan the channels of `data` for NaN and infinities on s and
 // wait for the answer.
 void check_finite_data(dsbt_plan_s* P, const void* data, hipStream_t s, const char* what) {
@@ -1093,12 +1173,7 @@ dsbt_status dsbt_set_potential_ex(dsbt_plan p, const double* V, double dt, int32
         p->has_potential = true;
         p->imaginary = imag;
         p->dt = dt;
-        if (p->graph_exec) {
-            (void)hipGraphExecDestroy(p->graph_exec);
-            (void)hipGraphDestroy(p->graph);
-            p->graph_exec = nullptr;
-            p->graph = nullptr;
-        }
+        p->drop_graphs();
         return DSBT_OK;
     });
 }
@@ -1152,24 +1227,7 @@ dsbt_status dsbt_kinetic_step(dsbt_plan p, void* psi, int32_t nsteps, const floa
                 p->graph_exec = nullptr;
                 p->graph = nullptr;
             }
-            hipStream_t cap;
-            hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
-            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                try {
-                    enqueue(cap);
-                } catch (...) {
-                    hipGraph_t g;
-                    (void)hipStreamEndCapture(cap, &g);
-                    if (g) (void)hipGraphDestroy(g);
-                    (void)hipStreamDestroy(cap);
-                    throw;
-                }
-                e = hipStreamEndCapture(cap, &p->graph);
-            }
-            (void)hipStreamDestroy(cap);
-            hip_check(e, "graph capture");
-            hip_check(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0), "graph instantiate");
+            capture_graph(enqueue, &p->graph, &p->graph_exec);
             p->graph_key = key;
         }
         hip_check(hipGraphLaunch(p->graph_exec, st), "graph launch");
@@ -1192,6 +1250,66 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
         else
             hip_check(dsbt::launch_grad_s<float>(p->d_fchans, nch, psi_t, psi_t1, lam_t, lam_t1, p->d_scratch, out,
                                                  st), "grad_s");
+        return DSBT_OK;
+    });
+}
+
+dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps, const float* s, void* lam,
+                                 double* gs, int32_t flags, void* stream) {
+    Range range("dsbt_adjoint_segment");
+    if (!p || !psi_a || !s || !lam || !gs) return fail(DSBT_ERR_INVALID_ARG, "NULL argument");
+    if (nsteps < 1) return fail(DSBT_ERR_INVALID_ARG, "a segment has at least one step");
+    if (flags & ~DSBT_STEP_GRAPH) return fail(DSBT_ERR_INVALID_ARG, "unknown segment flag");
+    if (!p->has_potential) return fail(DSBT_ERR_PLAN_MISMATCH, "dsbt_set_potential has not been called");
+    if (p->imaginary) return fail(DSBT_ERR_PLAN_MISMATCH, "the potential was set for imaginary time");
+    return guarded([&]() -> dsbt_status {
+        hipStream_t st = (hipStream_t)stream;
+        const size_t sb = (size_t)p->elems * p->elem_bytes;
+        if (p->opts.check_finite) {
+            check_finite_data(p, psi_a, st, "dsbt_adjoint_segment psi_a");
+            check_finite_data(p, lam, st, "dsbt_adjoint_segment lam");
+            flags &= ~DSBT_STEP_GRAPH;
+        }
+        if (p->seg_cap < nsteps) {
+            hip_check(hipStreamSynchronize(st), "segment buffers");   // the old buffers may still be read
+            p->drop_graphs();
+            p->free_segment();
+            p->seg_states = p->dalloc_raw(sb * (size_t)(nsteps + 1));
+            p->seg_lam = p->dalloc_raw(2 * sb);
+            p->seg_s = static_cast<float*>(p->dalloc_raw(sizeof(float) * (size_t)nsteps));
+            p->seg_gs = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps));
+            p->seg_cap = nsteps;
+        }
+        hip_check(hipMemcpyAsync(p->seg_states, psi_a, sb, hipMemcpyDeviceToDevice, st), "segment psi_a");
+        hip_check(hipMemcpyAsync(p->seg_lam, lam, sb, hipMemcpyDeviceToDevice, st), "segment lam");
+        hip_check(hipMemcpyAsync(p->seg_s, s, sizeof(float) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
+                  "segment strengths");
+        auto enqueue = [&](hipStream_t q) {
+            if (p->precision == DSBT_C128)
+                enqueue_segment<double, double>(p, nsteps, q);
+            else if (p->precision == DSBT_C64_FP64)
+                enqueue_segment<double, float>(p, nsteps, q);
+            else
+                enqueue_segment<float, float>(p, nsteps, q);
+        };
+        if (flags & DSBT_STEP_GRAPH) {
+            if (!p->seg_exec || p->seg_graph_n != nsteps) {
+                if (p->seg_exec) (void)hipGraphExecDestroy(p->seg_exec);
+                if (p->seg_graph) (void)hipGraphDestroy(p->seg_graph);
+                p->seg_exec = nullptr;
+                p->seg_graph = nullptr;
+                capture_graph(enqueue, &p->seg_graph, &p->seg_exec);
+                p->seg_graph_n = nsteps;
+            }
+            hip_check(hipGraphLaunch(p->seg_exec, st), "graph launch");
+        } else {
+            enqueue(st);
+        }
+        const unsigned char* lam_a = static_cast<const unsigned char*>(p->seg_lam) + sb * (size_t)(nsteps & 1);
+        hip_check(hipMemcpyAsync(lam, lam_a, sb, hipMemcpyDeviceToDevice, st), "segment lam_a");
+        hip_check(hipMemcpyAsync(gs, p->seg_gs, sizeof(double) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
+                  "segment gradients");
+        if (p->opts.check_finite) check_finite_data(p, lam, st, "dsbt_adjoint_segment result");
         return DSBT_OK;
     });
 }

@@ -21,6 +21,10 @@ class OraclePlan:
 
     def kinetic_step(self, psi, nsteps, s=None, adjoint=False, graph=False):
         self.calls.append(("step", nsteps, adjoint))
+        return self._steps(psi, s[:nsteps], adjoint)
+
+    def _steps(self, psi, s, adjoint=False):
+        nsteps = len(s)
         x = psi.numpy()
         sv = s.numpy().astype(np.float64)
         order = range(nsteps - 1, -1, -1) if adjoint else range(nsteps)
@@ -35,6 +39,21 @@ class OraclePlan:
         a, b, c, d = (v.numpy() for v in (psi_t, psi_t1, lam_t, lam_t1))
         out[0] = 0.5 * self.dt * float(np.sum(self.V * (np.conj(d) * b + np.conj(c) * a).imag))
         return out
+
+    def adjoint_segment(self, psi_a, nsteps, s, lam, gs, graph=False):
+        """The library's segment call: recompute psi_a .. psi_a+n, then
+        lam_t = U_t^H lam_t+1 and gs[t - a] for t = a+n-1 .. a."""
+        self.calls.append(("segment", nsteps, graph))
+        states = [psi_a.clone()]
+        for t in range(nsteps):
+            x = states[-1].clone()
+            self._steps(x, s[t:t + 1])
+            states.append(x)
+        for t in range(nsteps - 1, -1, -1):
+            lam_next = lam.clone()
+            self._steps(lam, s[t:t + 1], adjoint=True)
+            self.step_grad_s(states[t], states[t + 1], lam, lam_next, gs[t:t + 1])
+        return lam
 
 
 def _case(seed=0):
@@ -92,14 +111,15 @@ def test_checkpointed_adjoint_matches_torch_autograd(nsteps, every):
     assert abs(L.item() - Lr) < 1e-12
     assert np.max(np.abs(p0.grad.numpy() - gp)) < 1e-12
     assert np.max(np.abs(st.grad.numpy().astype(np.float64) - gs)) < 1e-6 * max(1.0, np.max(np.abs(gs)))
-    # forward: one multi-step call per segment; backward: per segment, single
-    # recompute steps forward then single adjoint steps
+    # forward: one multi-step call per segment; backward: one segment call per
+    # segment, last segment first
     nseg = -(-nsteps // every)
-    fwd = [c for c in plan.calls[:nseg]]
+    fwd = plan.calls[:nseg]
     assert all(c[0] == "step" and not c[2] for c in fwd)
     assert sum(c[1] for c in fwd) == nsteps
-    adj = [c for c in plan.calls[nseg:] if c[2]]
-    assert len(adj) == nsteps and all(c[1] == 1 for c in adj)
+    bwd = plan.calls[nseg:]
+    assert [c[0] for c in bwd] == ["segment"] * nseg
+    assert [c[1] for c in bwd] == [min(every, nsteps - a) for a in range(0, nsteps, every)][::-1]
 
 
 def test_gradient_matches_oracle_adjoint():

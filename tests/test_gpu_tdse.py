@@ -115,6 +115,47 @@ def test_adjoint_full_size_sampled_channels():
     assert np.max(np.abs(gs - gsr)) <= 1e-4 * np.max(np.abs(gsr))
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_adjoint_segment_matches_single_step_calls(precision):
+    # dsbt_adjoint_segment against the same recurrence run as separate
+    # dsbt_kinetic_step / dsbt_step_grad_s calls; eager and graph replays, a
+    # second segment length (a new capture), then the first length again
+    w = workloads.adjoint(N=512, rmax=51.2, lmax=5, nsteps=7)
+    plan = Plan(w.channels, precision=precision)
+    plan.set_potential(w.extra["V"], w.extra["dt"])
+    rng = np.random.default_rng(11)
+    s_all = dev(rng.uniform(0.8, 1.2, 7), torch.float32)
+    psi_a = dev(w.psi, plan.dtype)
+    lam0 = dev(w.extra["phi"] * (0.3 + 0.1j), plan.dtype)
+
+    def reference(n, s):
+        states = [psi_a.clone()]
+        for t in range(n):
+            x = states[-1].clone()
+            plan.kinetic_step(x, 1, s[t:t + 1])
+            states.append(x)
+        lam = lam0.clone()
+        gs = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for t in range(n - 1, -1, -1):
+            nxt = lam.clone()
+            plan.kinetic_step(lam, 1, s[t:t + 1], adjoint=True)
+            plan.step_grad_s(states[t], states[t + 1], lam, nxt, gs[t:t + 1])
+        return lam, gs
+
+    for n, s0, graph in ((4, 0, False), (4, 0, True), (3, 4, True), (4, 3, True), (4, 3, False)):
+        s = s_all[s0:s0 + n].contiguous()
+        lam_r, gs_r = reference(n, s)
+        lam = lam0.clone()
+        gs = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        plan.adjoint_segment(psi_a, n, s, lam, gs, graph=graph)
+        torch.cuda.synchronize()
+        scale = float(torch.max(torch.abs(lam_r)).item())
+        assert float(torch.max(torch.abs(lam - lam_r)).item()) <= 1e-6 * scale, (n, graph)
+        assert torch.allclose(gs, gs_r, rtol=1e-6, atol=1e-9 * float(torch.max(torch.abs(gs_r)).item())), (n, graph)
+    # the input state is left as it was
+    assert torch.equal(psi_a, dev(w.psi, plan.dtype))
+
+
 def test_adjoint_full_size_finite_differences():
     # full phi; FP64 (c128) plan: central differences on 5 strengths and 4
     # random directions of psi0; the c64 gradient against the same differences
