@@ -849,14 +849,42 @@ void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
         });
 }
 
+// nsteps split steps in place.  Batched plans run one step's inverse sine /
+// cosine stage and the next step's forward one as a single launch
+// (launch_fstage_inv_fwd), so a step costs three launches and three passes
+// over the data instead of four.
 template <typename T, typename S>
 void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool adjoint, hipStream_t s) {
-    for (int u = 0; u < nsteps; ++u) {
+    auto pv_of = [&](int u) {
         const int t = adjoint ? (nsteps - 1 - u) : u;
-        dsbt::PhaseArgs pv{1, adjoint ? 1 : 0, sc, t};
-        dsbt::PhaseArgs pk{1, adjoint ? 1 : 0, nullptr, 0};
-        enqueue_forward<T, S>(P, psi, psi, s, pv, pk);
-        enqueue_inverse<T, S>(P, psi, psi, s, pv);
+        return dsbt::PhaseArgs{1, adjoint ? 1 : 0, sc, t};
+    };
+    const dsbt::PhaseArgs pk{1, adjoint ? 1 : 0, nullptr, 0}, none{};
+    if (P->opts.mode == DSBT_MODE_PLAIN) {
+        for (int u = 0; u < nsteps; ++u) {
+            enqueue_forward<T, S>(P, psi, psi, s, pv_of(u), pk);
+            enqueue_inverse<T, S>(P, psi, psi, s, pv_of(u));
+        }
+        return;
+    }
+    for (auto& r : P->n_ranges)
+        timed(P, DSBT_STAGE_SINCOS, s, [&] {
+            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), psi,
+                                               psi, false, pv_of(0), s), "fstage");
+        });
+    for (int u = 0; u < nsteps; ++u) {
+        enqueue_mstage<T, S>(P, psi, psi, false, s, pk);
+        enqueue_mstage<T, S>(P, psi, psi, true, s, none);
+        for (auto& r : P->n_ranges)
+            timed(P, DSBT_STAGE_SINCOS, s, [&] {
+                if (u + 1 < nsteps)
+                    hip_check(dsbt::launch_fstage_inv_fwd<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r),
+                                                                std::get<2>(r), psi, pv_of(u), pv_of(u + 1), s),
+                              "fstage");
+                else
+                    hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r),
+                                                       std::get<2>(r), psi, psi, true, pv_of(u), s), "fstage");
+            });
     }
 }
 

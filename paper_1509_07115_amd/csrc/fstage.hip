@@ -308,12 +308,19 @@ template <typename V, typename W> __device__ __forceinline__ V to_prec(W w) {
     return {(decltype(V{}.x))w.x, (decltype(V{}.x))w.y};
 }
 
-// T: arithmetic and table precision; S: data precision in memory.
-template <typename T, typename S, int N, bool INV>
+// T: arithmetic and table precision; S: data precision in memory.  MODE 0:
+// forward F (phases ph on the input); 1: inverse F^T (phases ph on the
+// output); 2: F^T then F on the same channels (one step's inverse, then the
+// next step's forward), the two steps' phases ph and ph2 applied in LDS
+// between them -- exactly the products the two separate launches make, with
+// one pass over the data instead of two.
+template <typename T, typename S, int N, int MODE>
 __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
-                                                const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph) {
+                                                const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
+                                                PhaseArgs ph2) {
     using V = typename CV<T>::t;
     using SV = typename CV<S>::t;
+    using P2 = typename Pair<S>::t;
     constexpr int TPC = N / 8;              // threads per channel
     constexpr int PADN = N + N / 32;        // padded LDS slots per channel
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -335,14 +342,48 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     const TabPtr<T> postl = as_global(reinterpret_cast<const V*>(c.post_lo));
     // the sign (-1)^ceil(l/2) (an exact product); the orthonormal scales are in the post table
     const T sg = (T)c.sign;
-    if constexpr (!INV) {
+
+    // forward: X_k for k = 2m, 2m + 1 from the FFT in buf, stored as one
+    // 16-byte pair (reversed for the sine form)
+    auto forward_out = [&]() {
+        if (!live) return;
+        SV* y = dst + c.off;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = t + u * TPC;
+            SV o[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 2 * m + e;
+                // c w^k with the orthonormal scale c folded into the table
+                const Unit<V> w = unit_at(post, postl, k);
+                const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
+                // w a + conj(w) b = (w.x (a.x + b.x) + w.y (b.y - a.y), w.x (a.y + b.y) + w.y (a.x - b.x))
+                const T sx = a.x + b.x, dy = b.y - a.y, sy = a.y + b.y, dx = a.x - b.x;
+                V X;
+                if constexpr (sizeof(T) == sizeof(float)) {
+                    X = {__builtin_fmaf(w.h.x, sx, __builtin_fmaf(w.h.y, dy, w.l.x * sx + w.l.y * dy)),
+                         __builtin_fmaf(w.h.x, sy, __builtin_fmaf(w.h.y, dx, w.l.x * sy + w.l.y * dx))};
+                } else {
+                    X = {w.h.x * sx + w.h.y * dy, w.h.x * sy + w.h.y * dx};
+                }
+                o[e] = to_prec<SV>(f_scale(X, sg));
+            }
+            if (c.p)
+                *reinterpret_cast<P2*>(y + (N - 2 - 2 * m)) = P2{o[1].x, o[1].y, o[0].x, o[0].y};
+            else
+                *reinterpret_cast<P2*>(y + 2 * m) = P2{o[0].x, o[0].y, o[1].x, o[1].y};
+        }
+    };
+
+    if constexpr (MODE == 0) {
         if (live) {
             // pairs x_{2j}, x_{2j+1} (one 16-byte load) go to v_j and v_{N-1-j}
             const SV* x = src + c.off;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j = t + u * TPC;
-                const typename Pair<S>::t w = *reinterpret_cast<const typename Pair<S>::t*>(x + 2 * j);
+                const P2 w = *reinterpret_cast<const P2*>(x + 2 * j);
                 V a = to_prec<V>(SV{w[0], w[1]}), b = to_prec<V>(SV{w[2], w[3]});
                 if (ph.use) {
                     a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
@@ -355,37 +396,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         }
         lds_barrier();
         fft_n<T, N>(buf, qt, t);
-        if (live) {
-            // X_k for k = 2m, 2m + 1, stored as one 16-byte pair (reversed for the sine form)
-            SV* y = dst + c.off;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int m = t + u * TPC;
-                SV o[2];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int k = 2 * m + e;
-                    // c w^k with the orthonormal scale c folded into the table
-                    const Unit<V> w = unit_at(post, postl, k);
-                    const V a = buf[pidx(k)], b = buf[pidx((N - k) & (N - 1))];
-                    // w a + conj(w) b = (w.x (a.x + b.x) + w.y (b.y - a.y), w.x (a.y + b.y) + w.y (a.x - b.x))
-                    const T sx = a.x + b.x, dy = b.y - a.y, sy = a.y + b.y, dx = a.x - b.x;
-                    V X;
-                    if constexpr (sizeof(T) == sizeof(float)) {
-                        X = {__builtin_fmaf(w.h.x, sx, __builtin_fmaf(w.h.y, dy, w.l.x * sx + w.l.y * dy)),
-                             __builtin_fmaf(w.h.x, sy, __builtin_fmaf(w.h.y, dx, w.l.x * sy + w.l.y * dx))};
-                    } else {
-                        X = {w.h.x * sx + w.h.y * dy, w.h.x * sy + w.h.y * dx};
-                    }
-                    o[e] = to_prec<SV>(f_scale(X, sg));
-                }
-                if (c.p)
-                    *reinterpret_cast<typename Pair<S>::t*>(y + (N - 2 - 2 * m)) =
-                        typename Pair<S>::t{o[1].x, o[1].y, o[0].x, o[0].y};
-                else
-                    *reinterpret_cast<typename Pair<S>::t*>(y + 2 * m) = typename Pair<S>::t{o[0].x, o[0].y, o[1].x, o[1].y};
-            }
-        }
+        forward_out();
     } else {
         if (live) {
             // slots j = 2m, 2m + 1 loaded as one 16-byte pair
@@ -393,7 +404,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int m = t + u * TPC;
-                const typename Pair<S>::t v = *reinterpret_cast<const typename Pair<S>::t*>(f + 2 * m);
+                const P2 v = *reinterpret_cast<const P2*>(f + 2 * m);
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int j = 2 * m + e;
@@ -424,21 +435,50 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
         for (int u = 0; u < 8; ++u) buf[pidx(t + u * TPC)] = u8[u];
         lds_barrier();
         fft_n<T, N>(buf, qt, t);
-        if (live) {
-            // v_j and v_{N-1-j} go out as the pair x_{2j}, x_{2j+1} (one 16-byte store)
-            SV* x = dst + c.off;
+        if constexpr (MODE == 1) {
+            if (live) {
+                // v_j and v_{N-1-j} go out as the pair x_{2j}, x_{2j+1} (one 16-byte store)
+                SV* x = dst + c.off;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = t + u * TPC;
-                V a = buf[pidx(j)], b = buf[pidx(N - 1 - j)];
-                if (c.p) b = {-b.x, -b.y};
-                if (ph.use) {
-                    a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
-                    b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                for (int u = 0; u < 4; ++u) {
+                    const int j = t + u * TPC;
+                    V a = buf[pidx(j)], b = buf[pidx(N - 1 - j)];
+                    if (c.p) b = {-b.x, -b.y};
+                    if (ph.use) {
+                        a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
+                        b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                    }
+                    const SV sa = to_prec<SV>(a), sb = to_prec<SV>(b);
+                    *reinterpret_cast<P2*>(x + 2 * j) = P2{sa.x, sa.y, sb.x, sb.y};
                 }
-                const SV sa = to_prec<SV>(a), sb = to_prec<SV>(b);
-                *reinterpret_cast<typename Pair<S>::t*>(x + 2 * j) = typename Pair<S>::t{sa.x, sa.y, sb.x, sb.y};
             }
+        } else {
+            // x_{2j} = v_j and x_{2j+1} = (-1)^p v_{N-1-j} take both steps' phases
+            // and go back to slots j and N-1-j, where the forward transform reads
+            // them (the two sign changes cancel); the data precision is kept
+            // between the steps, as the separate launches do
+            if (live) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = t + u * TPC;
+                    V a = buf[pidx(j)], b = buf[pidx(N - 1 - j)];
+                    if (ph.use) {
+                        a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
+                        b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
+                    }
+                    a = to_prec<V>(to_prec<SV>(a));
+                    b = to_prec<V>(to_prec<SV>(b));
+                    if (ph2.use) {
+                        a = u_mul(a, phase_factor<V>(c, 2 * j, ph2));
+                        b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph2));
+                    }
+                    buf[pidx(j)] = a;
+                    buf[pidx(N - 1 - j)] = b;
+                }
+            }
+            lds_barrier();
+            fft_n<T, N>(buf, qt, t);
+            forward_out();
         }
     }
 }
@@ -450,18 +490,18 @@ static inline void fstage_shape(int N, int& cpb, int& threads) {
     threads = tpc * cpb;
 }
 
-template <typename T, typename S, bool INV>
-static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void* dst, PhaseArgs ph, hipStream_t s) {
-    using V = typename CV<T>::t;
+template <typename T, typename S, int MODE>
+static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void* dst, PhaseArgs ph, PhaseArgs ph2,
+                           hipStream_t s) {
     using SV = typename CV<S>::t;
     int cpb, threads;
     fstage_shape(N, cpb, threads);
     const int blocks = (nch + cpb - 1) / cpb;
     const size_t lds = fstage_lds_bytes<T>(N, cpb);
-#define DSBT_FN(NN)                                                                                     \
-    case NN:                                                                                            \
-        hipLaunchKernelGGL((fstage_n<T, S, NN, INV>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb, \
-                           (const SV*)src, (SV*)dst, ph);                                               \
+#define DSBT_FN(NN)                                                                                      \
+    case NN:                                                                                             \
+        hipLaunchKernelGGL((fstage_n<T, S, NN, MODE>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb, \
+                           (const SV*)src, (SV*)dst, ph, ph2);                                           \
         break;
     switch (N) {
         DSBT_FN(16) DSBT_FN(32) DSBT_FN(64) DSBT_FN(128) DSBT_FN(256) DSBT_FN(512) DSBT_FN(1024)
@@ -476,13 +516,19 @@ template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s) {
     if (nch <= 0) return hipSuccess;
-    return inverse ? launch_n<T, S, true>(N, d_chans, nch, src, dst, ph, s)
-                   : launch_n<T, S, false>(N, d_chans, nch, src, dst, ph, s);
+    return inverse ? launch_n<T, S, 1>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, s)
+                   : launch_n<T, S, 0>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, s);
 }
 
-template <typename T, typename S, bool INV>
+template <typename T, typename S>
+hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, PhaseArgs ph_inv,
+                                 PhaseArgs ph_fwd, hipStream_t s) {
+    if (nch <= 0) return hipSuccess;
+    return launch_n<T, S, 2>(N, d_chans, nch, data, data, ph_inv, ph_fwd, s);
+}
+
+template <typename T, typename S, int MODE>
 static hipError_t lds_attr_all() {
-    using V = typename CV<T>::t;
     hipError_t e = hipSuccess;
     auto set = [&](const void* f, int N) {
         int cpb, threads;
@@ -490,26 +536,29 @@ static hipError_t lds_attr_all() {
         const size_t lds = fstage_lds_bytes<T>(N, cpb);
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    set((const void*)fstage_n<T, S, 16, INV>, 16);
-    set((const void*)fstage_n<T, S, 32, INV>, 32);
-    set((const void*)fstage_n<T, S, 64, INV>, 64);
-    set((const void*)fstage_n<T, S, 128, INV>, 128);
-    set((const void*)fstage_n<T, S, 256, INV>, 256);
-    set((const void*)fstage_n<T, S, 512, INV>, 512);
-    set((const void*)fstage_n<T, S, 1024, INV>, 1024);
-    set((const void*)fstage_n<T, S, 2048, INV>, 2048);
-    set((const void*)fstage_n<T, S, 4096, INV>, 4096);
-    set((const void*)fstage_n<T, S, 8192, INV>, 8192);
+    set((const void*)fstage_n<T, S, 16, MODE>, 16);
+    set((const void*)fstage_n<T, S, 32, MODE>, 32);
+    set((const void*)fstage_n<T, S, 64, MODE>, 64);
+    set((const void*)fstage_n<T, S, 128, MODE>, 128);
+    set((const void*)fstage_n<T, S, 256, MODE>, 256);
+    set((const void*)fstage_n<T, S, 512, MODE>, 512);
+    set((const void*)fstage_n<T, S, 1024, MODE>, 1024);
+    set((const void*)fstage_n<T, S, 2048, MODE>, 2048);
+    set((const void*)fstage_n<T, S, 4096, MODE>, 4096);
+    set((const void*)fstage_n<T, S, 8192, MODE>, 8192);
     return e;
 }
 
 template <typename T>
 hipError_t set_lds_limits_fstage_n() {
-    hipError_t e = lds_attr_all<T, T, false>();
-    if (e == hipSuccess) e = lds_attr_all<T, T, true>();
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = lds_attr_all<T, T, 0>();
+    if (e == hipSuccess) e = lds_attr_all<T, T, 1>();
+    if (e == hipSuccess) e = lds_attr_all<T, T, 2>();
     if constexpr (sizeof(T) == sizeof(double)) {
-        if (e == hipSuccess) e = lds_attr_all<double, float, false>();
-        if (e == hipSuccess) e = lds_attr_all<double, float, true>();
+        if (e == hipSuccess) e = lds_attr_all<double, float, 0>();
+        if (e == hipSuccess) e = lds_attr_all<double, float, 1>();
+        if (e == hipSuccess) e = lds_attr_all<double, float, 2>();
     }
     return e;
 }
@@ -520,6 +569,12 @@ template hipError_t launch_fstage_n<double, double>(int, const FChan*, int, cons
                                                     hipStream_t);
 template hipError_t launch_fstage_n<double, float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs,
                                                    hipStream_t);
+template hipError_t launch_fstage_inv_fwd<float, float>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+                                                         hipStream_t);
+template hipError_t launch_fstage_inv_fwd<double, double>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+                                                           hipStream_t);
+template hipError_t launch_fstage_inv_fwd<double, float>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+                                                          hipStream_t);
 template hipError_t set_lds_limits_fstage_n<float>();
 template hipError_t set_lds_limits_fstage_n<double>();
 

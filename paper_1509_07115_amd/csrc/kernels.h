@@ -119,6 +119,12 @@ __device__ __forceinline__ float2 mul_unit(float2 z, float2 h, float2 l) {
 template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s);
+// One step's inverse stage followed by the next step's forward stage, in place
+// on the channels' data (one launch, one pass over the data): F^T with the
+// phases ph_inv on its output, then F with ph_fwd on its input.
+template <typename T, typename S>
+hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, PhaseArgs ph_inv,
+                                 PhaseArgs ph_fwd, hipStream_t s);
 template <typename T>
 hipError_t set_lds_limits_fstage_n();
 

@@ -120,6 +120,27 @@ def test_plain_and_batched_agree_bitwise():
     assert torch.equal(a, b)
 
 
+def test_fused_step_stages_agree_bitwise_with_separate_launches():
+    # batched split steps run one step's inverse sine/cosine stage and the next
+    # step's forward one as one launch; the plain form launches them
+    # separately: the products are the same, so the results agree bitwise
+    # (strengths per step, forward and adjoint order)
+    w = workloads.batched_all_m(seed=9, N=512, rmax=25.0, ells=[0, 1, 6, 13])
+    V = np.concatenate([-1.0 / np.sqrt(workloads.grid(N, rmax) ** 2 + 0.1) for N, _, rmax, _ in w.channels])
+    pb, pp = Plan(w.channels), Plan(w.channels, mode="plain")
+    for p in (pb, pp):
+        p.set_potential(V, 0.01)
+    x = to_dev(w.psi, torch.complex64)
+    a, b = x.clone(), x.clone()
+    s = torch.tensor([1.0, 0.97, 1.03, 1.1], dtype=torch.float32, device="cuda")
+    pb.kinetic_step(a, 4, s)
+    pp.kinetic_step(b, 4, s)
+    pb.kinetic_step(a, 3, s, adjoint=True)
+    pp.kinetic_step(b, 3, s, adjoint=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_in_place_and_offsets_with_gaps():
     rng = np.random.default_rng(3)
     chans = [(128, 5, 12.0, 7), (256, 12, 30.0, 400), (128, 0, 5.0, 1000)]
