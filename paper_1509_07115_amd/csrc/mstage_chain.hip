@@ -305,10 +305,14 @@ struct Pipe {
     template <int S>
     __device__ void pre_step(Pre& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
-        pre_load_tab<(S + kPD) % kSets>(r, t + kPD);
         pre_load_dat<(S + kPD + 1) % kSets>(r, t + kPD + 1);
         if constexpr (S % kPhase > 0) pre_readout<S % kPhase - 1>(r, t - 1);
         pre_mfma<S>(r);
+        // the table set refilled here was read by the matrix instructions of
+        // tile t - 1; loading it only after tile t's instructions are issued
+        // keeps the loads from waiting for those reads
+        __builtin_amdgcn_sched_barrier(0);
+        pre_load_tab<(S + kPD) % kSets>(r, t + kPD);
         pre_stage<(S + 1) % kSets>(r, t + 1);
     }
     // steps of one phase (tiles t0 .. t0 + kPhase - 1, register sets I0 ..)
@@ -383,7 +387,6 @@ struct Pipe {
             if (t >= NT) return;   // bm must keep mu_NT
         }
         __builtin_amdgcn_sched_barrier(0);
-        chain_load<(S + kPD) % kSets>(r, t + kPD);
         V4 c0[NCB], c1[NCB], m2[NCB], m3[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -403,6 +406,8 @@ struct Pipe {
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) m3[cb] = c0[cb] + c1[cb];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        chain_load<(S + kPD) % kSets>(r, t + kPD);   // after tile t's matrix instructions (see pre_step)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             result_to_operand(m2[cb], r.bm + 4 * KB * cb);
@@ -561,12 +566,13 @@ struct Pipe {
                 out_epilogue<RB, (S + 1) & 1>(r, t - 1);
             }
         }
-        out_load<RB, (S + kPD) % kSets>(r, t + kPD);
         constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI, P = S & 1;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) r.c0[P][cb] = r.c1[P][cb] = zero4();
         mac<LO, HI, 8>(r.c0[P], r.c1[P], r.a[S], r.x[S % kPhase] + LO);
         mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
+        __builtin_amdgcn_sched_barrier(0);
+        out_load<RB, (S + kPD) % kSets>(r, t + kPD);   // after tile t's matrix instructions (see pre_step)
         if constexpr (KPH) {
             r.wq[P] = r.w[S];
             if constexpr (sizeof(T) == sizeof(float)) r.wql[P] = r.wl[S];
