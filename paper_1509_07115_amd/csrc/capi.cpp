@@ -162,6 +162,11 @@ struct dsbt_plan_s {
     dsbt::FChan* d_fchans_n = nullptr;   // sorted by N, for one launch per N
     std::vector<int> order_n;            // channel index of each entry of d_fchans_n
     std::vector<std::tuple<int, int, int>> n_ranges;  // (N, first, count) in d_fchans_n
+    // plans with several N: the sine/cosine stage as one launch over tasks of
+    // one N each (largest N first), and the dynamic LDS it needs
+    dsbt::FTask* d_ftasks = nullptr;
+    int n_ftasks = 0;
+    size_t ftask_lds = 0;
     // moment-stage work items: matrix-core kernel (FP32, R16 <= 128) and the
     // generic kernel (FP64 plans, larger blocks); per-channel items for the
     // plain form
@@ -585,6 +590,19 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
     }
     P->d_fchans_n = (dsbt::FChan*)P->dalloc(sizeof(dsbt::FChan) * nch);
     upload_fchans_n(P);
+    if (P->n_ranges.size() > 1 && P->opts.mode == DSBT_MODE_BATCHED) {
+        std::vector<dsbt::FTask> tasks;
+        for (auto& r : P->n_ranges) {
+            const int N = std::get<0>(r), per = dsbt::kMultiThreads / (N / 8);
+            for (int i = 0; i < std::get<2>(r); i += per)
+                tasks.push_back({N, std::get<1>(r) + i, std::min(per, std::get<2>(r) - i)});
+            P->ftask_lds = std::max(P->ftask_lds, dsbt::fstage_multi_lds<T>(N));
+        }
+        P->d_ftasks = (dsbt::FTask*)P->dalloc(sizeof(dsbt::FTask) * tasks.size());
+        hip_check(hipMemcpy(P->d_ftasks, tasks.data(), sizeof(dsbt::FTask) * tasks.size(), hipMemcpyHostToDevice),
+                  "tasks");
+        P->n_ftasks = (int)tasks.size();
+    }
     // moment items
     const int cpb = P->opts.chans_per_block;
     bool any_nb8 = false;
@@ -807,6 +825,30 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
     });
 }
 
+// The batched sine/cosine stage: mode 0 forward, 1 inverse, 2 inverse then
+// forward (in place; ph on the inverse, ph2 on the forward).  One launch per
+// distinct N, or one launch over all N (plans with several N).
+template <typename T, typename S>
+void enqueue_fstage(dsbt_plan_s* P, const void* src, void* dst, int mode, dsbt::PhaseArgs ph, dsbt::PhaseArgs ph2,
+                    hipStream_t s) {
+    if (P->d_ftasks) {
+        timed(P, DSBT_STAGE_SINCOS, s, [&] {
+            hip_check(dsbt::launch_fstage_multi<T, S>(P->d_ftasks, P->n_ftasks, P->d_fchans_n, src, dst, mode, ph, ph2,
+                                                      P->ftask_lds, s), "fstage");
+        });
+        return;
+    }
+    for (auto& r : P->n_ranges)
+        timed(P, DSBT_STAGE_SINCOS, s, [&] {
+            const int N = std::get<0>(r), first = std::get<1>(r), count = std::get<2>(r);
+            if (mode == 2)
+                hip_check(dsbt::launch_fstage_inv_fwd<T, S>(N, P->d_fchans_n + first, count, dst, ph, ph2, s), "fstage");
+            else
+                hip_check(dsbt::launch_fstage_n<T, S>(N, P->d_fchans_n + first, count, src, dst, mode == 1, ph, s),
+                          "fstage");
+        });
+}
+
 template <typename T, typename S>
 void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv,
                      dsbt::PhaseArgs pk) {
@@ -820,11 +862,7 @@ void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
         }
         return;
     }
-    for (auto& r : P->n_ranges)
-        timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), src,
-                                               dst, false, pv, s), "fstage");
-        });
+    enqueue_fstage<T, S>(P, src, dst, 0, pv, dsbt::PhaseArgs{}, s);
     enqueue_mstage<T, S>(P, dst, dst, false, s, pk);
 }
 
@@ -842,11 +880,7 @@ void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
         return;
     }
     enqueue_mstage<T, S>(P, src, dst, true, s, none);
-    for (auto& r : P->n_ranges)
-        timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), dst,
-                                               dst, true, pv, s), "fstage");
-        });
+    enqueue_fstage<T, S>(P, dst, dst, 1, pv, dsbt::PhaseArgs{}, s);
 }
 
 // nsteps split steps in place.  Batched plans run one step's inverse sine /
@@ -867,24 +901,14 @@ void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool 
         }
         return;
     }
-    for (auto& r : P->n_ranges)
-        timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r), std::get<2>(r), psi,
-                                               psi, false, pv_of(0), s), "fstage");
-        });
+    enqueue_fstage<T, S>(P, psi, psi, 0, pv_of(0), none, s);
     for (int u = 0; u < nsteps; ++u) {
         enqueue_mstage<T, S>(P, psi, psi, false, s, pk);
         enqueue_mstage<T, S>(P, psi, psi, true, s, none);
-        for (auto& r : P->n_ranges)
-            timed(P, DSBT_STAGE_SINCOS, s, [&] {
-                if (u + 1 < nsteps)
-                    hip_check(dsbt::launch_fstage_inv_fwd<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r),
-                                                                std::get<2>(r), psi, pv_of(u), pv_of(u + 1), s),
-                              "fstage");
-                else
-                    hip_check(dsbt::launch_fstage_n<T, S>(std::get<0>(r), P->d_fchans_n + std::get<1>(r),
-                                                       std::get<2>(r), psi, psi, true, pv_of(u), s), "fstage");
-            });
+        if (u + 1 < nsteps)
+            enqueue_fstage<T, S>(P, psi, psi, 2, pv_of(u), pv_of(u + 1), s);
+        else
+            enqueue_fstage<T, S>(P, psi, psi, 1, pv_of(u), none, s);
     }
 }
 

@@ -23,6 +23,8 @@
 // compensated.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace dsbt {
 
 template <typename T> struct CV;
@@ -314,10 +316,12 @@ template <typename V, typename W> __device__ __forceinline__ V to_prec(W w) {
 // next step's forward), the two steps' phases ph and ph2 applied in LDS
 // between them -- exactly the products the two separate launches make, with
 // one pass over the data instead of two.
+// The work of one block: channel group `group` (cpb channels of N/8 threads
+// each) of the nch channels at chans.
 template <typename T, typename S, int N, int MODE>
-__global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
-                                                const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
-                                                PhaseArgs ph2) {
+__device__ __forceinline__ void fstage_body(const FChan* __restrict__ chans, int nch, int cpb, int group,
+                                            const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
+                                            PhaseArgs ph2) {
     using V = typename CV<T>::t;
     using SV = typename CV<S>::t;
     using P2 = typename Pair<S>::t;
@@ -325,7 +329,7 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     constexpr int PADN = N + N / 32;        // padded LDS slots per channel
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int cl = threadIdx.x / TPC, t = threadIdx.x % TPC;
-    const int cidx = blockIdx.x * cpb + cl;
+    const int cidx = group * cpb + cl;
     V* buf = reinterpret_cast<V*>(smem_raw) + cl * PADN;
     // a block's last slots may be past the channel list: they take part in the
     // barriers on a copy of the last descriptor (valid tables) and store nothing
@@ -483,6 +487,37 @@ __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __res
     }
 }
 
+template <typename T, typename S, int N, int MODE>
+__global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
+                                                const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
+                                                PhaseArgs ph2) {
+    fstage_body<T, S, N, MODE>(chans, nch, cpb, blockIdx.x, src, dst, ph, ph2);
+}
+
+// Every N of a plan in one launch: block b takes task b, a group of channels
+// of one N with kMultiThreads / (N/8) channels (8192 points for N >= 16),
+// and runs that N's body.  The plan lists the tasks largest N first, so the
+// hardware dispatcher, which hands out blocks in index order as compute
+// units free up, schedules the heaviest tasks first.
+template <typename T, typename S, int MODE>
+__global__ void __launch_bounds__(kMultiThreads) fstage_multi(const FTask* __restrict__ tasks,
+                                                           const FChan* __restrict__ chans,
+                                                           const typename CV<S>::t* src, typename CV<S>::t* dst,
+                                                           PhaseArgs ph, PhaseArgs ph2) {
+    const FTask task = tasks[blockIdx.x];
+    const FChan* c = chans + task.first;
+#define DSBT_MB(NN)                                                                                      \
+    case NN:                                                                                             \
+        fstage_body<T, S, NN, MODE>(c, task.count, kMultiThreads / (NN / 8), 0, src, dst, ph, ph2);    \
+        break;
+    switch (task.N) {
+        DSBT_MB(16) DSBT_MB(32) DSBT_MB(64) DSBT_MB(128) DSBT_MB(256) DSBT_MB(512) DSBT_MB(1024)
+        DSBT_MB(2048) DSBT_MB(4096) DSBT_MB(8192)
+        default: break;
+    }
+#undef DSBT_MB
+}
+
 // Threads per block for size N and channels per block.
 static inline void fstage_shape(int N, int& cpb, int& threads) {
     const int tpc = N / 8;
@@ -527,6 +562,26 @@ hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* dat
     return launch_n<T, S, 2>(N, d_chans, nch, data, data, ph_inv, ph_fwd, s);
 }
 
+template <typename T>
+size_t fstage_multi_lds(int N) {
+    return fstage_lds_bytes<T>(N, kMultiThreads / (N / 8));
+}
+
+template <typename T, typename S>
+hipError_t launch_fstage_multi(const FTask* d_tasks, int ntasks, const FChan* d_chans, const void* src, void* dst,
+                               int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s) {
+    using SV = typename CV<S>::t;
+    if (ntasks <= 0) return hipSuccess;
+    const dim3 grid(ntasks), block(kMultiThreads);
+    if (mode == 0)
+        hipLaunchKernelGGL((fstage_multi<T, S, 0>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+    else if (mode == 1)
+        hipLaunchKernelGGL((fstage_multi<T, S, 1>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+    else
+        hipLaunchKernelGGL((fstage_multi<T, S, 2>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+    return hipGetLastError();
+}
+
 template <typename T, typename S, int MODE>
 static hipError_t lds_attr_all() {
     hipError_t e = hipSuccess;
@@ -552,6 +607,19 @@ static hipError_t lds_attr_all() {
 template <typename T>
 hipError_t set_lds_limits_fstage_n() {
     hipError_t e = hipSuccess;
+    auto multi = [&](const void* f) {
+        size_t most = 0;
+        for (int N = 16; N <= 8192; N *= 2) most = std::max(most, fstage_multi_lds<T>(N));
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
+    };
+    multi((const void*)fstage_multi<T, T, 0>);
+    multi((const void*)fstage_multi<T, T, 1>);
+    multi((const void*)fstage_multi<T, T, 2>);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        multi((const void*)fstage_multi<double, float, 0>);
+        multi((const void*)fstage_multi<double, float, 1>);
+        multi((const void*)fstage_multi<double, float, 2>);
+    }
     if (e == hipSuccess) e = lds_attr_all<T, T, 0>();
     if (e == hipSuccess) e = lds_attr_all<T, T, 1>();
     if (e == hipSuccess) e = lds_attr_all<T, T, 2>();
@@ -575,6 +643,14 @@ template hipError_t launch_fstage_inv_fwd<double, double>(int, const FChan*, int
                                                            hipStream_t);
 template hipError_t launch_fstage_inv_fwd<double, float>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
                                                           hipStream_t);
+template size_t fstage_multi_lds<float>(int);
+template size_t fstage_multi_lds<double>(int);
+template hipError_t launch_fstage_multi<float, float>(const FTask*, int, const FChan*, const void*, void*, int,
+                                                      PhaseArgs, PhaseArgs, size_t, hipStream_t);
+template hipError_t launch_fstage_multi<double, double>(const FTask*, int, const FChan*, const void*, void*, int,
+                                                        PhaseArgs, PhaseArgs, size_t, hipStream_t);
+template hipError_t launch_fstage_multi<double, float>(const FTask*, int, const FChan*, const void*, void*, int,
+                                                       PhaseArgs, PhaseArgs, size_t, hipStream_t);
 template hipError_t set_lds_limits_fstage_n<float>();
 template hipError_t set_lds_limits_fstage_n<double>();
 

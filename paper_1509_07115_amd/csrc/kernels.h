@@ -119,6 +119,22 @@ __device__ __forceinline__ float2 mul_unit(float2 z, float2 h, float2 l) {
 template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s);
+// The sine/cosine stage over channels of every N in one launch: task b is
+// `count` channels of size N starting at entry `first` of the channel list
+// (count <= kMultiThreads / (N/8): one block of kMultiThreads threads, N/8
+// per channel).  mode: 0 forward, 1 inverse, 2 inverse then forward (as
+// launch_fstage_inv_fwd, data in place).  lds: fstage_multi_lds maximised
+// over the tasks' N.
+constexpr int kMultiThreads = 1024;
+struct FTask {
+    int N, first, count;
+};
+template <typename T>
+size_t fstage_multi_lds(int N);
+template <typename T, typename S>
+hipError_t launch_fstage_multi(const FTask* d_tasks, int ntasks, const FChan* d_chans, const void* src, void* dst,
+                               int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s);
+
 // One step's inverse stage followed by the next step's forward stage, in place
 // on the channels' data (one launch, one pass over the data): F^T with the
 // phases ph_inv on its output, then F with ph_fwd on its input.
