@@ -826,15 +826,16 @@ void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool 
 }
 
 // The batched sine/cosine stage: mode 0 forward, 1 inverse, 2 inverse then
-// forward (in place; ph on the inverse, ph2 on the forward).  One launch per
-// distinct N, or one launch over all N (plans with several N).
+// forward (in place; ph on the inverse, ph2 on the forward; mid, if not null,
+// also receives the state between the two).  One launch per distinct N, or
+// one launch over all N (plans with several N).
 template <typename T, typename S>
 void enqueue_fstage(dsbt_plan_s* P, const void* src, void* dst, int mode, dsbt::PhaseArgs ph, dsbt::PhaseArgs ph2,
-                    hipStream_t s) {
+                    hipStream_t s, void* mid = nullptr) {
     if (P->d_ftasks) {
         timed(P, DSBT_STAGE_SINCOS, s, [&] {
-            hip_check(dsbt::launch_fstage_multi<T, S>(P->d_ftasks, P->n_ftasks, P->d_fchans_n, src, dst, mode, ph, ph2,
-                                                      P->ftask_lds, s), "fstage");
+            hip_check(dsbt::launch_fstage_multi<T, S>(P->d_ftasks, P->n_ftasks, P->d_fchans_n, src, dst, mid, mode, ph,
+                                                      ph2, P->ftask_lds, s), "fstage");
         });
         return;
     }
@@ -842,7 +843,8 @@ void enqueue_fstage(dsbt_plan_s* P, const void* src, void* dst, int mode, dsbt::
         timed(P, DSBT_STAGE_SINCOS, s, [&] {
             const int N = std::get<0>(r), first = std::get<1>(r), count = std::get<2>(r);
             if (mode == 2)
-                hip_check(dsbt::launch_fstage_inv_fwd<T, S>(N, P->d_fchans_n + first, count, dst, ph, ph2, s), "fstage");
+                hip_check(dsbt::launch_fstage_inv_fwd<T, S>(N, P->d_fchans_n + first, count, dst, mid, ph, ph2, s),
+                          "fstage");
             else
                 hip_check(dsbt::launch_fstage_n<T, S>(N, P->d_fchans_n + first, count, src, dst, mode == 1, ph, s),
                           "fstage");
@@ -938,25 +940,65 @@ void capture_graph(F&& enqueue, hipGraph_t* graph, hipGraphExec_t* exec) {
 // One checkpoint segment of the adjoint method on the plan's segment buffers
 // (dsbt_adjoint_segment): states 1..n from state 0, then the n adjoint steps
 // and strength gradients, lam_{t+1} -> lam_t alternating between the two
-// adjoint buffers (lam_a ends in buffer n mod 2).
+// adjoint buffers (lam_a ends in buffer n mod 2).  Batched plans carry each
+// pass in the work buffer (the third adjoint buffer) with the fused inverse +
+// forward stage, which also stores the state between two steps where the
+// gradients read it: three launches a step instead of four, bitwise the same
+// results.
 template <typename T, typename S>
 void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
     const size_t sb = (size_t)P->elems * P->elem_bytes;
     auto state = [&](int t) { return static_cast<unsigned char*>(P->seg_states) + sb * (size_t)t; };
-    unsigned char* lam[2] = {static_cast<unsigned char*>(P->seg_lam), static_cast<unsigned char*>(P->seg_lam) + sb};
+    unsigned char* lam[3] = {static_cast<unsigned char*>(P->seg_lam), static_cast<unsigned char*>(P->seg_lam) + sb,
+                             static_cast<unsigned char*>(P->seg_lam) + 2 * sb};
     const int nch = (int)P->ch.size();
-    for (int t = 0; t < n; ++t) {
-        const dsbt::PhaseArgs pv{1, 0, P->seg_s, t}, pk{1, 0, nullptr, 0};
-        enqueue_forward<T, S>(P, state(t), state(t + 1), q, pv, pk);
-        enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv);
-    }
-    int cur = 0;   // lam[cur] holds lam_{t+1}
-    for (int t = n - 1; t >= 0; --t) {
-        const dsbt::PhaseArgs pv{1, 1, P->seg_s, t}, pk{1, 1, nullptr, 0};
-        enqueue_forward<T, S>(P, lam[cur], lam[cur ^ 1], q, pv, pk);
-        enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv);
+    auto grad = [&](int t, int cur) {
         hip_check(dsbt::launch_grad_s<S>(P->d_fchans, nch, state(t), state(t + 1), lam[cur ^ 1], lam[cur],
                                          P->d_scratch, P->seg_gs + t, q), "grad_s");
+    };
+    if (P->opts.mode == DSBT_MODE_PLAIN) {
+        for (int t = 0; t < n; ++t) {
+            const dsbt::PhaseArgs pv{1, 0, P->seg_s, t}, pk{1, 0, nullptr, 0};
+            enqueue_forward<T, S>(P, state(t), state(t + 1), q, pv, pk);
+            enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv);
+        }
+        int cur = 0;   // lam[cur] holds lam_{t+1}
+        for (int t = n - 1; t >= 0; --t) {
+            const dsbt::PhaseArgs pv{1, 1, P->seg_s, t}, pk{1, 1, nullptr, 0};
+            enqueue_forward<T, S>(P, lam[cur], lam[cur ^ 1], q, pv, pk);
+            enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv);
+            grad(t, cur);
+            cur ^= 1;
+        }
+        return;
+    }
+    void* w = lam[2];
+    const dsbt::PhaseArgs none{};
+    {
+        const dsbt::PhaseArgs pk{1, 0, nullptr, 0};
+        auto pv = [&](int t) { return dsbt::PhaseArgs{1, 0, P->seg_s, t}; };
+        enqueue_fstage<T, S>(P, state(0), w, 0, pv(0), none, q);
+        for (int t = 0; t < n; ++t) {
+            enqueue_mstage<T, S>(P, w, w, false, q, pk);
+            enqueue_mstage<T, S>(P, w, w, true, q, none);
+            if (t + 1 < n)
+                enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t + 1), q, state(t + 1));
+            else
+                enqueue_fstage<T, S>(P, w, state(n), 1, pv(t), none, q);
+        }
+    }
+    const dsbt::PhaseArgs pk{1, 1, nullptr, 0};
+    auto pv = [&](int t) { return dsbt::PhaseArgs{1, 1, P->seg_s, t}; };
+    enqueue_fstage<T, S>(P, lam[0], w, 0, pv(n - 1), none, q);
+    int cur = 0;   // lam[cur] holds lam_{t+1}
+    for (int t = n - 1; t >= 0; --t) {
+        enqueue_mstage<T, S>(P, w, w, false, q, pk);
+        enqueue_mstage<T, S>(P, w, w, true, q, none);
+        if (t > 0)
+            enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), q, lam[cur ^ 1]);
+        else
+            enqueue_fstage<T, S>(P, w, lam[cur ^ 1], 1, pv(t), none, q);
+        grad(t, cur);
         cur ^= 1;
     }
 }
@@ -1327,13 +1369,18 @@ dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps,
             p->drop_graphs();
             p->free_segment();
             p->seg_states = p->dalloc_raw(sb * (size_t)(nsteps + 1));
-            p->seg_lam = p->dalloc_raw(2 * sb);
+            p->seg_lam = p->dalloc_raw(3 * sb);
             p->seg_s = static_cast<float*>(p->dalloc_raw(sizeof(float) * (size_t)nsteps));
             p->seg_gs = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps));
             p->seg_cap = nsteps;
         }
         hip_check(hipMemcpyAsync(p->seg_states, psi_a, sb, hipMemcpyDeviceToDevice, st), "segment psi_a");
         hip_check(hipMemcpyAsync(p->seg_lam, lam, sb, hipMemcpyDeviceToDevice, st), "segment lam");
+        // lam_a ends in the second buffer for odd n: its gaps between channels
+        // (never written by the steps) must hold lam's
+        if (nsteps & 1)
+            hip_check(hipMemcpyAsync(static_cast<unsigned char*>(p->seg_lam) + sb, lam, sb, hipMemcpyDeviceToDevice, st),
+                      "segment lam");
         hip_check(hipMemcpyAsync(p->seg_s, s, sizeof(float) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
                   "segment strengths");
         auto enqueue = [&](hipStream_t q) {

@@ -321,7 +321,7 @@ template <typename V, typename W> __device__ __forceinline__ V to_prec(W w) {
 template <typename T, typename S, int N, int MODE>
 __device__ __forceinline__ void fstage_body(const FChan* __restrict__ chans, int nch, int cpb, int group,
                                             const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
-                                            PhaseArgs ph2) {
+                                            PhaseArgs ph2, typename CV<S>::t* mid) {
     using V = typename CV<T>::t;
     using SV = typename CV<S>::t;
     using P2 = typename Pair<S>::t;
@@ -470,8 +470,14 @@ __device__ __forceinline__ void fstage_body(const FChan* __restrict__ chans, int
                         a = u_mul(a, phase_factor<V>(c, 2 * j, ph));
                         b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph));
                     }
-                    a = to_prec<V>(to_prec<SV>(a));
-                    b = to_prec<V>(to_prec<SV>(b));
+                    const SV sa = to_prec<SV>(a), sb = to_prec<SV>(b);
+                    if (mid) {
+                        // the state between the two steps, as mode 1 stores it
+                        const SV sbs = c.p ? SV{-sb.x, -sb.y} : sb;
+                        *reinterpret_cast<P2*>(mid + c.off + 2 * j) = P2{sa.x, sa.y, sbs.x, sbs.y};
+                    }
+                    a = to_prec<V>(sa);
+                    b = to_prec<V>(sb);
                     if (ph2.use) {
                         a = u_mul(a, phase_factor<V>(c, 2 * j, ph2));
                         b = u_mul(b, phase_factor<V>(c, 2 * j + 1, ph2));
@@ -490,8 +496,8 @@ __device__ __forceinline__ void fstage_body(const FChan* __restrict__ chans, int
 template <typename T, typename S, int N, int MODE>
 __global__ void __launch_bounds__(fstage_threads(N)) fstage_n(const FChan* __restrict__ chans, int nch, int cpb,
                                                 const typename CV<S>::t* src, typename CV<S>::t* dst, PhaseArgs ph,
-                                                PhaseArgs ph2) {
-    fstage_body<T, S, N, MODE>(chans, nch, cpb, blockIdx.x, src, dst, ph, ph2);
+                                                PhaseArgs ph2, typename CV<S>::t* mid) {
+    fstage_body<T, S, N, MODE>(chans, nch, cpb, blockIdx.x, src, dst, ph, ph2, mid);
 }
 
 // Every N of a plan in one launch: block b takes task b, a group of channels
@@ -503,12 +509,12 @@ template <typename T, typename S, int MODE>
 __global__ void __launch_bounds__(kMultiThreads) fstage_multi(const FTask* __restrict__ tasks,
                                                            const FChan* __restrict__ chans,
                                                            const typename CV<S>::t* src, typename CV<S>::t* dst,
-                                                           PhaseArgs ph, PhaseArgs ph2) {
+                                                           PhaseArgs ph, PhaseArgs ph2, typename CV<S>::t* mid) {
     const FTask task = tasks[blockIdx.x];
     const FChan* c = chans + task.first;
 #define DSBT_MB(NN)                                                                                      \
     case NN:                                                                                             \
-        fstage_body<T, S, NN, MODE>(c, task.count, kMultiThreads / (NN / 8), 0, src, dst, ph, ph2);    \
+        fstage_body<T, S, NN, MODE>(c, task.count, kMultiThreads / (NN / 8), 0, src, dst, ph, ph2, mid); \
         break;
     switch (task.N) {
         DSBT_MB(16) DSBT_MB(32) DSBT_MB(64) DSBT_MB(128) DSBT_MB(256) DSBT_MB(512) DSBT_MB(1024)
@@ -527,7 +533,7 @@ static inline void fstage_shape(int N, int& cpb, int& threads) {
 
 template <typename T, typename S, int MODE>
 static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void* dst, PhaseArgs ph, PhaseArgs ph2,
-                           hipStream_t s) {
+                           void* mid, hipStream_t s) {
     using SV = typename CV<S>::t;
     int cpb, threads;
     fstage_shape(N, cpb, threads);
@@ -536,7 +542,7 @@ static hipError_t launch_n(int N, const FChan* d, int nch, const void* src, void
 #define DSBT_FN(NN)                                                                                      \
     case NN:                                                                                             \
         hipLaunchKernelGGL((fstage_n<T, S, NN, MODE>), dim3(blocks), dim3(threads), lds, s, d, nch, cpb, \
-                           (const SV*)src, (SV*)dst, ph, ph2);                                           \
+                           (const SV*)src, (SV*)dst, ph, ph2, (SV*)mid);                                 \
         break;
     switch (N) {
         DSBT_FN(16) DSBT_FN(32) DSBT_FN(64) DSBT_FN(128) DSBT_FN(256) DSBT_FN(512) DSBT_FN(1024)
@@ -551,15 +557,15 @@ template <typename T, typename S>
 hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src, void* dst, bool inverse,
                            PhaseArgs ph, hipStream_t s) {
     if (nch <= 0) return hipSuccess;
-    return inverse ? launch_n<T, S, 1>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, s)
-                   : launch_n<T, S, 0>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, s);
+    return inverse ? launch_n<T, S, 1>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, nullptr, s)
+                   : launch_n<T, S, 0>(N, d_chans, nch, src, dst, ph, PhaseArgs{}, nullptr, s);
 }
 
 template <typename T, typename S>
-hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, PhaseArgs ph_inv,
+hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, void* mid, PhaseArgs ph_inv,
                                  PhaseArgs ph_fwd, hipStream_t s) {
     if (nch <= 0) return hipSuccess;
-    return launch_n<T, S, 2>(N, d_chans, nch, data, data, ph_inv, ph_fwd, s);
+    return launch_n<T, S, 2>(N, d_chans, nch, data, data, ph_inv, ph_fwd, mid, s);
 }
 
 template <typename T>
@@ -569,16 +575,19 @@ size_t fstage_multi_lds(int N) {
 
 template <typename T, typename S>
 hipError_t launch_fstage_multi(const FTask* d_tasks, int ntasks, const FChan* d_chans, const void* src, void* dst,
-                               int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s) {
+                               void* mid, int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s) {
     using SV = typename CV<S>::t;
     if (ntasks <= 0) return hipSuccess;
     const dim3 grid(ntasks), block(kMultiThreads);
+    const SV* in = (const SV*)src;
+    SV* out = (SV*)dst;
+    SV* mi = (SV*)mid;
     if (mode == 0)
-        hipLaunchKernelGGL((fstage_multi<T, S, 0>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+        hipLaunchKernelGGL((fstage_multi<T, S, 0>), grid, block, lds, s, d_tasks, d_chans, in, out, ph, ph2, mi);
     else if (mode == 1)
-        hipLaunchKernelGGL((fstage_multi<T, S, 1>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+        hipLaunchKernelGGL((fstage_multi<T, S, 1>), grid, block, lds, s, d_tasks, d_chans, in, out, ph, ph2, mi);
     else
-        hipLaunchKernelGGL((fstage_multi<T, S, 2>), grid, block, lds, s, d_tasks, d_chans, (const SV*)src, (SV*)dst, ph, ph2);
+        hipLaunchKernelGGL((fstage_multi<T, S, 2>), grid, block, lds, s, d_tasks, d_chans, in, out, ph, ph2, mi);
     return hipGetLastError();
 }
 
@@ -637,20 +646,20 @@ template hipError_t launch_fstage_n<double, double>(int, const FChan*, int, cons
                                                     hipStream_t);
 template hipError_t launch_fstage_n<double, float>(int, const FChan*, int, const void*, void*, bool, PhaseArgs,
                                                    hipStream_t);
-template hipError_t launch_fstage_inv_fwd<float, float>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+template hipError_t launch_fstage_inv_fwd<float, float>(int, const FChan*, int, void*, void*, PhaseArgs, PhaseArgs,
                                                          hipStream_t);
-template hipError_t launch_fstage_inv_fwd<double, double>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+template hipError_t launch_fstage_inv_fwd<double, double>(int, const FChan*, int, void*, void*, PhaseArgs, PhaseArgs,
                                                            hipStream_t);
-template hipError_t launch_fstage_inv_fwd<double, float>(int, const FChan*, int, void*, PhaseArgs, PhaseArgs,
+template hipError_t launch_fstage_inv_fwd<double, float>(int, const FChan*, int, void*, void*, PhaseArgs, PhaseArgs,
                                                           hipStream_t);
 template size_t fstage_multi_lds<float>(int);
 template size_t fstage_multi_lds<double>(int);
-template hipError_t launch_fstage_multi<float, float>(const FTask*, int, const FChan*, const void*, void*, int,
+template hipError_t launch_fstage_multi<float, float>(const FTask*, int, const FChan*, const void*, void*, void*, int,
                                                       PhaseArgs, PhaseArgs, size_t, hipStream_t);
-template hipError_t launch_fstage_multi<double, double>(const FTask*, int, const FChan*, const void*, void*, int,
-                                                        PhaseArgs, PhaseArgs, size_t, hipStream_t);
-template hipError_t launch_fstage_multi<double, float>(const FTask*, int, const FChan*, const void*, void*, int,
-                                                       PhaseArgs, PhaseArgs, size_t, hipStream_t);
+template hipError_t launch_fstage_multi<double, double>(const FTask*, int, const FChan*, const void*, void*, void*,
+                                                        int, PhaseArgs, PhaseArgs, size_t, hipStream_t);
+template hipError_t launch_fstage_multi<double, float>(const FTask*, int, const FChan*, const void*, void*, void*,
+                                                       int, PhaseArgs, PhaseArgs, size_t, hipStream_t);
 template hipError_t set_lds_limits_fstage_n<float>();
 template hipError_t set_lds_limits_fstage_n<double>();
 

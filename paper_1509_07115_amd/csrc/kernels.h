@@ -123,8 +123,8 @@ hipError_t launch_fstage_n(int N, const FChan* d_chans, int nch, const void* src
 // `count` channels of size N starting at entry `first` of the channel list
 // (count <= kMultiThreads / (N/8): one block of kMultiThreads threads, N/8
 // per channel).  mode: 0 forward, 1 inverse, 2 inverse then forward (as
-// launch_fstage_inv_fwd, data in place).  lds: fstage_multi_lds maximised
-// over the tasks' N.
+// launch_fstage_inv_fwd, data in place, mid as there).  lds:
+// fstage_multi_lds maximised over the tasks' N.
 constexpr int kMultiThreads = 1024;
 struct FTask {
     int N, first, count;
@@ -133,13 +133,15 @@ template <typename T>
 size_t fstage_multi_lds(int N);
 template <typename T, typename S>
 hipError_t launch_fstage_multi(const FTask* d_tasks, int ntasks, const FChan* d_chans, const void* src, void* dst,
-                               int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s);
+                               void* mid, int mode, PhaseArgs ph, PhaseArgs ph2, size_t lds, hipStream_t s);
 
 // One step's inverse stage followed by the next step's forward stage, in place
 // on the channels' data (one launch, one pass over the data): F^T with the
-// phases ph_inv on its output, then F with ph_fwd on its input.
+// phases ph_inv on its output, then F with ph_fwd on its input.  mid: nullptr,
+// or a data buffer that also receives the state between the two stages (what
+// the inverse stage alone would store).
 template <typename T, typename S>
-hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, PhaseArgs ph_inv,
+hipError_t launch_fstage_inv_fwd(int N, const FChan* d_chans, int nch, void* data, void* mid, PhaseArgs ph_inv,
                                  PhaseArgs ph_fwd, hipStream_t s);
 template <typename T>
 hipError_t set_lds_limits_fstage_n();
