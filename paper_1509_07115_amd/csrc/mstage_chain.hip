@@ -19,10 +19,12 @@
 //                layout by two lane-swap stages (the FP64 one already is);
 //                mu_J+1 -> LDS;
 //   result waves o_J = A'[16 r : 16 r + 16, :] [x_J; mu_J], r = 0, 1, from
-//                LDS; each 16 x 16 result block is turned through LDS so that
-//                a lane stores two consecutive complex slots of one channel
-//                (16 bytes), with the kinetic phase; tile J - 1 is read out
-//                and stored while tile J's matrix instructions run.
+//                LDS, the two waves trading r from tile to tile so that both
+//                carry the same matrix work; each 16 x 16 result block is
+//                turned through LDS so that a lane stores two consecutive
+//                complex slots of one channel (16 bytes), with the kinetic
+//                phase; tile J - 1 is read out and stored while tile J's
+//                matrix instructions run.
 // The waves run one phase of kPhase tiles apart (pre, chain, results) and
 // meet at one LDS barrier per phase.  All global reads of a tile happen two
 // phases before any write of it, so the stage may run in place.  Global
@@ -488,15 +490,20 @@ struct Pipe {
     }
 
     // ---- result waves: rows 16 RB .. 16 RB + 15 of o_t ----
+    // The two result waves W = 0, 1 take row block rb(W, t) of tile t: the
+    // heavier block (rows 16..31 forward, 0..15 inverse) on every other tile,
+    // so that both carry the same matrix work.
     // Step t issues the loads of tile t + kPD, the read-out and stores of tile
     // t - 1 and the matrix instructions of tile t, so that the read-out runs
     // while the matrix core works.  The first loop iteration is peeled (no tile
     // -1), which keeps every loop body free of branches around memory operations.
-    template <int RB>
+    static constexpr int rb(int W, int t) { return ((INV ? 0 : 1) + W + t) & 1; }
+    static constexpr int lo_of(int RB) { return RB == 0 ? R0LO : R1LO; }
+    static constexpr int hi_of(int RB) { return RB == 0 ? R0HI : R1HI; }
+    static constexpr int nd_of(int RB) { return (hi_of(RB) - lo_of(RB)) / 4; }
+    static constexpr int NDMAX = nd_of(0) > nd_of(1) ? nd_of(0) : nd_of(1);
     struct Out {
-        static constexpr int LO = RB == 0 ? R0LO : R1LO, HI = RB == 0 ? R0HI : R1HI;
-        static constexpr int ND = (HI - LO) / 4;
-        V4 a[kSets][ND + KB];
+        V4 a[kSets][NDMAX + KB];      // tile t: data chunks of its row block, then the moment chunks
         V4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
         V4 wl[kSets];                 // FP32: their lo parts
         T x[kPhase][NCB * 8];         // block cb: data chunk kc in x[.][8 cb + kc]
@@ -505,27 +512,29 @@ struct Pipe {
         V4 wq[2];                     // kinetic phases of tile t in [t % 2]
         V4 wql[2];
     };
-    template <int RB, int S>
-    __device__ void out_load(Out<RB>& r, int t) const {
+    template <int W, int S>
+    __device__ void out_load(Out& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);
+        constexpr int RB = rb(W, S);
         const int J = tile(t);
-        seg<Out<RB>::ND>(r.a[S], J, RB, Out<RB>::LO / 4);
-        seg<KB>(r.a[S] + Out<RB>::ND, J, RB, 2);
+        seg<nd_of(RB)>(r.a[S], J, RB, lo_of(RB) / 4);
+        seg<KB>(r.a[S] + nd_of(RB), J, RB, 2);
         if constexpr (KPH) {
             r.w[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
             if constexpr (sizeof(T) == sizeof(float))
                 r.wl[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase_lo + J * 32 + 16 * RB + 2 * (lane & 7));
         }
     }
-    // read-out of tile t from accumulators [P]: result layout -> (channel
-    // 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through LDS, phase, 16-byte store
-    template <int RB, int P>
-    __device__ void out_epilogue(Out<RB>& r, int t) const {
+    // read-out of tile t (row block RB) from accumulators [P]: result layout ->
+    // (channel 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through this wave's LDS
+    // staging area, phase, 16-byte store
+    template <int W, int RB, int P>
+    __device__ void out_epilogue(Out& r, int t) const {
         const int J = tile(t);
         const int c = lane >> 3, s0 = 2 * (lane & 7);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-            T* y = yring + (RB * NCB + cb) * 16 * kYCol;
+            T* y = yring + (W * NCB + cb) * 16 * kYCol;
             const V4 o = r.c0[P][cb] + r.c1[P][cb];
             if constexpr (sizeof(T) == sizeof(float)) {
                 st4(y + col * kYCol + 4 * q, o);   // rows 4 (l/16) + v
@@ -556,97 +565,100 @@ struct Pipe {
                 __builtin_convertvector(v, DV4);
         }
     }
-    template <int RB, int S, bool FIRST>
-    __device__ void out_step(Out<RB>& r, int t) const {
+    template <int W, int S, bool FIRST>
+    __device__ void out_step(Out& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (!FIRST) {
             if constexpr (TAIL) {
-                if (t - 1 < NT) out_epilogue<RB, (S + 1) & 1>(r, t - 1);
+                if (t - 1 < NT) out_epilogue<W, rb(W, S + 1), (S + 1) & 1>(r, t - 1);
             } else {
-                out_epilogue<RB, (S + 1) & 1>(r, t - 1);
+                out_epilogue<W, rb(W, S + 1), (S + 1) & 1>(r, t - 1);
             }
         }
-        constexpr int LO = Out<RB>::LO, HI = Out<RB>::HI, P = S & 1;
+        constexpr int RB = rb(W, S), LO = lo_of(RB), HI = hi_of(RB), P = S & 1;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) r.c0[P][cb] = r.c1[P][cb] = zero4();
         mac<LO, HI, 8>(r.c0[P], r.c1[P], r.a[S], r.x[S % kPhase] + LO);
-        mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + Out<RB>::ND, r.mu[S % kPhase]);
+        mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + nd_of(RB), r.mu[S % kPhase]);
         __builtin_amdgcn_sched_barrier(0);
-        out_load<RB, (S + kPD) % kSets>(r, t + kPD);   // after tile t's matrix instructions (see pre_step)
+        out_load<W, (S + kPD) % kSets>(r, t + kPD);   // after tile t's matrix instructions (see pre_step)
         if constexpr (KPH) {
             r.wq[P] = r.w[S];
             if constexpr (sizeof(T) == sizeof(float)) r.wql[P] = r.wl[S];
         }
     }
-    template <int RB, int I0, bool FIRST, int I = 0>
-    __device__ void out_phase(Out<RB>& r, int t0) const {
+    template <int W, int I0, bool FIRST, int I = 0>
+    __device__ void out_phase(Out& r, int t0) const {
         if constexpr (I < kPhase) {
-            out_step<RB, I0 + I, FIRST && I0 + I == 0>(r, t0 + I);
-            out_phase<RB, I0, FIRST, I + 1>(r, t0);
+            out_step<W, I0 + I, FIRST && I0 + I == 0>(r, t0 + I);
+            out_phase<W, I0, FIRST, I + 1>(r, t0);
         }
     }
-    template <int RB, int I0, bool FIRST>
-    __device__ void out_phase_body(Out<RB>& r, int t0) const {
-#pragma unroll
-        for (int i = 0; i < kPhase; ++i) {
-            const T* xs = xring + ((t0 + i) % kXRing) * XSLOT;
-            const T* ms = mring + ((t0 + i) % kMRing) * SLOT + 4 * lane;
+    // operands of the phase's tiles (t0 even: tile t0 + i has row block rb(W, i))
+    template <int W, int I = 0>
+    __device__ void out_read(Out& r, int t0) const {
+        if constexpr (I < kPhase) {
+            constexpr int RB = rb(W, I);
+            const T* xs = xring + ((t0 + I) % kXRing) * XSLOT;
+            const T* ms = mring + ((t0 + I) % kMRing) * SLOT + 4 * lane;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-                for (int kc = 0; kc < 8; ++kc) r.x[i][8 * cb + kc] = xs[xop[cb] + 8 * kc];
+                for (int kc = lo_of(RB); kc < hi_of(RB); ++kc) r.x[I][8 * cb + kc] = xs[xop[cb] + 8 * kc];
                 const V4 m0 = ld4(ms + 2 * cb * 256);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + j] = m0[j];
+                for (int j = 0; j < 4; ++j) r.mu[I][4 * KB * cb + j] = m0[j];
                 if constexpr (KB == 2) {
                     const V4 m1 = ld4(ms + (2 * cb + 1) * 256);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) r.mu[i][4 * KB * cb + 4 + j] = m1[j];
+                    for (int j = 0; j < 4; ++j) r.mu[I][4 * KB * cb + 4 + j] = m1[j];
                 }
             }
+            out_read<W, I + 1>(r, t0);
         }
-        out_phase<RB, I0, FIRST>(r, t0);
+    }
+    template <int W, int I0, bool FIRST>
+    __device__ void out_phase_body(Out& r, int t0) const {
+        out_read<W>(r, t0);
+        out_phase<W, I0, FIRST>(r, t0);
         lds_barrier();
     }
-    template <int RB, bool FIRST, int P = 0>
-    __device__ void out_iter(Out<RB>& r, int ph) const {
+    template <int W, bool FIRST, int P = 0>
+    __device__ void out_iter(Out& r, int ph) const {
         if constexpr (P < kRep) {
-            out_phase_body<RB, P * kPhase, FIRST>(r, (ph + P) * kPhase);
-            out_iter<RB, FIRST, P + 1>(r, ph);
+            out_phase_body<W, P * kPhase, FIRST>(r, (ph + P) * kPhase);
+            out_iter<W, FIRST, P + 1>(r, ph);
         }
     }
-    template <int RB>
+    template <int W>
     __device__ void run_out() const {
-        Out<RB> r;
-        out_load<RB, 0>(r, 0);
-        out_load<RB, 1>(r, 1);
-        out_load<RB, 2>(r, 2);
+        Out r;
+        out_load<W, 0>(r, 0);
+        out_load<W, 1>(r, 1);
+        out_load<W, 2>(r, 2);
         lds_barrier();
         lds_barrier();
-        const int tl = nact * kPhase - 1;   // last step
+        const int tl = nact * kPhase - 1;   // last step (odd)
         if constexpr (TAIL) {
             // nact == 1 < kRep: one phase
-            out_phase_body<RB, 0, true>(r, 0);
-            if (tl < NT) out_epilogue<RB, (kPhase - 1) & 1>(r, tl);
+            out_phase_body<W, 0, true>(r, 0);
+            if (tl < NT) out_epilogue<W, rb(W, 1), 1>(r, tl);
         } else {
-            out_iter<RB, true>(r, 0);
-            for (int ph = kRep; ph + kRep <= nact; ph += kRep) out_iter<RB, false>(r, ph);
-            out_epilogue<RB, (kSets - 1) & 1>(r, tl);   // nact is a multiple of kRep
+            out_iter<W, true>(r, 0);
+            for (int ph = kRep; ph + kRep <= nact; ph += kRep) out_iter<W, false>(r, ph);
+            out_epilogue<W, rb(W, 1), 1>(r, tl);   // nact is a multiple of kRep
         }
     }
 
     __device__ void run() const {
-        // roles by wave: pre, chain, then the heavier result block (rows 16..31
-        // forward, 0..15 inverse) and the lighter one.  Consecutive workgroups on
-        // a compute unit start their waves one SIMD further along the sequence
-        // 0, 2, 1, 3, so this order pairs a heavy and a light role on each SIMD.
+        // roles by wave: pre, chain, then the two result waves
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         T bm[NCB * 4 * KB];
         switch (wave) {
             case 0: run_pre(); break;
             case 1: run_chain(bm); break;
-            case 2: run_out<INV ? 0 : 1>(); break;
-            default: run_out<INV ? 1 : 0>(); break;
+            case 2: run_out<0>(); break;
+            default: run_out<1>(); break;
         }
         if constexpr (!INV) {
             // the result waves' stores of tile 0 are ordered before the
