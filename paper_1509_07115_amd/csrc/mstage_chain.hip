@@ -10,14 +10,15 @@
 // inverse): rows/columns 0..31 are the tile slots, 32..63 the moments.  The
 // only serial dependence is mu_J+1 = Q x_J + D mu_J, so the work of a tile is
 // split by role:
-//   pre wave     x_J -> LDS (contiguous 16-byte loads, natural layout) and
-//                back in the operand layout, q_J = Q x_J = A'[32:64, 0:32] x_J
-//                -> LDS; tile J + 1 is staged while tile J's matrix
-//                instructions run;
+//   pre wave     q_J = Q x_J = A'[32:64, 0:32] x_J -> LDS, with x_J read
+//                from LDS in the operand layout at the start of its phase;
 //   chain wave   mu_J+1 = q_J + A'[32:64, 32:64] mu_J, with mu kept in
 //                registers: the FP32 result layout is turned into the operand
 //                layout by two lane-swap stages (the FP64 one already is);
-//                mu_J+1 -> LDS;
+//                mu_J+1 -> LDS; it also stages the tile data, x_J+4 -> LDS
+//                (contiguous 16-byte loads, natural layout), which keeps
+//                that work off the pre wave, the role with the most matrix
+//                instructions;
 //   result waves o_J = A'[16 r : 16 r + 16, :] [x_J; mu_J], r = 0, 1, from
 //                LDS, the two waves trading r from tile to tile so that both
 //                carry the same matrix work; each 16 x 16 result block is
@@ -250,15 +251,27 @@ struct Pipe {
     static __device__ void st4(T* p, V4 v) { *reinterpret_cast<V4*>(p) = v; }
     static __device__ V4 zero4() { return V4{0, 0, 0, 0}; }
 
-    // ---- pre wave: q_t = Q x_t, x_t -> LDS ----
-    // Step t issues the loads (tables of t + kPD, data of t + kPD + 1), the
-    // matrix instructions of tile t from operands already in registers, the
-    // LDS round trip that turns tile t + 1 into the operand layout, and the
-    // read-out of tile t - 1 (in the same phase) while tile t's instructions run.
+    // Tile data in the natural layout: lane l loads channel l/LPC, FPL floats
+    // from slot 4 (l%LPC) NCB of tile t, and writes them to the tile's LDS slot.
+    __device__ void load_dat(DV4* x, int t) const {
+        const DV4 DSBT_GLOBAL* g = reinterpret_cast<const DV4 DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)tile(t));
+#pragma unroll
+        for (int i = 0; i < 2 * NCB; ++i) x[i] = g[i];
+    }
+    __device__ void write_dat(const DV4* x, int t) const {
+        T* xs = xring + (t % kXRing) * XSLOT;
+#pragma unroll
+        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, __builtin_convertvector(x[i], V4));
+    }
+
+    // ---- pre wave: q_t = Q x_t ----
+    // A phase starts with the LDS reads of its tiles in the operand layout
+    // (the chain wave staged them in the phase before); step t issues the
+    // read-out of tile t - 1 (in the same phase), the matrix instructions of
+    // tile t and the table loads of tile t + kPD.
     struct Pre {
         V4 a[kSets][2 * KB];                // tables, tile t in set t % kSets
-        DV4 x[kSets][2 * NCB];              // natural-layout data, tile t in set t % kSets
-        T xv[2][NCB * 8];                   // operand layout of tile t in xv[t % 2]
+        T xv[kPhase][NCB * 8];              // operand layout of the phase's tiles
         V4 c0[kPhase][KB][NCB], c1[kPhase][KB][NCB];   // accumulators per step of a phase
     };
     template <int S>
@@ -267,24 +280,14 @@ struct Pipe {
         seg<2>(r.a[S], J, 2, 0);
         if constexpr (KB == 2) seg<2>(r.a[S] + 2, J, 3, 0);
     }
-    template <int S>
-    __device__ void pre_load_dat(Pre& r, int t) const {
-        const DV4 DSBT_GLOBAL* g = reinterpret_cast<const DV4 DSBT_GLOBAL*>(src + gpre + 64 * (int64_t)tile(t));
-#pragma unroll
-        for (int i = 0; i < 2 * NCB; ++i) r.x[S][i] = g[i];
-    }
-    // tile t (data set S) -> LDS data slot, read back in the operand layout
-    template <int S>
-    __device__ void pre_stage(Pre& r, int t) const {
-        T* xs = xring + (t % kXRing) * XSLOT;
-#pragma unroll
-        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, __builtin_convertvector(r.x[S][i], V4));
-        wave_lds_fence();
+    // tile t from its LDS data slot in the operand layout -> xv[I]
+    template <int I>
+    __device__ void pre_read(Pre& r, int t) const {
+        const T* xs = xring + (t % kXRing) * XSLOT;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int kc = 0; kc < 8; ++kc) r.xv[S & 1][8 * cb + kc] = xs[xop[cb] + 8 * kc];
-        wave_lds_fence();
+            for (int kc = 0; kc < 8; ++kc) r.xv[I][8 * cb + kc] = xs[xop[cb] + 8 * kc];
     }
     template <int S>
     __device__ void pre_mfma(Pre& r) const {
@@ -293,7 +296,7 @@ struct Pipe {
         for (int h = 0; h < KB; ++h) {
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) r.c0[I][h][cb] = r.c1[I][h][cb] = zero4();
-            mac<0, 8, 8>(r.c0[I][h], r.c1[I][h], r.a[S] + 2 * h, r.xv[S & 1]);
+            mac<0, 8, 8>(r.c0[I][h], r.c1[I][h], r.a[S] + 2 * h, r.xv[I]);
         }
     }
     template <int I>
@@ -307,7 +310,6 @@ struct Pipe {
     template <int S>
     __device__ void pre_step(Pre& r, int t) const {
         __builtin_amdgcn_sched_barrier(0);   // keep the steps (and their prefetches) in order
-        pre_load_dat<(S + kPD + 1) % kSets>(r, t + kPD + 1);
         if constexpr (S % kPhase > 0) pre_readout<S % kPhase - 1>(r, t - 1);
         pre_mfma<S>(r);
         // the table set refilled here was read by the matrix instructions of
@@ -315,7 +317,6 @@ struct Pipe {
         // keeps the loads from waiting for those reads
         __builtin_amdgcn_sched_barrier(0);
         pre_load_tab<(S + kPD) % kSets>(r, t + kPD);
-        pre_stage<(S + 1) % kSets>(r, t + 1);
     }
     // steps of one phase (tiles t0 .. t0 + kPhase - 1, register sets I0 ..)
     template <int I0, int I = 0>
@@ -327,12 +328,24 @@ struct Pipe {
             pre_readout<kPhase - 1>(r, t0 + kPhase - 1);
         }
     }
+    template <int I = 0>
+    __device__ void pre_read_phase(Pre& r, int t0) const {
+        if constexpr (I < kPhase) {
+            pre_read<I>(r, t0 + I);
+            pre_read_phase<I + 1>(r, t0);
+        }
+    }
+    template <int I0>
+    __device__ void pre_phase_body(Pre& r, int t0) const {
+        pre_read_phase(r, t0);
+        pre_phase<I0>(r, t0);
+        lds_barrier();
+    }
     // phases ph .. ph + kRep - 1
     template <int P = 0>
     __device__ void pre_iter(Pre& r, int ph) const {
         if constexpr (P < kRep) {
-            pre_phase<P * kPhase>(r, (ph + P) * kPhase);
-            lds_barrier();
+            pre_phase_body<P * kPhase>(r, (ph + P) * kPhase);
             pre_iter<P + 1>(r, ph);
         }
     }
@@ -342,30 +355,34 @@ struct Pipe {
         pre_load_tab<0>(r, 0);
         pre_load_tab<1>(r, 1);
         pre_load_tab<2>(r, 2);
-        __builtin_amdgcn_sched_barrier(0);
-        pre_load_dat<0>(r, 0);
-        pre_load_dat<1>(r, 1);
-        pre_load_dat<2>(r, 2);
-        pre_load_dat<3>(r, 3);
-        __builtin_amdgcn_sched_barrier(0);
-        pre_stage<0>(r, 0);
+        // tiles 0 .. kPhase - 1 -> LDS (the chain wave stages the later ones)
+#pragma unroll
+        for (int u = 0; u < kPhase; ++u) {
+            DV4 x[2 * NCB];
+            load_dat(x, u);
+            write_dat(x, u);
+        }
+        wave_lds_fence();
         int ph = 0;
         for (; ph + kRep <= nact; ph += kRep) pre_iter(r, ph);
         if constexpr (TAIL) {
-            if (ph < nact) {   // nact < kRep
-                pre_phase<0>(r, ph * kPhase);
-                lds_barrier();
-            }
+            if (ph < nact) pre_phase_body<0>(r, ph * kPhase);   // nact < kRep
         }
         lds_barrier();
         lds_barrier();
     }
 
     // ---- chain wave: mu_t+1 = q_t + D mu_t ----
+    // The chain wave also stages the tile data for the other roles: step t
+    // writes tile t + kStage to its LDS slot (the pre wave reads it a phase
+    // later) and loads tile t + 2 kStage in its place, kStage = 2 kPhase.
+    static constexpr int kStage = 2 * kPhase;
+    static_assert(kStage == kSets, "staging set t % kSets holds tile t + kStage");
     struct Chain {
         V4 a[kSets][NC2 + NC3];
         V4 qg[kPhase][NCB][KB];
         T bm[NCB * 4 * KB];   // block cb: moment row 4 j + l/16 in bm[4 KB cb + j]
+        DV4 x[kSets][2 * NCB];   // natural-layout data, tile t + kStage in set t % kSets
     };
     template <int S>
     __device__ void chain_load(Chain& r, int t) const {
@@ -416,6 +433,8 @@ struct Pipe {
             if constexpr (KB == 2) result_to_operand(m3[cb], r.bm + 4 * KB * cb + 4);
         }
         store_mu(r, t + 1);
+        write_dat(r.x[S], t + kStage);
+        load_dat(r.x[S], t + 2 * kStage);
     }
     template <int I0, int I = 0>
     __device__ void chain_phase(Chain& r, int t0) const {
@@ -450,6 +469,17 @@ struct Pipe {
         chain_load<0>(r, 0);
         chain_load<1>(r, 1);
         chain_load<2>(r, 2);
+        // staging: tiles kPhase .. kStage - 1 (read by the pre wave in its
+        // second phase) now, tiles kStage .. 2 kStage - 1 into the sets
+#pragma unroll
+        for (int u = kPhase; u < kStage; ++u) load_dat(r.x[u], u);
+#pragma unroll
+        for (int u = 0; u < kPhase; ++u) load_dat(r.x[u], u + kStage);
+#pragma unroll
+        for (int u = kPhase; u < kStage; ++u) {
+            write_dat(r.x[u], u);
+            load_dat(r.x[u], u + kStage);
+        }
         // mu_0: zero forward; inverse (-1)^p times the completion slots 0..k-1 of tile 0
         const T sgn = p ? -1 : 1;
 #pragma unroll
@@ -651,20 +681,24 @@ struct Pipe {
     }
 
     __device__ void run() const {
-        // roles by wave: pre, chain, then the two result waves
+        // roles by wave: pre, result, chain, result.  Two workgroups on a
+        // compute unit place their waves on the SIMDs in the order 0, 2, 1, 3,
+        // the second starting one SIMD further along, so that each SIMD holds
+        // wave w of one and wave w - 1 of the other: this order pairs every
+        // result wave with a pre or chain wave.
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         T bm[NCB * 4 * KB];
         switch (wave) {
             case 0: run_pre(); break;
-            case 1: run_chain(bm); break;
-            case 2: run_out<0>(); break;
+            case 1: run_out<0>(); break;
+            case 2: run_chain(bm); break;
             default: run_out<1>(); break;
         }
         if constexpr (!INV) {
             // the result waves' stores of tile 0 are ordered before the
             // completion rows that replace slots 0..k-1
             __syncthreads();
-            if (wave == 1) completion(bm);
+            if (wave == 2) completion(bm);
         }
     }
 };
