@@ -795,33 +795,45 @@ hipError_t launch_mf(dsbt_plan_s* P, const dsbt::MItem* items, int n, int ncb, c
     return dsbt::launch_mstage_mfma(items, n, P->mf_waves, P->mf_lds, src, dst, inverse, ph, s);
 }
 
+// kin: the kinetic factors of a split step, which sit between the forward and
+// the inverse moment stage: callers pass the same kin to both directions, and
+// each kernel applies it on its side (the four-wave pipeline to the inverse's
+// input, the other moment kernels to the forward's output).
+inline dsbt::PhaseArgs kin_for(bool chain_kernel, bool inverse, dsbt::PhaseArgs kin) {
+    return (chain_kernel ? inverse : !inverse) ? kin : dsbt::PhaseArgs{};
+}
+
 template <typename T, typename S>
-void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs ph) {
+void enqueue_mstage(dsbt_plan_s* P, const void* src, void* dst, bool inverse, hipStream_t s, dsbt::PhaseArgs kin) {
     if (P->d_lchans) {
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(dsbt::launch_monomial(P->d_lchans, (int)P->h_lchans.size(), src, dst, inverse, ph, s), "monomial");
+            hip_check(dsbt::launch_monomial(P->d_lchans, (int)P->h_lchans.size(), src, dst, inverse,
+                                            kin_for(false, inverse, kin), s), "monomial");
         });
         return;
     }
     if (P->d_items_mf)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(launch_mf<T, S>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T, S>(P, P->d_items_mf, (int)P->h_items_mf.size(), P->chain_ncb, src, dst, inverse,
+                                      kin_for(P->mf_waves == 4, inverse, kin), s), "mstage_mfma");
         });
     if (P->d_items_v1)
         timed(P, DSBT_STAGE_MOMENT, s, [&] {
-            hip_check(dsbt::launch_mstage<T, S>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse, ph,
-                                             s), "mstage");
+            hip_check(dsbt::launch_mstage<T, S>(P->d_items_v1, (int)P->h_items_v1.size(), P->maxR, src, dst, inverse,
+                                                kin_for(false, inverse, kin), s), "mstage");
         });
 }
 
 template <typename T, typename S>
 void enqueue_mstage_one(dsbt_plan_s* P, int c, const void* src, void* dst, bool inverse, hipStream_t s,
-                        dsbt::PhaseArgs ph) {
+                        dsbt::PhaseArgs kin) {
     timed(P, DSBT_STAGE_MOMENT, s, [&] {
         if (P->items1_mf[c])
-            hip_check(launch_mf<T, S>(P, P->d_items1 + c, 1, 1, src, dst, inverse, ph, s), "mstage_mfma");
+            hip_check(launch_mf<T, S>(P, P->d_items1 + c, 1, 1, src, dst, inverse,
+                                      kin_for(P->mf_waves == 4, inverse, kin), s), "mstage_mfma");
         else
-            hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse, ph, s), "mstage");
+            hip_check(dsbt::launch_mstage<T, S>(P->d_items1 + c, 1, P->maxR, src, dst, inverse,
+                                                kin_for(false, inverse, kin), s), "mstage");
     });
 }
 
@@ -868,20 +880,22 @@ void enqueue_forward(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, 
     enqueue_mstage<T, S>(P, dst, dst, false, s, pk);
 }
 
+// pk: the kinetic factors given to the preceding enqueue_forward (see
+// enqueue_mstage), or none
 template <typename T, typename S>
-void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv) {
+void enqueue_inverse(dsbt_plan_s* P, const void* src, void* dst, hipStream_t s, dsbt::PhaseArgs pv,
+                     dsbt::PhaseArgs pk = dsbt::PhaseArgs{}) {
     const int nch = (int)P->ch.size();
-    dsbt::PhaseArgs none{};
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int c = 0; c < nch; ++c) {
-            enqueue_mstage_one<T, S>(P, c, src, dst, true, s, none);
+            enqueue_mstage_one<T, S>(P, c, src, dst, true, s, pk);
             timed(P, DSBT_STAGE_SINCOS, s, [&] {
                 hip_check(dsbt::launch_fstage_n<T, S>(P->ch[c].N, P->d_fchans + c, 1, dst, dst, true, pv, s), "fstage");
             });
         }
         return;
     }
-    enqueue_mstage<T, S>(P, src, dst, true, s, none);
+    enqueue_mstage<T, S>(P, src, dst, true, s, pk);
     enqueue_fstage<T, S>(P, dst, dst, 1, pv, dsbt::PhaseArgs{}, s);
 }
 
@@ -899,14 +913,14 @@ void enqueue_steps(dsbt_plan_s* P, void* psi, int nsteps, const float* sc, bool 
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int u = 0; u < nsteps; ++u) {
             enqueue_forward<T, S>(P, psi, psi, s, pv_of(u), pk);
-            enqueue_inverse<T, S>(P, psi, psi, s, pv_of(u));
+            enqueue_inverse<T, S>(P, psi, psi, s, pv_of(u), pk);
         }
         return;
     }
     enqueue_fstage<T, S>(P, psi, psi, 0, pv_of(0), none, s);
     for (int u = 0; u < nsteps; ++u) {
         enqueue_mstage<T, S>(P, psi, psi, false, s, pk);
-        enqueue_mstage<T, S>(P, psi, psi, true, s, none);
+        enqueue_mstage<T, S>(P, psi, psi, true, s, pk);
         if (u + 1 < nsteps)
             enqueue_fstage<T, S>(P, psi, psi, 2, pv_of(u), pv_of(u + 1), s);
         else
@@ -960,13 +974,13 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
         for (int t = 0; t < n; ++t) {
             const dsbt::PhaseArgs pv{1, 0, P->seg_s, t}, pk{1, 0, nullptr, 0};
             enqueue_forward<T, S>(P, state(t), state(t + 1), q, pv, pk);
-            enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv);
+            enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv, pk);
         }
         int cur = 0;   // lam[cur] holds lam_{t+1}
         for (int t = n - 1; t >= 0; --t) {
             const dsbt::PhaseArgs pv{1, 1, P->seg_s, t}, pk{1, 1, nullptr, 0};
             enqueue_forward<T, S>(P, lam[cur], lam[cur ^ 1], q, pv, pk);
-            enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv);
+            enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv, pk);
             grad(t, cur);
             cur ^= 1;
         }
@@ -980,7 +994,7 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
         enqueue_fstage<T, S>(P, state(0), w, 0, pv(0), none, q);
         for (int t = 0; t < n; ++t) {
             enqueue_mstage<T, S>(P, w, w, false, q, pk);
-            enqueue_mstage<T, S>(P, w, w, true, q, none);
+            enqueue_mstage<T, S>(P, w, w, true, q, pk);
             if (t + 1 < n)
                 enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t + 1), q, state(t + 1));
             else
@@ -993,7 +1007,7 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
     int cur = 0;   // lam[cur] holds lam_{t+1}
     for (int t = n - 1; t >= 0; --t) {
         enqueue_mstage<T, S>(P, w, w, false, q, pk);
-        enqueue_mstage<T, S>(P, w, w, true, q, none);
+        enqueue_mstage<T, S>(P, w, w, true, q, pk);
         if (t > 0)
             enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), q, lam[cur ^ 1]);
         else

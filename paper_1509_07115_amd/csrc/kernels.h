@@ -174,7 +174,9 @@ hipError_t set_lds_limits_mfma();
 // arithmetic, items of one column block, complex64 or complex128 data).  An item has NCB = 1 or 2 blocks of
 // 8 channels (off[]: slots past nch repeat a real channel); ncb is the largest
 // NCB of the launched items and sizes the LDS.  Runs in place.  Phases
-// (ph.use, complex of T per slot) are supported on the forward direction only.
+// (ph.use, complex of T per slot) are supported on the inverse direction only,
+// where they multiply the input (the other moment kernels apply them to the
+// forward's output: the kinetic factor of a split step sits between the two).
 // D: data scalar in memory, float (complex64) or, with T = double, double
 // (complex128).
 template <typename T, typename D>

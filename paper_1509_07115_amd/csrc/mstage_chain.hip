@@ -23,9 +23,11 @@
 //                LDS, the two waves trading r from tile to tile so that both
 //                carry the same matrix work; each 16 x 16 result block is
 //                turned through LDS so that a lane stores two consecutive
-//                complex slots of one channel (16 bytes), with the kinetic
-//                phase; tile J - 1 is read out and stored while tile J's
-//                matrix instructions run.
+//                complex slots of one channel (16 bytes); tile J - 1 is read
+//                out and stored while tile J's matrix instructions run.
+// The kinetic factors of a split step (Sec. 4.1) multiply the inverse's input
+// where the chain wave stages it (and the completion slots it starts from),
+// which keeps them off the result waves of the forward direction.
 // The waves run one phase of kPhase tiles apart (pre, chain, results) and
 // meet at one LDS barrier per phase.  All global reads of a tile happen two
 // phases before any write of it, so the stage may run in place.  Global
@@ -258,10 +260,42 @@ struct Pipe {
 #pragma unroll
         for (int i = 0; i < 2 * NCB; ++i) x[i] = g[i];
     }
-    __device__ void write_dat(const DV4* x, int t) const {
+    // With KPH (inverse only) the staged values are the input times the
+    // kinetic factors of their slots (conjugated for the adjoint step), which
+    // load_kph fetches ahead into registers.
+    struct Kph {
+        V4 w[2 * NCB], wl[2 * NCB];   // factors of the lane's slot pairs (wl: FP32 lo parts)
+    };
+    __device__ int slot0(int t) const { return 32 * tile(t) + (FPL / 2) * (lane % LPC); }   // slot of x[0].xy
+    __device__ void load_kph(Kph& k, int t) const {
+        const int n0 = slot0(t);
+#pragma unroll
+        for (int i = 0; i < 2 * NCB; ++i) {
+            k.w[i] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase + n0 + 2 * i);
+            if constexpr (sizeof(T) == sizeof(float))
+                k.wl[i] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase_lo + n0 + 2 * i);
+        }
+    }
+    __device__ void write_dat(const DV4* x, int t, const Kph& k) const {
         T* xs = xring + (t % kXRing) * XSLOT;
 #pragma unroll
-        for (int i = 0; i < 2 * NCB; ++i) st4(xs + xnat + 4 * i, __builtin_convertvector(x[i], V4));
+        for (int i = 0; i < 2 * NCB; ++i) {
+            V4 v = __builtin_convertvector(x[i], V4);
+            if constexpr (KPH) v = times_kphase(v, k.w[i], k.wl[i]);
+            st4(xs + xnat + 4 * i, v);
+        }
+    }
+    // (v.x + i v.y, v.z + i v.w) times the factors (w.x + i w.y, w.z + i w.w)
+    __device__ V4 times_kphase(V4 v, V4 w, V4 l) const {
+        const T s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
+        if constexpr (sizeof(T) == sizeof(float)) {
+            const T l1 = conj ? -l.y : l.y, l2 = conj ? -l.w : l.w;
+            const float2 a = mul_unit(make_float2(v.x, v.y), make_float2(w.x, s1), make_float2(l.x, l1));
+            const float2 b = mul_unit(make_float2(v.z, v.w), make_float2(w.z, s2), make_float2(l.z, l2));
+            return V4{a.x, a.y, b.x, b.y};
+        } else {
+            return V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
+        }
     }
 
     // ---- pre wave: q_t = Q x_t ----
@@ -360,7 +394,9 @@ struct Pipe {
         for (int u = 0; u < kPhase; ++u) {
             DV4 x[2 * NCB];
             load_dat(x, u);
-            write_dat(x, u);
+            Kph k;
+            if constexpr (KPH) load_kph(k, u);
+            write_dat(x, u, k);
         }
         wave_lds_fence();
         int ph = 0;
@@ -378,11 +414,16 @@ struct Pipe {
     // later) and loads tile t + 2 kStage in its place, kStage = 2 kPhase.
     static constexpr int kStage = 2 * kPhase;
     static_assert(kStage == kSets, "staging set t % kSets holds tile t + kStage");
+    // kinetic factors are fetched kKS steps before their tile is staged (two
+    // sets of registers for items of one column block, one for two)
+    static constexpr int kKS = NCB == 1 ? 2 : 1;
+    static_assert(kSets % kKS == 0, "a loop iteration must cycle through the factor sets");
     struct Chain {
         V4 a[kSets][NC2 + NC3];
         V4 qg[kPhase][NCB][KB];
         T bm[NCB * 4 * KB];   // block cb: moment row 4 j + l/16 in bm[4 KB cb + j]
         DV4 x[kSets][2 * NCB];   // natural-layout data, tile t + kStage in set t % kSets
+        Kph k[kKS];              // KPH: kinetic factors of tile t + kStage in k[t % kKS]
     };
     template <int S>
     __device__ void chain_load(Chain& r, int t) const {
@@ -433,8 +474,9 @@ struct Pipe {
             if constexpr (KB == 2) result_to_operand(m3[cb], r.bm + 4 * KB * cb + 4);
         }
         store_mu(r, t + 1);
-        write_dat(r.x[S], t + kStage);
+        write_dat(r.x[S], t + kStage, r.k[S % kKS]);
         load_dat(r.x[S], t + 2 * kStage);
+        if constexpr (KPH) load_kph(r.k[S % kKS], t + kStage + kKS);   // staged kKS steps on
     }
     template <int I0, int I = 0>
     __device__ void chain_phase(Chain& r, int t0) const {
@@ -477,8 +519,13 @@ struct Pipe {
         for (int u = 0; u < kPhase; ++u) load_dat(r.x[u], u + kStage);
 #pragma unroll
         for (int u = kPhase; u < kStage; ++u) {
-            write_dat(r.x[u], u);
+            if constexpr (KPH) load_kph(r.k[0], u);
+            write_dat(r.x[u], u, r.k[0]);
             load_dat(r.x[u], u + kStage);
+        }
+        if constexpr (KPH) {
+#pragma unroll
+            for (int i = 0; i < kKS; ++i) load_kph(r.k[(kStage + i) % kKS], kStage + i);
         }
         // mu_0: zero forward; inverse (-1)^p times the completion slots 0..k-1 of tile 0
         const T sgn = p ? -1 : 1;
@@ -487,7 +534,13 @@ struct Pipe {
 #pragma unroll
             for (int j = 0; j < 4 * KB; ++j) {
                 const int row = 4 * j + q;
-                r.bm[4 * KB * cb + j] = (INV && row < k) ? sgn * (T)src[e0[cb] + 2 * row] : T(0);
+                T x = (INV && row < k) ? sgn * (T)src[e0[cb] + 2 * row] : T(0);
+                if constexpr (KPH) {
+                    // lanes col and col ^ 1 hold the (re, im) pair of one slot
+                    const V2 wl = sizeof(T) == sizeof(float) ? kphase_lo[row] : V2{0, 0};
+                    x = phase(x, kphase[row], wl, col & 1, conj);
+                }
+                r.bm[4 * KB * cb + j] = x;
             }
         store_mu(r, 0);
         lds_barrier();
@@ -510,11 +563,7 @@ struct Pipe {
 #pragma unroll
             for (int j = 0; j < 4 * KB; ++j) {
                 const int row = 4 * j + q;
-                T x = sgn * bm[4 * KB * cb + j];
-                if constexpr (KPH) {
-                    const V2 wl = sizeof(T) == sizeof(float) ? kphase_lo[row] : V2{0, 0};
-                    x = phase(x, kphase[row], wl, col & 1, conj);
-                }
+                const T x = sgn * bm[4 * KB * cb + j];
                 if (row < k) dst[e0[cb] + 2 * row] = (D)x;
             }
     }
@@ -534,13 +583,9 @@ struct Pipe {
     static constexpr int NDMAX = nd_of(0) > nd_of(1) ? nd_of(0) : nd_of(1);
     struct Out {
         V4 a[kSets][NDMAX + KB];      // tile t: data chunks of its row block, then the moment chunks
-        V4 w[kSets];                  // kinetic phases of the two stored slots (re, im, re, im)
-        V4 wl[kSets];                 // FP32: their lo parts
         T x[kPhase][NCB * 8];         // block cb: data chunk kc in x[.][8 cb + kc]
         T mu[kPhase][NCB * 4 * KB];
         V4 c0[2][NCB], c1[2][NCB];    // accumulators of tile t in [t % 2]
-        V4 wq[2];                     // kinetic phases of tile t in [t % 2]
-        V4 wql[2];
     };
     template <int W, int S>
     __device__ void out_load(Out& r, int t) const {
@@ -549,15 +594,10 @@ struct Pipe {
         const int J = tile(t);
         seg<nd_of(RB)>(r.a[S], J, RB, lo_of(RB) / 4);
         seg<KB>(r.a[S] + nd_of(RB), J, RB, 2);
-        if constexpr (KPH) {
-            r.w[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase + J * 32 + 16 * RB + 2 * (lane & 7));
-            if constexpr (sizeof(T) == sizeof(float))
-                r.wl[S] = *reinterpret_cast<const V4 DSBT_GLOBAL*>(kphase_lo + J * 32 + 16 * RB + 2 * (lane & 7));
-        }
     }
     // read-out of tile t (row block RB) from accumulators [P]: result layout ->
     // (channel 8 cb + l/8, slots 2 (l%8), 2 (l%8) + 1) through this wave's LDS
-    // staging area, phase, 16-byte store
+    // staging area, 16-byte store
     template <int W, int RB, int P>
     __device__ void out_epilogue(Out& r, int t) const {
         const int J = tile(t);
@@ -576,20 +616,7 @@ struct Pipe {
             const V2 re = *reinterpret_cast<const V2*>(y + 2 * c * kYCol + s0);
             const V2 im = *reinterpret_cast<const V2*>(y + (2 * c + 1) * kYCol + s0);
             wave_lds_fence();
-            V4 v = V4{re.x, im.x, re.y, im.y};
-            if constexpr (KPH) {
-                const V4 w = r.wq[P];
-                const T s1 = conj ? -w.y : w.y, s2 = conj ? -w.w : w.w;
-                if constexpr (sizeof(T) == sizeof(float)) {
-                    const V4 l = r.wql[P];
-                    const T l1 = conj ? -l.y : l.y, l2 = conj ? -l.w : l.w;
-                    const float2 a = mul_unit(make_float2(v.x, v.y), make_float2(w.x, s1), make_float2(l.x, l1));
-                    const float2 b = mul_unit(make_float2(v.z, v.w), make_float2(w.z, s2), make_float2(l.z, l2));
-                    v = V4{a.x, a.y, b.x, b.y};
-                } else {
-                    v = V4{v.x * w.x - v.y * s1, v.x * s1 + v.y * w.x, v.z * w.z - v.w * s2, v.z * s2 + v.w * w.z};
-                }
-            }
+            const V4 v = V4{re.x, im.x, re.y, im.y};
             // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
             *reinterpret_cast<DV4 DSBT_GLOBAL*>(dst + g0[cb] + 64 * (int64_t)J + 2 * (16 * RB + s0)) =
                 __builtin_convertvector(v, DV4);
@@ -612,10 +639,6 @@ struct Pipe {
         mac<8, MHI, 4 * KB>(r.c0[P], r.c1[P], r.a[S] + nd_of(RB), r.mu[S % kPhase]);
         __builtin_amdgcn_sched_barrier(0);
         out_load<W, (S + kPD) % kSets>(r, t + kPD);   // after tile t's matrix instructions (see pre_step)
-        if constexpr (KPH) {
-            r.wq[P] = r.w[S];
-            if constexpr (sizeof(T) == sizeof(float)) r.wql[P] = r.wl[S];
-        }
     }
     template <int W, int I0, bool FIRST, int I = 0>
     __device__ void out_phase(Out& r, int t0) const {
@@ -746,11 +769,11 @@ hipError_t set_lds_limits_chain() {
         if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     };
     set((const void*)mstage_chain<T, float, true, false>);
-    set((const void*)mstage_chain<T, float, false, true>);
+    set((const void*)mstage_chain<T, float, true, true>);
     set((const void*)mstage_chain<T, float, false, false>);
     if constexpr (sizeof(T) == sizeof(double)) {
         set((const void*)mstage_chain<T, double, true, false>);
-        set((const void*)mstage_chain<T, double, false, true>);
+        set((const void*)mstage_chain<T, double, true, true>);
         set((const void*)mstage_chain<T, double, false, false>);
     }
     return e;
@@ -760,14 +783,14 @@ template <typename T, typename D>
 hipError_t launch_mstage_chain(const MItem* d_items, int nitems, int ncb, const void* src, void* dst, bool inverse,
                                PhaseArgs ph, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (inverse && ph.use) return hipErrorInvalidValue;   // phases are applied on the forward output only
+    if (!inverse && ph.use) return hipErrorInvalidValue;   // phases are applied to the inverse's input only
     if (sizeof(T) != sizeof(float) && ncb != 1) return hipErrorInvalidValue;
     if (sizeof(D) > sizeof(T)) return hipErrorInvalidValue;
     const size_t lds = chain_lds_bytes<T>(ncb);
-    if (inverse)
+    if (inverse && ph.use)
+        hipLaunchKernelGGL((mstage_chain<T, D, true, true>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
+    else if (inverse)
         hipLaunchKernelGGL((mstage_chain<T, D, true, false>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
-    else if (ph.use)
-        hipLaunchKernelGGL((mstage_chain<T, D, false, true>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
     else
         hipLaunchKernelGGL((mstage_chain<T, D, false, false>), dim3(nitems), dim3(256), lds, s, d_items, src, dst, ph);
     return hipGetLastError();

@@ -141,6 +141,32 @@ def test_fused_step_stages_agree_bitwise_with_separate_launches():
     assert torch.equal(a, b)
 
 
+def test_steps_of_two_block_items_agree_bitwise_with_plain():
+    # l = 0..63 with all m (4096 channels) gives 288 items of 16 channels, more
+    # than the device's compute units, so the batched moment stage runs items
+    # of two 16-column blocks; the plain form runs one channel per launch.
+    # Split steps with the kinetic factors (forward and adjoint): same products
+    # per channel, bitwise equal results
+    w = workloads.batched_all_m(seed=12, N=256, rmax=25.6, lmax=63)
+    V = np.concatenate([-1.0 / np.sqrt(workloads.grid(N, rmax) ** 2 + 0.1) for N, _, rmax, _ in w.channels])
+    pb, pp = Plan(w.channels), Plan(w.channels, mode="plain")
+    for p in (pb, pp):
+        p.set_potential(V, 0.01)
+    x = to_dev(w.psi, torch.complex64)
+    a, b = x.clone(), x.clone()
+    s = torch.tensor([1.0, 0.9], dtype=torch.float32, device="cuda")
+    pb.kinetic_step(a, 2, s)
+    pp.kinetic_step(b, 2, s)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    pb.kinetic_step(a, 2, s, adjoint=True)
+    pp.kinetic_step(b, 2, s, adjoint=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # two steps and their adjoint return the input to rounding
+    assert float(torch.max(torch.abs(a - x)).item()) < 1e-5 * float(torch.max(torch.abs(x)).item())
+
+
 def test_in_place_and_offsets_with_gaps():
     rng = np.random.default_rng(3)
     chans = [(128, 5, 12.0, 7), (256, 12, 30.0, 400), (128, 0, 5.0, 1000)]
