@@ -22,9 +22,10 @@
 //   result waves o_J = A'[16 r : 16 r + 16, :] [x_J; mu_J], r = 0, 1, from
 //                LDS, the two waves trading r from tile to tile so that both
 //                carry the same matrix work; each 16 x 16 result block is
-//                turned through LDS so that a lane stores two consecutive
-//                complex slots of one channel (16 bytes); tile J - 1 is read
-//                out and stored while tile J's matrix instructions run.
+//                rearranged (FP32: between lane pairs; FP64: through LDS) so
+//                that a lane stores two consecutive complex slots of one
+//                channel (16 bytes); tile J - 1 is read out and stored while
+//                tile J's matrix instructions run.
 // The kinetic factors of a split step (Sec. 4.1) multiply the inverse's input
 // where the chain wave stages it (and the completion slots it starts from),
 // which keeps them off the result waves of the forward direction.
@@ -248,6 +249,10 @@ struct Pipe {
             const T s = cj ? -w.y : w.y;
             return im ? x * w.x + y * s : x * w.x - y * s;
         }
+    }
+    // the value of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2)
+    static __device__ float swap_pair(float x) {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
     }
     static __device__ V4 ld4(const T* p) { return *reinterpret_cast<const V4*>(p); }
     static __device__ void st4(T* p, V4 v) { *reinterpret_cast<V4*>(p) = v; }
@@ -601,17 +606,33 @@ struct Pipe {
     template <int W, int RB, int P>
     __device__ void out_epilogue(Out& r, int t) const {
         const int J = tile(t);
+        if constexpr (sizeof(T) == sizeof(float)) {
+            // lane l holds rows 4 (l/16) + v of column l%16, the re (even
+            // column) or im (odd) part of channel 8 cb + (l%16)/2: the lane
+            // pair (col, col ^ 1) trades two values (one DPP move each) so that
+            // the even lane holds rows 4 (l/16) + 0, 1 and the odd one rows
+            // 4 (l/16) + 2, 3 as (re, im, re, im), two consecutive slots
+            const bool odd = col & 1;
+            const int s0 = 16 * RB + 4 * q + 2 * (col & 1);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const V4 o = r.c0[P][cb] + r.c1[P][cb];
+                const float g0 = swap_pair(odd ? o[0] : o[2]);
+                const float g1 = swap_pair(odd ? o[1] : o[3]);
+                const V4 v = odd ? V4{g0, o[2], g1, o[3]} : V4{o[0], g0, o[1], g1};
+                // forward: slots 0..k-1 of tile 0 are rewritten with the completion rows at the end
+                *reinterpret_cast<DV4 DSBT_GLOBAL*>(dst + (e0[cb] - (col & 1)) + 64 * (int64_t)J + 2 * s0) =
+                    __builtin_convertvector(v, DV4);
+            }
+            return;
+        }
         const int c = lane >> 3, s0 = 2 * (lane & 7);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             T* y = yring + (W * NCB + cb) * 16 * kYCol;
             const V4 o = r.c0[P][cb] + r.c1[P][cb];
-            if constexpr (sizeof(T) == sizeof(float)) {
-                st4(y + col * kYCol + 4 * q, o);   // rows 4 (l/16) + v
-            } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) y[col * kYCol + 4 * v + q] = o[v];   // rows 4 v + l/16
-            }
+            for (int v = 0; v < 4; ++v) y[col * kYCol + 4 * v + q] = o[v];   // rows 4 v + l/16
             wave_lds_fence();
             const V2 re = *reinterpret_cast<const V2*>(y + 2 * c * kYCol + s0);
             const V2 im = *reinterpret_cast<const V2*>(y + (2 * c + 1) * kYCol + s0);
