@@ -660,6 +660,9 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         for (size_t i0 = 0; i0 < g.chans.size(); i0 += per) {
             dsbt::MItem it = base;
             it.nch = (int)std::min<size_t>(per, g.chans.size() - i0);
+            // a last item of at most 8 channels needs one column block (half
+            // the matrix work of two)
+            if (mf && P->mf_waves == 4 && it.NCB == 2 && it.nch <= 8) it.NCB = 1;
             for (int j = 0; j < dsbt::kMaxChanPerItem; ++j)
                 it.off[j] = P->ch[g.chans[i0 + (j < it.nch ? j : 0)]].offset;   // repeat a real channel
             if (mf) {
