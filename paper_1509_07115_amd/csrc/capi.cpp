@@ -660,9 +660,18 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         for (size_t i0 = 0; i0 < g.chans.size(); i0 += per) {
             dsbt::MItem it = base;
             it.nch = (int)std::min<size_t>(per, g.chans.size() - i0);
-            // a last item of at most 8 channels needs one column block (half
-            // the matrix work of two)
-            if (mf && P->mf_waves == 4 && it.NCB == 2 && it.nch <= 8) it.NCB = 1;
+            if (mf && P->mf_waves == 4 && it.NCB == 2) {
+                // the rest of an l group in items of one column block (half the
+                // matrix work of two): a last item of at most 8 channels, and
+                // for k <= 16 every last item, which leaves the scheduler light
+                // items to pair on the compute units that must hold two
+                const size_t rest = g.chans.size() - i0;
+                if (rest <= 8 || (rest < 16 && g.k <= 16)) {
+                    it.NCB = 1;
+                    it.nch = (int)std::min<size_t>(8, rest);
+                    per = 8;
+                }
+            }
             for (int j = 0; j < dsbt::kMaxChanPerItem; ++j)
                 it.off[j] = P->ch[g.chans[i0 + (j < it.nch ? j : 0)]].offset;   // repeat a real channel
             if (mf) {
@@ -717,12 +726,27 @@ void build_plan(dsbt_plan_s* P, hipStream_t s) {
         }
         std::stable_sort(chunks.begin(), chunks.end(),
                          [](const auto& a, const auto& b) { return a.first > b.first; });
+        // least loaded XCD, among those where the chunk's items that should
+        // not share a compute unit with anything but the lightest items (all
+        // but the lightest class) still find a compute unit of their own
+        double lightest = 0.0;
+        for (auto& it : items_mf) {
+            const double c = cost_of(it);
+            if (lightest == 0.0 || c < lightest) lightest = c;
+        }
         std::vector<std::vector<int>> bins(nx);
         std::vector<double> load(nx, 0.0);
+        std::vector<int> nbig(nx, 0);
         for (auto& ch : chunks) {
-            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            int big = 0;
+            for (int i : ch.second) big += cost_of(items_mf[i]) > lightest ? 1 : 0;
+            int x = -1;
+            for (int y = 0; y < nx; ++y)
+                if (nbig[y] + big <= cpx && (x < 0 || load[y] < load[x])) x = y;
+            if (x < 0) x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             for (int i : ch.second) bins[x].push_back(i);
             load[x] += ch.first;
+            nbig[x] += big;
         }
         std::vector<std::vector<int>> order(nx);   // per XCD, in block order; -1: idle slot
         for (int x = 0; x < nx; ++x) {
