@@ -239,8 +239,11 @@ def _small_tdse(N=256, rmax=25.6, lmax=3, dt=0.01):
     return workloads.tdse(seed=5, N=N, rmax=rmax, lmax=lmax, dt=dt, small=0.1)
 
 
-def test_step_matches_oracle_and_is_unitary():
-    w = _small_tdse()
+@pytest.mark.parametrize("N,rmax,lmax", [(256, 25.6, 3), (64, 12.8, 6)])
+def test_step_matches_oracle_and_is_unitary(N, rmax, lmax):
+    # N = 64: two tiles of 32 per channel, fewer than a pipeline loop
+    # iteration (the tail variant), with the kinetic factors on the inverse
+    w = _small_tdse(N=N, rmax=rmax, lmax=lmax)
     plan = Plan(w.channels)
     plan.set_potential(w.extra["V"], w.extra["dt"])
     d = to_dev(w.psi, torch.complex64)
