@@ -228,6 +228,7 @@ struct dsbt_plan_s {
     void* seg_lam = nullptr;
     float* seg_s = nullptr;
     double* seg_gs = nullptr;
+    double* seg_part = nullptr;   // per-channel partials of the segment's gradients
     int seg_cap = 0;
     hipGraphExec_t seg_exec = nullptr;
     hipGraph_t seg_graph = nullptr;
@@ -279,9 +280,11 @@ struct dsbt_plan_s {
         dfree(seg_lam);
         dfree(seg_s);
         dfree(seg_gs);
+        dfree(seg_part);
         seg_states = seg_lam = nullptr;
         seg_s = nullptr;
         seg_gs = nullptr;
+        seg_part = nullptr;
         seg_cap = 0;
     }
     void release() {
@@ -978,42 +981,45 @@ void capture_graph(F&& enqueue, hipGraph_t* graph, hipGraphExec_t* exec) {
     hip_check(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
+// Adjoint buffer holding the segment's result lam_a: the batched form keeps
+// lam_t in buffer t; the plain form alternates two buffers.
+inline int segment_result_buffer(const dsbt_plan_s* P, int n) {
+    return P->opts.mode == DSBT_MODE_PLAIN ? (n & 1) : 0;
+}
+
 // One checkpoint segment of the adjoint method on the plan's segment buffers
 // (dsbt_adjoint_segment): states 1..n from state 0, then the n adjoint steps
-// and strength gradients, lam_{t+1} -> lam_t alternating between the two
-// adjoint buffers (lam_a ends in buffer n mod 2).  Batched plans carry each
-// pass in the work buffer (the third adjoint buffer) with the fused inverse +
-// forward stage, which also stores the state between two steps where the
-// gradients read it: three launches a step instead of four, bitwise the same
-// results.
+// lam_{t+1} -> lam_t and the strength gradients.  Batched plans carry each
+// pass in a work buffer (adjoint buffer n + 1) through the fused inverse +
+// forward stage, which also stores the state between two steps: psi_t into
+// state t, lam_t into adjoint buffer t (lam_n is given there).  All n
+// gradients then take two launches; the plain form alternates lam between
+// adjoint buffers 0 and 1 and reduces each step's gradient in turn.  Both
+// give the results of separate step and gradient calls bitwise.
 template <typename T, typename S>
 void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
     const size_t sb = (size_t)P->elems * P->elem_bytes;
     auto state = [&](int t) { return static_cast<unsigned char*>(P->seg_states) + sb * (size_t)t; };
-    unsigned char* lam[3] = {static_cast<unsigned char*>(P->seg_lam), static_cast<unsigned char*>(P->seg_lam) + sb,
-                             static_cast<unsigned char*>(P->seg_lam) + 2 * sb};
+    auto lam = [&](int t) { return static_cast<unsigned char*>(P->seg_lam) + sb * (size_t)t; };
     const int nch = (int)P->ch.size();
-    auto grad = [&](int t, int cur) {
-        hip_check(dsbt::launch_grad_s<S>(P->d_fchans, nch, state(t), state(t + 1), lam[cur ^ 1], lam[cur],
-                                         P->d_scratch, P->seg_gs + t, q), "grad_s");
-    };
     if (P->opts.mode == DSBT_MODE_PLAIN) {
         for (int t = 0; t < n; ++t) {
             const dsbt::PhaseArgs pv{1, 0, P->seg_s, t}, pk{1, 0, nullptr, 0};
             enqueue_forward<T, S>(P, state(t), state(t + 1), q, pv, pk);
             enqueue_inverse<T, S>(P, state(t + 1), state(t + 1), q, pv, pk);
         }
-        int cur = 0;   // lam[cur] holds lam_{t+1}
+        int cur = 0;   // buffer cur holds lam_{t+1}
         for (int t = n - 1; t >= 0; --t) {
             const dsbt::PhaseArgs pv{1, 1, P->seg_s, t}, pk{1, 1, nullptr, 0};
-            enqueue_forward<T, S>(P, lam[cur], lam[cur ^ 1], q, pv, pk);
-            enqueue_inverse<T, S>(P, lam[cur ^ 1], lam[cur ^ 1], q, pv, pk);
-            grad(t, cur);
+            enqueue_forward<T, S>(P, lam(cur), lam(cur ^ 1), q, pv, pk);
+            enqueue_inverse<T, S>(P, lam(cur ^ 1), lam(cur ^ 1), q, pv, pk);
+            hip_check(dsbt::launch_grad_s<S>(P->d_fchans, nch, state(t), state(t + 1), lam(cur ^ 1), lam(cur),
+                                             P->d_scratch, P->seg_gs + t, q), "grad_s");
             cur ^= 1;
         }
         return;
     }
-    void* w = lam[2];
+    void* w = lam(n + 1);
     const dsbt::PhaseArgs none{};
     {
         const dsbt::PhaseArgs pk{1, 0, nullptr, 0};
@@ -1030,18 +1036,17 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
     }
     const dsbt::PhaseArgs pk{1, 1, nullptr, 0};
     auto pv = [&](int t) { return dsbt::PhaseArgs{1, 1, P->seg_s, t}; };
-    enqueue_fstage<T, S>(P, lam[0], w, 0, pv(n - 1), none, q);
-    int cur = 0;   // lam[cur] holds lam_{t+1}
+    enqueue_fstage<T, S>(P, lam(n), w, 0, pv(n - 1), none, q);
     for (int t = n - 1; t >= 0; --t) {
         enqueue_mstage<T, S>(P, w, w, false, q, pk);
         enqueue_mstage<T, S>(P, w, w, true, q, pk);
         if (t > 0)
-            enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), q, lam[cur ^ 1]);
+            enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), q, lam(t));
         else
-            enqueue_fstage<T, S>(P, w, lam[cur ^ 1], 1, pv(t), none, q);
-        grad(t, cur);
-        cur ^= 1;
+            enqueue_fstage<T, S>(P, w, lam(0), 1, pv(t), none, q);
     }
+    hip_check(dsbt::launch_grad_s_steps<S>(P->d_fchans, nch, n, state(0), lam(0), (int64_t)P->elems, P->seg_part,
+                                           P->seg_gs, q), "grad_s");
 }
 
 // Checked plans: scan the channels of `data` for NaN and infinities on s and
@@ -1410,18 +1415,21 @@ dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps,
             p->drop_graphs();
             p->free_segment();
             p->seg_states = p->dalloc_raw(sb * (size_t)(nsteps + 1));
-            p->seg_lam = p->dalloc_raw(3 * sb);
+            p->seg_lam = p->dalloc_raw(sb * (size_t)(nsteps + 2));
             p->seg_s = static_cast<float*>(p->dalloc_raw(sizeof(float) * (size_t)nsteps));
             p->seg_gs = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps));
+            p->seg_part = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps * p->ch.size()));
             p->seg_cap = nsteps;
         }
+        auto lam_buf = [&](int t) { return static_cast<unsigned char*>(p->seg_lam) + sb * (size_t)t; };
         hip_check(hipMemcpyAsync(p->seg_states, psi_a, sb, hipMemcpyDeviceToDevice, st), "segment psi_a");
-        hip_check(hipMemcpyAsync(p->seg_lam, lam, sb, hipMemcpyDeviceToDevice, st), "segment lam");
-        // lam_a ends in the second buffer for odd n: its gaps between channels
-        // (never written by the steps) must hold lam's
-        if (nsteps & 1)
-            hip_check(hipMemcpyAsync(static_cast<unsigned char*>(p->seg_lam) + sb, lam, sb, hipMemcpyDeviceToDevice, st),
-                      "segment lam");
+        // lam_{a+n} where the steps start from it (buffer n batched, 0 plain);
+        // the buffer lam_a ends in also gets lam, as its gaps between
+        // channels (never written by the steps) must hold lam's
+        const int first = p->opts.mode == DSBT_MODE_PLAIN ? 0 : nsteps, last = segment_result_buffer(p, nsteps);
+        hip_check(hipMemcpyAsync(lam_buf(first), lam, sb, hipMemcpyDeviceToDevice, st), "segment lam");
+        if (last != first)
+            hip_check(hipMemcpyAsync(lam_buf(last), lam, sb, hipMemcpyDeviceToDevice, st), "segment lam");
         hip_check(hipMemcpyAsync(p->seg_s, s, sizeof(float) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
                   "segment strengths");
         auto enqueue = [&](hipStream_t q) {
@@ -1445,8 +1453,7 @@ dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps,
         } else {
             enqueue(st);
         }
-        const unsigned char* lam_a = static_cast<const unsigned char*>(p->seg_lam) + sb * (size_t)(nsteps & 1);
-        hip_check(hipMemcpyAsync(lam, lam_a, sb, hipMemcpyDeviceToDevice, st), "segment lam_a");
+        hip_check(hipMemcpyAsync(lam, lam_buf(last), sb, hipMemcpyDeviceToDevice, st), "segment lam_a");
         hip_check(hipMemcpyAsync(gs, p->seg_gs, sizeof(double) * (size_t)nsteps, hipMemcpyDeviceToDevice, st),
                   "segment gradients");
         if (p->opts.check_finite) check_finite_data(p, lam, st, "dsbt_adjoint_segment result");

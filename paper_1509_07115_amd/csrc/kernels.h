@@ -199,5 +199,12 @@ template <typename T>
 hipError_t launch_grad_s(const FChan* d_chans, int nch, const void* p0, const void* p1,
                          const void* l0, const void* l1, double* scratch, double* out,
                          hipStream_t s);
+// The same for steps t = 0 .. nsteps - 1 in two launches: step t reads
+// p_t = states + t stride, p_t+1, l_t = lams + t stride, l_t+1 (stride in
+// complex elements) and writes out[t]; scratch holds nsteps nch partials.
+// Each out[t] is bitwise what launch_grad_s gives for the same vectors.
+template <typename T>
+hipError_t launch_grad_s_steps(const FChan* d_chans, int nch, int nsteps, const void* states, const void* lams,
+                               int64_t stride, double* scratch, double* out, hipStream_t s);
 
 }  // namespace dsbt

@@ -192,14 +192,22 @@ template hipError_t launch_scan_nonfinite<double>(const FChan*, int, const void*
 // Reduction for the strength gradient of a step.
 // ---------------------------------------------------------------------------
 
+// Block (c, t): channel c of step t, whose vectors sit t stride elements
+// after p0, p1, l0, l1; the partial goes to part[t nch + c].
 template <typename T>
 __global__ void __launch_bounds__(kBlock) grad_s_partial(const FChan* __restrict__ chans,
                                                          const typename C2<T>::t* p0,
                                                          const typename C2<T>::t* p1,
                                                          const typename C2<T>::t* l0,
                                                          const typename C2<T>::t* l1,
-                                                         double* __restrict__ part) {
+                                                         int64_t stride, double* __restrict__ part) {
     const FChan c = chans[blockIdx.x];
+    const int64_t ts = stride * blockIdx.y;
+    p0 += ts;
+    p1 += ts;
+    l0 += ts;
+    l1 += ts;
+    part += (size_t)blockIdx.y * gridDim.x;
     double acc = 0.0;
     for (int i = threadIdx.x; i < c.N; i += kBlock) {
         const int64_t g = c.off + i;
@@ -217,8 +225,11 @@ __global__ void __launch_bounds__(kBlock) grad_s_partial(const FChan* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// block t: out[t] = the sum of part[t n .. t n + n)
 __global__ void __launch_bounds__(kBlock) sum_partials(const double* __restrict__ part, int n,
                                                        double* __restrict__ out) {
+    part += (size_t)blockIdx.x * n;
+    out += blockIdx.x;
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += kBlock) acc += part[i];
     __shared__ double red[kBlock];
@@ -260,8 +271,21 @@ hipError_t launch_grad_s(const FChan* d_chans, int nch, const void* p0, const vo
                          const void* l1, double* scratch, double* out, hipStream_t s) {
     using V = typename C2<T>::t;
     hipLaunchKernelGGL(grad_s_partial<T>, dim3(nch), dim3(kBlock), 0, s, d_chans, (const V*)p0, (const V*)p1,
-                       (const V*)l0, (const V*)l1, scratch);
+                       (const V*)l0, (const V*)l1, (int64_t)0, scratch);
     hipLaunchKernelGGL(sum_partials, dim3(1), dim3(kBlock), 0, s, scratch, nch, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grad_s_steps(const FChan* d_chans, int nch, int nsteps, const void* states, const void* lams,
+                               int64_t stride, double* scratch, double* out, hipStream_t s) {
+    using V = typename C2<T>::t;
+    if (nch <= 0 || nsteps <= 0) return hipSuccess;
+    const V* p = static_cast<const V*>(states);
+    const V* l = static_cast<const V*>(lams);
+    hipLaunchKernelGGL(grad_s_partial<T>, dim3(nch, nsteps), dim3(kBlock), 0, s, d_chans, p, p + stride, l,
+                       l + stride, stride, scratch);
+    hipLaunchKernelGGL(sum_partials, dim3(nsteps), dim3(kBlock), 0, s, scratch, nch, out);
     return hipGetLastError();
 }
 
@@ -294,5 +318,9 @@ template hipError_t launch_grad_s<float>(const FChan*, int, const void*, const v
                                          double*, double*, hipStream_t);
 template hipError_t launch_grad_s<double>(const FChan*, int, const void*, const void*, const void*, const void*,
                                           double*, double*, hipStream_t);
+template hipError_t launch_grad_s_steps<float>(const FChan*, int, int, const void*, const void*, int64_t, double*,
+                                               double*, hipStream_t);
+template hipError_t launch_grad_s_steps<double>(const FChan*, int, int, const void*, const void*, int64_t, double*,
+                                                double*, hipStream_t);
 
 }  // namespace dsbt
