@@ -32,8 +32,8 @@ PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP 
 # applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h",
                               "paper_1509_07115_amd/csrc/capi.cpp"],
-                  "sha256": "9575d7a6a0f103e877dc6508bdea78a0a2e1a81b33b593b5815c89e1f8523321",
-                  "fetch_bytes": 147617488, "write_bytes": 67482528}
+                  "sha256": "6996b83ac5e4c2ae11cea79449c48810d38219966057196a9fa941aac1c7e18e",
+                  "fetch_bytes": 147489248, "write_bytes": 67482496}
 
 
 def sources_sha256(paths):
