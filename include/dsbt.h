@@ -220,9 +220,11 @@ dsbt_status dsbt_step_grad_s(dsbt_plan p, const void* psi_t, const void* psi_t1,
  * t = a+n-1 .. a forms lam_t and gs[t-a] = dL/ds_t exactly as
  * dsbt_step_grad_s does, and leaves lam_a in lam (psi_a is not written).
  * gs: device FP64 array of n values, written.  All work runs on plan-owned
- * buffers (2n + 3 states and n x nch doubles, grown through the plan's
+ * buffers (2n + 4 states and n x nch doubles, grown through the plan's
  * allocator to the largest n seen; a call that grows them synchronises
  * `stream`): the inputs are copied in and the results out on `stream`.
+ * Batched plans run the recompute and the adjoint steps side by side on
+ * `stream` and a second stream of the plan, joined before the gradients.
  * flags: 0, or DSBT_STEP_GRAPH: the segment's launches (n steps, n adjoint
  * steps, the gradient reductions) are captured
  * once in a hipGraph on those buffers and replayed, so every later call with

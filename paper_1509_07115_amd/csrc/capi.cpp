@@ -230,6 +230,10 @@ struct dsbt_plan_s {
     double* seg_gs = nullptr;
     double* seg_part = nullptr;   // per-channel partials of the segment's gradients
     int seg_cap = 0;
+    // a second stream (default priority) and two events: a batched segment
+    // runs its recompute and its adjoint chain side by side
+    hipStream_t seg_side = nullptr;
+    hipEvent_t seg_fork = nullptr, seg_join = nullptr;
     hipGraphExec_t seg_exec = nullptr;
     hipGraph_t seg_graph = nullptr;
     int seg_graph_n = 0;
@@ -290,6 +294,11 @@ struct dsbt_plan_s {
     void release() {
         drop_graphs();
         free_segment();
+        if (seg_fork) (void)hipEventDestroy(seg_fork);
+        if (seg_join) (void)hipEventDestroy(seg_join);
+        if (seg_side) (void)hipStreamDestroy(seg_side);
+        seg_fork = seg_join = nullptr;
+        seg_side = nullptr;
         for (void* p : allocs) dfree(p);
         allocs.clear();
         if (h_flag) (void)hipHostFree(h_flag);
@@ -990,10 +999,12 @@ inline int segment_result_buffer(const dsbt_plan_s* P, int n) {
 // One checkpoint segment of the adjoint method on the plan's segment buffers
 // (dsbt_adjoint_segment): states 1..n from state 0, then the n adjoint steps
 // lam_{t+1} -> lam_t and the strength gradients.  Batched plans carry each
-// pass in a work buffer (adjoint buffer n + 1) through the fused inverse +
-// forward stage, which also stores the state between two steps: psi_t into
-// state t, lam_t into adjoint buffer t (lam_n is given there).  All n
-// gradients then take two launches; the plain form alternates lam between
+// pass in a work buffer (adjoint buffers n + 1 and n + 2) through the fused
+// inverse + forward stage, which also stores the state between two steps:
+// psi_t into state t, lam_t into adjoint buffer t (lam_n is given there).
+// The adjoint chain needs no psi, so it runs on the plan's second stream
+// beside the recompute (its launches are small); all n gradients then take
+// two launches once both are done.  The plain form alternates lam between
 // adjoint buffers 0 and 1 and reduces each step's gradient in turn.  Both
 // give the results of separate step and gradient calls bitwise.
 template <typename T, typename S>
@@ -1019,9 +1030,12 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
         }
         return;
     }
-    void* w = lam(n + 1);
     const dsbt::PhaseArgs none{};
+    hipStream_t a = P->seg_side;
+    hip_check(hipEventRecord(P->seg_fork, q), "segment fork");
+    hip_check(hipStreamWaitEvent(a, P->seg_fork, 0), "segment fork");
     {
+        void* w = lam(n + 1);
         const dsbt::PhaseArgs pk{1, 0, nullptr, 0};
         auto pv = [&](int t) { return dsbt::PhaseArgs{1, 0, P->seg_s, t}; };
         enqueue_fstage<T, S>(P, state(0), w, 0, pv(0), none, q);
@@ -1034,17 +1048,22 @@ void enqueue_segment(dsbt_plan_s* P, int n, hipStream_t q) {
                 enqueue_fstage<T, S>(P, w, state(n), 1, pv(t), none, q);
         }
     }
-    const dsbt::PhaseArgs pk{1, 1, nullptr, 0};
-    auto pv = [&](int t) { return dsbt::PhaseArgs{1, 1, P->seg_s, t}; };
-    enqueue_fstage<T, S>(P, lam(n), w, 0, pv(n - 1), none, q);
-    for (int t = n - 1; t >= 0; --t) {
-        enqueue_mstage<T, S>(P, w, w, false, q, pk);
-        enqueue_mstage<T, S>(P, w, w, true, q, pk);
-        if (t > 0)
-            enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), q, lam(t));
-        else
-            enqueue_fstage<T, S>(P, w, lam(0), 1, pv(t), none, q);
+    {
+        void* w = lam(n + 2);
+        const dsbt::PhaseArgs pk{1, 1, nullptr, 0};
+        auto pv = [&](int t) { return dsbt::PhaseArgs{1, 1, P->seg_s, t}; };
+        enqueue_fstage<T, S>(P, lam(n), w, 0, pv(n - 1), none, a);
+        for (int t = n - 1; t >= 0; --t) {
+            enqueue_mstage<T, S>(P, w, w, false, a, pk);
+            enqueue_mstage<T, S>(P, w, w, true, a, pk);
+            if (t > 0)
+                enqueue_fstage<T, S>(P, w, w, 2, pv(t), pv(t - 1), a, lam(t));
+            else
+                enqueue_fstage<T, S>(P, w, lam(0), 1, pv(t), none, a);
+        }
     }
+    hip_check(hipEventRecord(P->seg_join, a), "segment join");
+    hip_check(hipStreamWaitEvent(q, P->seg_join, 0), "segment join");
     hip_check(dsbt::launch_grad_s_steps<S>(P->d_fchans, nch, n, state(0), lam(0), (int64_t)P->elems, P->seg_part,
                                            P->seg_gs, q), "grad_s");
 }
@@ -1415,11 +1434,16 @@ dsbt_status dsbt_adjoint_segment(dsbt_plan p, const void* psi_a, int32_t nsteps,
             p->drop_graphs();
             p->free_segment();
             p->seg_states = p->dalloc_raw(sb * (size_t)(nsteps + 1));
-            p->seg_lam = p->dalloc_raw(sb * (size_t)(nsteps + 2));
+            p->seg_lam = p->dalloc_raw(sb * (size_t)(nsteps + 3));
             p->seg_s = static_cast<float*>(p->dalloc_raw(sizeof(float) * (size_t)nsteps));
             p->seg_gs = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps));
             p->seg_part = static_cast<double*>(p->dalloc_raw(sizeof(double) * (size_t)nsteps * p->ch.size()));
             p->seg_cap = nsteps;
+        }
+        if (p->opts.mode != DSBT_MODE_PLAIN && !p->seg_side) {
+            hip_check(hipStreamCreateWithFlags(&p->seg_side, hipStreamNonBlocking), "segment stream");
+            hip_check(hipEventCreateWithFlags(&p->seg_fork, hipEventDisableTiming), "segment event");
+            hip_check(hipEventCreateWithFlags(&p->seg_join, hipEventDisableTiming), "segment event");
         }
         auto lam_buf = [&](int t) { return static_cast<unsigned char*>(p->seg_lam) + sb * (size_t)t; };
         hip_check(hipMemcpyAsync(p->seg_states, psi_a, sb, hipMemcpyDeviceToDevice, st), "segment psi_a");
