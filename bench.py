@@ -32,8 +32,8 @@ PROFILE_EVERY = 10   # steps of the timed region whose stage launches carry HIP 
 # applies and the roofline reports traffic as null.
 MOMENT_TRAFFIC = {"sources": ["paper_1509_07115_amd/csrc/mstage_chain.hip", "paper_1509_07115_amd/csrc/kernels.h",
                               "paper_1509_07115_amd/csrc/capi.cpp"],
-                  "sha256": "6996b83ac5e4c2ae11cea79449c48810d38219966057196a9fa941aac1c7e18e",
-                  "fetch_bytes": 147489248, "write_bytes": 67482496}
+                  "sha256": "1c669beaf6aa8ff7bbb6fe284e792422aecaf6657f1f03e6c87fd52ea51efca4",
+                  "fetch_bytes": 147867056, "write_bytes": 67482496}
 
 
 def sources_sha256(paths):
