@@ -239,6 +239,12 @@ def main():
     ap.add_argument("--angular-profile", action="store_true",
                     help="only time the angular transform Y = P Phi (N_r = 4096, N_theta = 64, N_phi = 17, "
                          "complex64) forward and inverse, and B Y psi with the radial transform")
+    ap.add_argument("--uneven-profile", action="store_true",
+                    help="only run --steps forward + inverse pairs of the uneven batch (512 transforms, N 512..8192, "
+                         "l 0..127) after --warmup untimed pairs, for a kernel trace")
+    ap.add_argument("--adjoint-profile", action="store_true",
+                    help="only run --steps loss-and-gradient passes through 200 split steps (checkpoints every 20, "
+                         "graph-replayed segments) after --warmup untimed ones, for a kernel trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU per process; --gpus must be 1", file=sys.stderr)
@@ -255,6 +261,38 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 4}))
+        return
+
+    if args.uneven_profile:
+        w = workloads.uneven()
+        plan = Plan(w.channels)
+        x = torch.from_numpy(w.psi).to(torch.complex64).cuda()
+        b, y = plan.empty(), plan.empty()
+        step = lambda: (plan.forward(x, b), plan.inverse(b, y))
+        for _ in range(max(args.warmup, 1)):
+            step()
+        ms = _timed(step, args.steps)
+        print(json.dumps({"workload": w.name, "ms_per_fwd_inv": ms, "pairs": args.steps,
+                          "points_per_s": w.points / (ms * 1e-3)}))
+        return
+
+    if args.adjoint_profile:
+        from paper_1509_07115_amd.autograd import propagate
+        w = workloads.adjoint()
+        plan = Plan(w.channels)
+        plan.set_potential(w.extra["V"], w.extra["dt"])
+        phi = torch.from_numpy(w.extra["phi"]).to(torch.complex64).cuda()
+        s = torch.from_numpy(w.extra["s"]).to(torch.float32).cuda()
+
+        def grad_pass():
+            p0 = torch.from_numpy(w.psi).to(torch.complex64).cuda().requires_grad_(True)
+            st = s.clone().requires_grad_(True)
+            z = torch.vdot(phi, propagate(plan, p0, st, checkpoint_every=20, graph=True))
+            ((z * z.conj()).real).backward()
+        for _ in range(max(args.warmup, 1)):
+            grad_pass()
+        ms = _timed(grad_pass, args.steps)
+        print(json.dumps({"workload": w.name, "ms_per_loss_and_gradient": ms, "passes": args.steps}))
         return
 
     if args.split_step_profile:
